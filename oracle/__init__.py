@@ -1,0 +1,322 @@
+"""CPU oracle for the LLR energy-restricted sweep (test infrastructure only).
+
+This package wraps ``llr_oracle.c``, a plain FP64 C implementation of the
+method of arXiv:1509.08391 (Sec. 2.2 restricted expectation values and the
+Robbins-Monro iteration, Algorithm 1, Sec. 2.5 replica exchange, Sec. 3.1
+compact U(1) model, eqs. (kk3a), (l19)-(l20) reconstruction).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the GPU library.
+
+Conventions (identical on both sides, written independently):
+  * canonical link layout: ``theta[chain, mu, s]``, s = x0 + L x1 + L^2 x2 + ...
+  * colour c = 2 mu + p (p = site parity), heatbath colours 0..2d-1 then
+    overrelaxation colours 0..2d-1 per sweep
+  * Philox4x32-10 key = (seed lo, seed hi); counter = (h or link index,
+    attempt|colour<<8|kind<<12|lattice<<16, sweep, interval)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "llr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP = 0, 1, 2, 3, 4
+MODE_RESTRICTED, MODE_APPROACH, MODE_FREE = 0, 1, 2
+N_PARAMS = 4417
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _p(t):
+    return C.POINTER(t)
+
+
+class RunParams(C.Structure):
+    _fields_ = [("d", C.c_int), ("L", C.c_int), ("n", C.c_int),
+                ("n_th", C.c_int), ("n_a", C.c_int), ("n_rm", C.c_int),
+                ("recompute_every", C.c_int), ("approach_cap", C.c_int),
+                ("replica_exchange", C.c_int), ("f32", C.c_int), ("lattice_id", C.c_int),
+                ("hot_start", C.c_int), ("seed", C.c_uint64),
+                ("dE", C.c_double), ("w", C.c_double), ("eps", C.c_double)]
+
+
+class RunOut(C.Structure):
+    _fields_ = [("a", _p(C.c_double)), ("a_hist", _p(C.c_double)), ("theta", _p(C.c_double)),
+                ("E", _p(C.c_double)), ("conf", _p(C.c_int)), ("conv_iter", _p(C.c_int)),
+                ("conv_sweeps", _p(C.c_longlong)), ("approach_sweeps", _p(C.c_longlong)),
+                ("bits", _p(C.c_uint16)), ("sumE_hist", _p(C.c_double)),
+                ("re_acc", _p(C.c_longlong))]
+
+
+def _declare(L):
+    d, i, u32, u64, l = C.c_double, C.c_int, C.c_uint32, C.c_uint64, C.c_long
+    L.or_philox_batch.argtypes = [l, _p(u32), _p(u32), _p(u32)]
+    L.or_uniforms.argtypes = [l, _p(u32), i, _p(d), _p(d)]
+    L.or_neighbour.argtypes = [i, i, l, i, i]
+    L.or_neighbour.restype = l
+    L.or_energy.argtypes = [i, i, _p(d)]
+    L.or_energy.restype = d
+    L.or_local_field.argtypes = [i, i, _p(d), i, l, _p(d), _p(d)]
+    L.or_vonmises_batch.argtypes = [l, d, u64, u32, u32, u32, i, _p(d), _p(i), _p(d)]
+    L.or_hot_start.argtypes = [i, i, i, u64, i, i, _p(d)]
+    L.or_class_pass.argtypes = [i, i, _p(d), i, i, i, d, d, d, _p(d), u64, i, i, u32, u32, i,
+                                _p(d), _p(d)]
+    L.or_class_pass.restype = i
+    L.or_sweeps.argtypes = [i, i, i, _p(d), _p(d), _p(d), _p(d), _p(i), _p(d), i, u32, i, i, i,
+                            u64, i, i, _p(i)]
+    L.or_llr_run.argtypes = [C.POINTER(RunParams), _p(d), C.POINTER(RunOut)]
+    L.or_llr_run.restype = i
+    L.or_rm_step.argtypes = [d, d, d, i, d]
+    L.or_rm_step.restype = d
+    L.or_ln_rho.argtypes = [_p(d), i, d, _p(d)]
+    L.or_reconstruct.argtypes = [_p(d), _p(d), i, d, d, _p(d), i, _p(d), _p(d), _p(d)]
+    L.or_beta_c.argtypes = [_p(d), _p(d), i, d, d, d, d, d, d, _p(d), _p(d)]
+    L.or_mlp_nparams.restype = i
+    L.or_mlp_init.argtypes = [u64, _p(d)]
+    L.or_mlp_forward.argtypes = [_p(d), _p(d), _p(d), i, _p(d), _p(d), _p(d)]
+    L.or_mlp_loss_grad.argtypes = [_p(d), _p(d), _p(d), _p(d), i, _p(d)]
+    L.or_mlp_loss_grad.restype = d
+    L.or_mlp_adam.argtypes = [_p(d), _p(d), _p(d), _p(d), i, d, d, d, d]
+    L.or_mlp_train.argtypes = [_p(d), _p(d), _p(d), _p(d), i, i, d, _p(d)]
+    L.or_num_threads.restype = i
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _key(seed):
+    return np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+
+
+def ctr1(attempt_pair=0, colour=0, kind=0, lattice_id=0):
+    return (attempt_pair & 0xFF) | ((colour & 0xF) << 8) | ((kind & 0xF) << 12) | ((lattice_id & 0xFF) << 16)
+
+
+# ---------------------------------------------------------------- wrappers
+def philox(ctr, seed):
+    """Philox4x32-10 of an (n, 4) uint32 counter array with key from seed."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    key = _key(seed)
+    lib().or_philox_batch(ctr.shape[0], _ptr(ctr, C.c_uint32), _ptr(key, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def uniforms(words, u24=False):
+    w = np.ascontiguousarray(words, dtype=np.uint32).ravel()
+    u = np.empty(w.size)
+    v = np.empty(w.size)
+    lib().or_uniforms(w.size, _ptr(w, C.c_uint32), int(u24), _ptr(u, C.c_double), _ptr(v, C.c_double))
+    return u, v
+
+
+def neighbour(d, L, s, mu, step):
+    return lib().or_neighbour(d, L, s, mu, step)
+
+
+def energy(d, L, theta):
+    th = _f64(theta)
+    return lib().or_energy(d, L, _ptr(th, C.c_double))
+
+
+def local_field(d, L, theta, mu, s):
+    th = _f64(theta)
+    c, sn = C.c_double(), C.c_double()
+    lib().or_local_field(d, L, _ptr(th, C.c_double), mu, s, C.byref(c), C.byref(sn))
+    return c.value, sn.value
+
+
+def vonmises(n, kappa, seed, c1=0, c2=0, c3=0, u24=False):
+    """n draws X ~ vM(kappa) with counters (i, c1, c2, c3); returns X, attempts, margin."""
+    X = np.empty(n)
+    att = np.empty(n, dtype=np.int32)
+    mg = np.empty(n)
+    lib().or_vonmises_batch(n, kappa, seed, c1, c2, c3, int(u24), _ptr(X, C.c_double),
+                            _ptr(att, C.c_int), _ptr(mg, C.c_double))
+    return X, att, mg
+
+
+def hot_start(d, L, n_chains, seed, lattice_id=0, f32=False):
+    V = L ** d
+    th = np.empty((n_chains, d, V))
+    lib().or_hot_start(d, L, n_chains, seed, lattice_id, int(f32), _ptr(th, C.c_double))
+    return th
+
+
+def class_pass(d, L, theta, hb, colour, mode, a, lo, hi, E, seed, kind=KIND_SWEEP, lattice_id=0,
+               sweep=0, interval=0, f32=False, want_margin=False):
+    """One class pass on one chain (theta modified in place).  Returns (accept, E, dE, margin)."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    e = C.c_double(E)
+    de = C.c_double(0.0)
+    V = L ** d
+    mg = np.empty(V // 2) if want_margin else None
+    acc = lib().or_class_pass(d, L, _ptr(theta, C.c_double), int(hb), colour, mode, a, lo, hi,
+                              C.byref(e), seed, kind, lattice_id, sweep, interval, int(f32),
+                              _ptr(mg, C.c_double), C.byref(de))
+    return acc, e.value, de.value, mg
+
+
+def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_RESTRICTED,
+           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False):
+    """n_sweeps sweeps of every chain of theta (n_chains, d, V), in place.  Returns bits."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    nch = theta.shape[0]
+    a, lo, hi = _f64(a), _f64(lo), _f64(hi)
+    itv = np.ascontiguousarray(interval, dtype=np.int32)
+    Earr = np.ascontiguousarray(E, dtype=np.float64).copy()
+    bits = np.zeros((n_sweeps, nch), dtype=np.int32)
+    lib().or_sweeps(d, L, nch, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
+                    _ptr(hi, C.c_double), _ptr(itv, C.c_int), _ptr(Earr, C.c_double), n_sweeps,
+                    sweep0, mode, kind, int(do_or), seed, lattice_id, int(f32), _ptr(bits, C.c_int))
+    return Earr, bits
+
+
+def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=10,
+            approach_cap=100000, replica_exchange=False, f32=False, lattice_id=0, eps=1e-4,
+            theta=None, record_bits=False):
+    """Algorithm 1 on every interval of one lattice.  Returns a dict of results."""
+    E_low = _f64(E_low)
+    n = E_low.size
+    V = L ** d
+    if w is None:
+        w = 2.0 * dE if replica_exchange else dE
+    p = RunParams(d, L, n, n_th, n_a, n_rm, recompute_every, approach_cap, int(replica_exchange),
+                  int(f32), lattice_id, int(theta is None), seed, dE, w, eps)
+    a = _f64(a0).copy() if np.ndim(a0) else np.full(n, float(a0))
+    th = np.empty((n, d, V)) if theta is None else _f64(theta).copy()
+    a_hist = np.zeros((n_rm + 1, n))
+    E = np.zeros(n)
+    conf = np.zeros(n, dtype=np.int32)
+    conv = np.zeros(n, dtype=np.int32)
+    convs = np.zeros(n, dtype=np.int64)
+    ap = np.zeros(1, dtype=np.int64)
+    nb = (approach_cap + recompute_every + n_rm * (n_th + n_a)) if record_bits else 0
+    bits = np.zeros((nb, n), dtype=np.uint16) if record_bits else None
+    sumE = np.zeros((n_rm, n))
+    re = np.zeros(2, dtype=np.int64)
+    out = RunOut(_ptr(a, C.c_double), _ptr(a_hist, C.c_double), _ptr(th, C.c_double),
+                 _ptr(E, C.c_double), _ptr(conf, C.c_int), _ptr(conv, C.c_int),
+                 _ptr(convs, C.c_longlong), _ptr(ap, C.c_longlong),
+                 _ptr(bits, C.c_uint16) if record_bits else None, _ptr(sumE, C.c_double),
+                 _ptr(re, C.c_longlong))
+    rc = lib().or_llr_run(C.byref(p), _ptr(E_low, C.c_double), C.byref(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle llr_run failed with status {rc}")
+    res = dict(a=a, a_hist=a_hist, theta=th, E=E, conf=conf, conv_iter=conv, conv_sweeps=convs,
+               approach_sweeps=int(ap[0]), sumE_hist=sumE, re=re, w=w)
+    if record_bits:
+        res["bits"] = bits[: int(ap[0]) + n_rm * (n_th + n_a)]
+    return res
+
+
+def rm_step(a, mean, centre, n, w):
+    """One Robbins-Monro update of eq. (kk21) (Algorithm 1 sign)."""
+    return lib().or_rm_step(float(a), float(mean), float(centre), int(n), float(w))
+
+
+def ln_rho(a, s):
+    a = _f64(a)
+    out = np.empty_like(a)
+    lib().or_ln_rho(_ptr(a, C.c_double), a.size, s, _ptr(out, C.c_double))
+    return out
+
+
+def reconstruct(centres, a, s, six_v, beta):
+    c, a, b = _f64(centres), _f64(a), _f64(beta)
+    lr = np.empty(a.size)
+    u = np.empty(b.size)
+    cv = np.empty(b.size)
+    lib().or_reconstruct(_ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, six_v,
+                         _ptr(b, C.c_double), b.size, _ptr(lr, C.c_double), _ptr(u, C.c_double),
+                         _ptr(cv, C.c_double))
+    return lr, u, cv
+
+
+def beta_c(centres, a, s, six_v, blo, bhi, h=1e-5, tol=1e-9):
+    c, a = _f64(centres), _f64(a)
+    bc, pk = C.c_double(), C.c_double()
+    lib().or_beta_c(_ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, six_v, blo, bhi, h, tol,
+                    C.byref(bc), C.byref(pk))
+    return bc.value, pk.value
+
+
+def mlp_init(seed):
+    w = np.empty(N_PARAMS)
+    lib().or_mlp_init(seed, _ptr(w, C.c_double))
+    return w
+
+
+def mlp_forward(w, u, invL, want_hidden=False):
+    w, u, invL = _f64(w), _f64(u), _f64(invL)
+    n = u.size
+    a = np.empty(n)
+    h1 = np.empty((n, 64)) if want_hidden else None
+    h2 = np.empty((n, 64)) if want_hidden else None
+    lib().or_mlp_forward(_ptr(w, C.c_double), _ptr(u, C.c_double), _ptr(invL, C.c_double), n,
+                         _ptr(a, C.c_double), _ptr(h1, C.c_double), _ptr(h2, C.c_double))
+    return (a, h1, h2) if want_hidden else a
+
+
+def mlp_loss_grad(w, u, invL, a):
+    w, u, invL, a = _f64(w), _f64(u), _f64(invL), _f64(a)
+    g = np.empty(N_PARAMS)
+    loss = lib().or_mlp_loss_grad(_ptr(w, C.c_double), _ptr(u, C.c_double), _ptr(invL, C.c_double),
+                                  _ptr(a, C.c_double), u.size, _ptr(g, C.c_double))
+    return loss, g
+
+
+def mlp_adam(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    for x in (w, m, v):
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+    g = _f64(g)
+    lib().or_mlp_adam(_ptr(w, C.c_double), _ptr(m, C.c_double), _ptr(v, C.c_double),
+                      _ptr(g, C.c_double), t, lr, b1, b2, eps)
+
+
+def mlp_train(w, u, invL, a, epochs, lr):
+    w = _f64(w).copy()
+    u, invL, a = _f64(u), _f64(invL), _f64(a)
+    hist = np.empty(epochs)
+    lib().or_mlp_train(_ptr(w, C.c_double), _ptr(u, C.c_double), _ptr(invL, C.c_double),
+                       _ptr(a, C.c_double), u.size, epochs, lr, _ptr(hist, C.c_double))
+    return w, hist
+
+
+def num_threads():
+    return lib().or_num_threads()
