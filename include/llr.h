@@ -1,0 +1,225 @@
+/*
+ * llr.h -- C ABI of the MI355X (gfx950) LLR library: energy-restricted
+ * Monte-Carlo for 4D compact U(1) lattice gauge theory and the Robbins-Monro
+ * determination of the density-of-states slopes a_k (Langfeld, Lucini,
+ * Pellegrini, Rago, arXiv:1509.08391).
+ *
+ * What the calls compute, with the passage that defines it:
+ *   - the model: links theta_mu(x) in [-pi, pi), action without the coupling
+ *     E = sum_{x, mu<nu} cos theta_{mu nu}(x) (Sec. 3.1);
+ *   - the interval set E_k = E_min + k dE and the closed restriction
+ *     E_k <= E <= E_k + dE (Sec. 2.2, interval indicator; Algorithm 1);
+ *   - the restricted, reweighted measure exp(+a E) 1[E in I_k] sampled by
+ *     colour-class heatbath and overrelaxation moves (eqs. (kk7)-(kk9)); the
+ *     sign convention makes a_k = -d ln rho/dE ~ beta > 0;
+ *   - the Robbins-Monro update a <- a - 12 (<E> - c_k)/((n+1) w^2)
+ *     (eq. (kk21), Algorithm 1) and its stopping rule |a^(n+1)-a^(n)| < eps;
+ *   - replica exchange between neighbouring overlapping intervals (Sec. 2.5);
+ *   - ln rho at the interval centres by the trapezium rule (eq. (kk3a)) and
+ *     <u>(beta), C_V(beta) by the midpoint sums (eqs. (l19)-(l20), Sec. 3.4);
+ *   - a warm start a(u, 1/L) for the Robbins-Monro iteration from a small
+ *     network (the paper's initial values a_i-bar "inverting <E(beta)>",
+ *     Sec. 2.4, here learned from converged a_k).
+ *
+ * Conventions shared by every call:
+ *   - Units: E in plaquette-sum units; u = E/(6V) with V = L^4.
+ *   - Canonical link layout (import/export): [chain][mu][s], with
+ *     s = x0 + L x1 + L^2 x2 + L^3 x3, in the precision of the context.
+ *   - Colour c = 2 mu + p, p = parity of the site; a sweep is heatbath on
+ *     colours 0..7, then overrelaxation on colours 0..7.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed lo,
+ *     seed hi), counter = (w0, w1, w2, w3) with
+ *       w0 = half index h = s >> 1 (sweeps), mu*V + s (hot start), k (pair),
+ *       w1 = attempt pair | colour << 8 | kind << 12 | lattice id << 16,
+ *            kind 0 sweep, 1 hot start, 2 approach, 3 replica exchange, 4 MLP init,
+ *       w2 = sweep index, w3 = interval index within the lattice.
+ *   - Pointers: "host" arrays are read or written synchronously by the call;
+ *     "device" pointers are HIP device memory owned by the caller (e.g. torch
+ *     tensors); the library never frees caller memory.  Work is enqueued on
+ *     the stream given at creation and every call synchronises that stream
+ *     before it returns unless stated otherwise.
+ *   - Errors: every call returns an llr_status; < 0 is an error and
+ *     llr_last_error() holds a message (thread-local).  No exception crosses
+ *     the ABI.  A context is used by one host thread at a time.
+ */
+#ifndef LLR_H
+#define LLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct llr_ctx llr_ctx;
+typedef int llr_status;
+
+enum {
+    LLR_OK = 0,
+    LLR_WARN_NOT_CONVERGED = 1, /* some interval never met |da| < eps */
+    LLR_EINVAL = -1,            /* invalid argument */
+    LLR_ENOMEM = -2,            /* device allocation failed */
+    LLR_EDEVICE = -3,           /* HIP runtime error */
+    LLR_ESTATE = -4,            /* call out of order (e.g. state not bound) */
+    LLR_EAPPROACH = -5,         /* approach cap reached before every chain entered its interval */
+    LLR_ENUMERIC = -6           /* non-finite value detected */
+};
+
+enum { LLR_FP64 = 0, LLR_FP32 = 1 }; /* precision of link angles and local arithmetic;
+                                        energies, interval tests, a_k, RM always FP64 */
+enum { LLR_MODE_RESTRICTED = 0, LLR_MODE_APPROACH = 1, LLR_MODE_FREE = 2 };
+
+typedef struct {
+    int n_th;             /* thermalisation sweeps per RM iteration (Algorithm 1 N_TH) */
+    int n_a;              /* measured sweeps per RM iteration (N_A; N_SW = N_TH + N_A) */
+    int n_rm;             /* Robbins-Monro iterations (N_RM) */
+    uint64_t seed;        /* Philox key */
+    int replica_exchange; /* 0/1: exchange between neighbouring intervals after every sweep */
+    double overlap;       /* with replica exchange the restriction width is w = (1 + overlap) dE */
+    int recompute_every;  /* K: full FP64 recompute of E after every K-th sweep and the last */
+    double eps;           /* stopping threshold on |a^(n+1) - a^(n)| (1e-4) */
+    int approach_cap;     /* maximum approach sweeps (multiple of K) */
+} llr_params;
+
+/* --- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `hip_device`; `hip_stream` is a hipStream_t
+ * (NULL = default stream), e.g. torch.cuda.current_stream().cuda_stream.
+ * precision is LLR_FP64 or LLR_FP32.  Owns only small scratch buffers. */
+llr_status llr_create(llr_ctx **out, int hip_device, void *hip_stream, int precision);
+void llr_destroy(llr_ctx *ctx);
+const char *llr_last_error(void);
+llr_status llr_set_params(llr_ctx *ctx, const llr_params *p);
+
+/* Add a lattice of size L (even, 2 <= L <= 32) with n_intervals chains, one
+ * per interval; E_low (host, n_intervals) are the ascending lower edges E_k,
+ * dE > 0 the spacing (Algorithm 1: E_k = E_min + k dE).  Interval k has centre
+ * c_k = E_k + dE/2 and restriction [c_k - w/2, c_k + w/2] with w = dE, or
+ * (1 + overlap) dE under replica exchange.  lattice_id receives 0, 1, ...
+ * At most 8 lattices.  Must precede llr_bind_state. */
+llr_status llr_add_lattice(llr_ctx *ctx, int L, int n_intervals, const double *E_low, double dE,
+                           int *lattice_id);
+
+/* Bytes of device memory the caller must bind: 2 x 4V x n_intervals angles of
+ * the context precision per lattice (two planes per colour: proposals are
+ * written to the non-current plane). */
+llr_status llr_state_bytes(llr_ctx *ctx, size_t *bytes);
+/* Bind caller-owned device memory of exactly llr_state_bytes bytes, aligned
+ * to 256 bytes.  The library reads and writes it until destroy/rebind. */
+llr_status llr_bind_state(llr_ctx *ctx, void *dev_state, size_t bytes);
+
+/* Initial a_k^(0) per interval (host, n_intervals); default 1.0. */
+llr_status llr_set_a(llr_ctx *ctx, int lattice_id, const double *a);
+
+/* Uniform hot start of every chain (kind 1 counters, w3 = chain index), then a
+ * full FP64 energy computation. */
+llr_status llr_hot_start(llr_ctx *ctx);
+/* Import/export one lattice's angles in canonical layout (device pointer,
+ * n_intervals x 4 x V values of the context precision).  Import resets the
+ * chain <-> interval assignment to the identity and recomputes E. */
+llr_status llr_import_state(llr_ctx *ctx, int lattice_id, const void *dev_canonical);
+llr_status llr_export_state(llr_ctx *ctx, int lattice_id, void *dev_canonical);
+
+/* --- Algorithm 1 -------------------------------------------------------- */
+
+/* Approach phase: heatbath-only sweeps that accept a class move iff it does
+ * not move E away from the interval, coupling adapted per pass; in blocks of
+ * K sweeps and a full recompute until every chain is inside.  *sweeps
+ * (host, n_lattices) receives the approach sweeps per lattice.  LLR_EAPPROACH
+ * if the cap is reached. */
+llr_status llr_approach(llr_ctx *ctx, long long *sweeps);
+/* The same in steps: llr_approach_begin initialises the approach couplings
+ * from a_k^(0), recomputes E and marks lattices already inside;
+ * llr_approach_continue performs up to max_sweeps further approach sweeps
+ * (whole blocks of K) and reports in *all_done whether every chain is inside;
+ * sweeps (host, n_lattices) receives the approach sweeps so far. */
+llr_status llr_approach_begin(llr_ctx *ctx);
+llr_status llr_approach_continue(llr_ctx *ctx, long long max_sweeps, long long *sweeps, int *all_done);
+/* Robbins-Monro iterations of Algorithm 1 on every interval of every lattice
+ * (chains batched in one launch per pass).  Requires state inside the
+ * intervals (after llr_approach).  Returns LLR_WARN_NOT_CONVERGED if some
+ * interval never met the stopping rule. */
+llr_status llr_run(llr_ctx *ctx);
+/* The same in steps: llr_rm_begin resets the iteration counter, the sweep
+ * counter and the history; llr_rm_step performs the next `iterations`
+ * Robbins-Monro iterations (at most n_rm in total since llr_rm_begin) and
+ * returns LLR_WARN_NOT_CONVERGED after the last one if some interval never
+ * met the stopping rule.  llr_run = llr_rm_begin + llr_rm_step(n_rm). */
+llr_status llr_rm_begin(llr_ctx *ctx);
+llr_status llr_rm_step(llr_ctx *ctx, int iterations);
+/* Final a_k, first RM iteration n with |a^(n+1)-a^(n)| < eps (-1 if never)
+ * and sweeps up to it (approach + (n+1)(N_TH+N_A)); host arrays, n_intervals. */
+llr_status llr_get_a(llr_ctx *ctx, int lattice_id, double *a, int *conv_iter, long long *conv_sweeps);
+/* a_k^(n) for n = 0..n_rm (host, (n_rm + 1) x n_intervals) of the last run. */
+llr_status llr_get_history(llr_ctx *ctx, int lattice_id, double *a_hist);
+/* Current energy per chain and chain in each interval (host, n_intervals each). */
+llr_status llr_get_energy(llr_ctx *ctx, int lattice_id, double *E, int *conf);
+/* ln rho at the centres (trapezium recursion, eq. (kk3a)), from the current a
+ * (host, n_intervals each). */
+llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double *ln_rho);
+
+/* --- test and measurement hooks ----------------------------------------- */
+
+/* n_sweeps sweeps of every chain with the current a_k (mode LLR_MODE_*),
+ * starting at sweep index sweep0 (kind 0 counters; no replica exchange, no
+ * measurement, no recompute).  bits (host, n_sweeps x total chains, optional):
+ * bit c = heatbath colour c accepted, bit 8 + c = overrelaxation colour c. */
+llr_status llr_sweeps(llr_ctx *ctx, int n_sweeps, long long sweep0, int mode, uint16_t *bits);
+/* Full FP64 recompute of every chain's E. */
+llr_status llr_recompute_energy(llr_ctx *ctx);
+/* Record per-sweep accept bits of approach and run (host readback). */
+llr_status llr_enable_bits_log(llr_ctx *ctx, long long max_rows);
+llr_status llr_get_bits_log(llr_ctx *ctx, uint16_t *bits, long long *rows);
+/* Accumulated acceptance counts since creation (host, total chains each):
+ * heatbath proposals/accepts; replica-exchange proposals/accepts (scalars). */
+llr_status llr_stats(llr_ctx *ctx, long long *hb_prop, long long *hb_acc, long long *re_prop,
+                     long long *re_acc);
+/* Per-kernel timing with HIP events on the context stream: on/off, and the
+ * summed duration (ms) and count of heatbath-pass, overrelaxation-pass and
+ * energy launches since enabling. */
+llr_status llr_set_timing(llr_ctx *ctx, int on);
+llr_status llr_get_timing(llr_ctx *ctx, double *hb_ms, long long *hb_n, double *or_ms,
+                          long long *or_n, double *en_ms, long long *en_n);
+/* Philox4x32-10 of n counters (host n x 4) -> out (host n x 4). */
+llr_status llr_test_philox(llr_ctx *ctx, long n, const uint32_t *ctr, uint64_t seed, uint32_t *out);
+/* n von Mises draws (heatbath sampler of the context precision) with
+ * counters (i, c1, c2, c3); X (host, n, FP64), attempts (host, n; 0 = cap). */
+llr_status llr_test_vonmises(llr_ctx *ctx, long n, double kappa, uint64_t seed, uint32_t c1,
+                             uint32_t c2, uint32_t c3, double *X, int *attempts);
+
+/* --- reconstruction (FP64 kernels) -------------------------------------- */
+
+/* ln rho at centres and, for nb couplings beta (host), <u> = <E>/(6V) and
+ * C_V = Var(E)/(6V) from the midpoint sums (eqs. (l19)-(l20)); all host arrays. */
+llr_status llr_reconstruct(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
+                           double six_v, const double *beta, int nb, double *ln_rho,
+                           double *u_mean, double *cv);
+/* beta_c = argmax C_V on [blo, bhi] (grid step h, then golden section to tol)
+ * and the peak C_V/(6V) = Var(u). */
+llr_status llr_beta_c(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
+                      double six_v, double blo, double bhi, double h, double tol,
+                      double *beta_c, double *cv_peak_over_6v);
+
+/* --- warm-start network a(u, 1/L): 2 -> 64 (tanh) -> 64 (tanh) -> 1 ------ */
+/* Parameter vector (host, 4417 FP32): W1[64][2], b1[64], W2[64][64], b2[64],
+ * W3[64], b3.  Inputs uh = (u - 0.6)/0.1, lh = (1/L - 0.0875)/0.0375; output
+ * a = 1 + 0.1 y.  bf16 != 0: the 64x64 layer runs on MFMA in bfloat16 with
+ * FP32 accumulation; otherwise FP32 on the vector units. */
+llr_status llr_mlp_init(llr_ctx *ctx, uint64_t seed, float *weights);
+llr_status llr_mlp_predict(llr_ctx *ctx, const float *weights, const float *u, const float *inv_L,
+                           int n, int bf16, double *a_out);
+/* Mean squared error on a and its gradient (host, 4417). */
+llr_status llr_mlp_loss_grad(llr_ctx *ctx, const float *weights, const float *u,
+                             const float *inv_L, const double *a, int n, int bf16, float *grad,
+                             double *loss);
+/* Full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `epochs` steps;
+ * weights in/out; loss_hist (host, epochs, optional). n <= 4096. */
+llr_status llr_mlp_train(llr_ctx *ctx, float *weights, const float *u, const float *inv_L,
+                         const double *a, int n, int epochs, float lr, int bf16,
+                         double *loss_hist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LLR_H */

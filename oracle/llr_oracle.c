@@ -555,9 +555,10 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
      * heatbath passes only, at a per-chain coupling b (initially a^(0)).  A
      * class move is accepted iff it does not increase the distance of E to
      * the interval.  After every pass b moves by eta * sign(c_k - E_new),
-     * where E_new is the proposal's energy (accepted or not), and eta halves
-     * whenever that sign flips: a sign-based root search for the coupling
-     * whose proposals land at the centre.  Sweeps run in blocks of K followed
+     * where E_new is the proposal's energy (accepted or not); eta halves when
+     * that sign flips and grows by 1.2 while it repeats (within [1e-6, 0.05]):
+     * a sign-based root search for the coupling whose proposals land at the
+     * centre that cannot freeze while the target moves.  Sweeps run in blocks of K followed
      * by a full recompute of E; the phase ends once every chain is inside. */
     long long t_ap = 0;
     long long bitrow = 0;
@@ -589,7 +590,8 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                         bits |= 1 << col;
                     double En = E0 + dE;
                     int sg = (cen[k] > En) ? 1 : (cen[k] < En ? -1 : 0);
-                    if (sprev[c] != 0 && sg != sprev[c]) eta[c] *= 0.5;
+                    if (sprev[c] != 0 && sg != 0)
+                        eta[c] = (sg == sprev[c]) ? fmin(0.05, 1.2 * eta[c]) : fmax(1e-6, 0.5 * eta[c]);
                     b[c] = fmin(4.0, fmax(0.0, b[c] + eta[c] * (double)sg));
                     sprev[c] = sg;
                 }

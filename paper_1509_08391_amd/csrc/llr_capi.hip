@@ -1,0 +1,954 @@
+// llr_capi.hip -- host runtime and C ABI of the LLR library (include/llr.h).
+// Drives Algorithm 1 of arXiv:1509.08391 on the GPU: approach, then per
+// Robbins-Monro iteration N_TH + N_A sweeps of all chains (8 heatbath + 8
+// overrelaxation class passes each, periodic FP64 recompute, optional replica
+// exchange, measurement) and the update of every a_k.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/llr.h"
+#include "llr_internal.hpp"
+
+using namespace llr;
+
+static thread_local std::string g_err;
+
+static llr_status fail(llr_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(LLR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+struct HostLat {
+    int L;
+    int n;
+    double dE;
+    std::vector<double> E_low;
+    std::vector<double> a0;
+};
+
+struct TimingPair {
+    hipEvent_t a, b;
+    int kind;  // 0 hb, 1 or, 2 energy
+};
+
+struct llr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = LLR_FP64;
+    llr_params prm{};
+    std::vector<HostLat> lats;
+    LatTable lt{};
+    DevState ds{};
+    bool laid_out = false;
+    void* state = nullptr;
+    size_t state_bytes = 0;
+    bool have_energy = false;
+    std::vector<void*> allocs;
+    std::vector<long long> approach_sweeps;
+    std::vector<int> ap_done;  // approach finished per lattice
+    bool ap_open = false;
+    int rm_done = 0;       // RM iterations performed since llr_rm_begin
+    bool rm_open = false;
+    // timing
+    bool timing = false;
+    std::vector<TimingPair> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[3] = {0, 0, 0};
+    long long t_n[3] = {0, 0, 0};
+    // scratch for host <-> device staging of small arrays
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+static size_t elem_size(const llr_ctx* c) { return c->precision == LLR_FP32 ? 4 : 8; }
+
+static llr_status ensure_scratch(llr_ctx* c, size_t bytes) {
+    if (c->scratch_bytes >= bytes) return LLR_OK;
+    if (c->scratch) HIPCHK(hipFree(c->scratch));
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    HIPCHK(hipMalloc(&c->scratch, bytes));
+    c->scratch_bytes = bytes;
+    return LLR_OK;
+}
+
+template <typename P>
+static llr_status dalloc(llr_ctx* c, P** p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count * sizeof(P), 8)) != hipSuccess)
+        return fail(LLR_ENOMEM, "device allocation failed");
+    HIPCHK(hipMemsetAsync(q, 0, std::max<size_t>(count * sizeof(P), 8), c->stream));
+    c->allocs.push_back(q);
+    *p = (P*)q;
+    return LLR_OK;
+}
+
+// ceil(2^32 / d) for d >= 2 (divisor 1 is handled by the kernels directly)
+static uint32_t magic(uint32_t d) { return d < 2 ? 0u : (uint32_t)(((1ull << 32) + d - 1) / d); }
+
+static double restriction_width(const llr_ctx* c, double dE) {
+    return c->prm.replica_exchange ? (1.0 + c->prm.overlap) * dE : dE;
+}
+
+// Upload per-interval tables (lo, hi, cen, w) from the host lattice set.
+static llr_status upload_intervals(llr_ctx* c) {
+    const int n = c->lt.n_chains;
+    std::vector<double> lo(n), hi(n), cen(n), w(n), a(n);
+    int k = 0;
+    for (auto& hl : c->lats)
+        for (int i = 0; i < hl.n; ++i, ++k) {
+            const double ww = restriction_width(c, hl.dE);
+            cen[k] = hl.E_low[i] + 0.5 * hl.dE;
+            lo[k] = cen[k] - 0.5 * ww;
+            hi[k] = cen[k] + 0.5 * ww;
+            w[k] = ww;
+            a[k] = hl.a0[i];
+        }
+    HIPCHK(hipMemcpyAsync(c->ds.lo, lo.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ds.hi, hi.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ds.cen, cen.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ds.w, w.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ds.a, a.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LLR_OK;
+}
+
+static llr_status layout(llr_ctx* c) {
+    if (c->laid_out) return LLR_OK;
+    if (c->lats.empty()) return fail(LLR_ESTATE, "no lattice added");
+    LatTable& lt = c->lt;
+    memset(&lt, 0, sizeof(lt));
+    lt.n = (int)c->lats.size();
+    int chain0 = 0, block0 = 0, eblock0 = 0;
+    long long base = 0;
+    for (int i = 0; i < lt.n; ++i) {
+        const HostLat& h = c->lats[i];
+        LatDev& d = lt.l[i];
+        d.L = h.L;
+        d.hL = h.L / 2;
+        const long long V = (long long)h.L * h.L * h.L * h.L;
+        d.V2 = (uint32_t)(V / 2);
+        d.mL = magic((uint32_t)h.L);
+        d.mhL = magic((uint32_t)(h.L / 2));
+        d.n_chains = h.n;
+        d.chain0 = chain0;
+        d.bpc = (int)((d.V2 + kBlock - 1) / kBlock);
+        d.block0 = block0;
+        d.ebpc = (int)((V + kBlock - 1) / kBlock);
+        d.eblock0 = eblock0;
+        d.lat_id = i;
+        d.base = base;
+        chain0 += h.n;
+        block0 += h.n * d.bpc;
+        eblock0 += h.n * d.ebpc;
+        base += (long long)h.n * 8 * V;
+    }
+    lt.pass_blocks = block0;
+    lt.site_blocks = eblock0;
+    lt.n_chains = chain0;
+    c->state_bytes = (size_t)base * elem_size(c);
+    const int n = chain0;
+    DevState& s = c->ds;
+    llr_status st;
+#define AL(field, cnt) \
+    if ((st = dalloc(c, &s.field, (cnt))) != LLR_OK) return st;
+    AL(E, n) AL(acc, n) AL(eacc, n) AL(cur, 8 * n) AL(itv, n) AL(b, n) AL(eta, n)
+    AL(sprev, n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
+    AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n)
+    AL(lat_done, kMaxLat) AL(lat_outside, kMaxLat) AL(lat_approach, kMaxLat) AL(sweep_ctr, 1)
+    AL(approach_ctr, 1) AL(rm_iter, 1) AL(re_cnt, 2) AL(bits_row, 1)
+#undef AL
+    s.a_hist = nullptr;
+    s.bits_log = nullptr;
+    s.bits_rows_max = 0;
+    std::vector<int> ident(n);
+    for (int i = 0; i < n; ++i) ident[i] = i;
+    HIPCHK(hipMemcpyAsync(s.itv, ident.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(s.conf, ident.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    c->approach_sweeps.assign(lt.n, 0);
+    c->laid_out = true;
+    return upload_intervals(c);
+}
+
+// ---------------------------------------------------------------- timing
+static hipEvent_t ev_get(llr_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+}
+static void harvest(llr_ctx* c) {
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->t_ms[p.kind] += ms;
+            c->t_n[p.kind] += 1;
+        }
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+struct TimeScope {
+    llr_ctx* c;
+    int kind;
+    hipEvent_t a{}, b{};
+    TimeScope(llr_ctx* cc, int k) : c(cc), kind(k) {
+        if (c->timing) {
+            a = ev_get(c);
+            b = ev_get(c);
+            hipEventRecord(a, c->stream);
+        }
+    }
+    ~TimeScope() {
+        if (c->timing) {
+            hipEventRecord(b, c->stream);
+            c->pending.push_back({a, b, kind});
+            if (c->pending.size() >= 2048) {
+                hipEventSynchronize(b);
+                harvest(c);
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------- sweep drivers
+template <typename T>
+static void enqueue_hb_pass(llr_ctx* c, int colour, int mode, int kind) {
+    TimeScope ts(c, 0);
+    launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, colour, mode, kind, (uint32_t)c->prm.seed,
+                      (uint32_t)(c->prm.seed >> 32), c->stream);
+}
+template <typename T>
+static void enqueue_or_pass(llr_ctx* c, int colour) {
+    TimeScope ts(c, 1);
+    launch_or_pass<T>(c->lt, (T*)c->state, c->ds, colour, c->stream);
+}
+template <typename T>
+static void enqueue_energy(llr_ctx* c) {
+    TimeScope ts(c, 2);
+    launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream);
+}
+
+// one restricted sweep of all chains, then recompute / replica exchange / measurement
+template <typename T>
+static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bool measure) {
+    for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, mode, kSweep);
+    for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
+    if (recompute) enqueue_energy<T>(c);
+    if (replica) launch_replica(c->lt, c->ds, (uint32_t)c->prm.seed, (uint32_t)(c->prm.seed >> 32), c->stream);
+    launch_end_sweep(c->lt, c->ds, measure ? 1 : 0, 0, 1, c->stream);
+}
+
+template <typename T>
+static void enqueue_approach_sweep(llr_ctx* c) {
+    for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, LLR_MODE_APPROACH, kApproach);
+    launch_end_sweep(c->lt, c->ds, 0, 1, 0, c->stream);
+}
+
+static llr_status need_state(llr_ctx* c) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    if (!c->laid_out || !c->state) return fail(LLR_ESTATE, "state not bound");
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status approach_check(llr_ctx* c, bool* all) {
+    std::vector<int> outside(c->lt.n, 0);
+    launch_approach_check(c->lt, c->ds, c->stream);
+    HIPCHK(hipMemcpyAsync(outside.data(), c->ds.lat_outside, 4 * c->lt.n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *all = true;
+    for (int i = 0; i < c->lt.n; ++i) {
+        if (!c->ap_done[i] && outside[i] == 0) c->ap_done[i] = 1;
+        *all = *all && c->ap_done[i];
+    }
+    HIPCHK(hipMemcpyAsync(c->ds.lat_done, c->ap_done.data(), 4 * c->lt.n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status approach_begin_impl(llr_ctx* c) {
+    launch_approach_init(c->lt, c->ds, c->stream);
+    HIPCHK(hipMemsetAsync(c->ds.approach_ctr, 0, 4, c->stream));
+    c->ap_done.assign(c->lt.n, 0);
+    c->approach_sweeps.assign(c->lt.n, 0);
+    enqueue_energy<T>(c);
+    bool all = false;
+    llr_status st = approach_check<T>(c, &all);
+    if (st != LLR_OK) return st;
+    c->ap_open = true;
+    return LLR_OK;
+}
+
+// up to max_sweeps approach sweeps, in blocks of K followed by a recompute
+template <typename T>
+static llr_status approach_continue_impl(llr_ctx* c, long long max_sweeps, int* all_done) {
+    if (!c->ap_open) return fail(LLR_ESTATE, "call llr_approach_begin first");
+    const int K = std::max(1, c->prm.recompute_every);
+    bool all = true;
+    for (int i = 0; i < c->lt.n; ++i) all = all && c->ap_done[i];
+    long long t = 0;
+    while (!all && t < max_sweeps) {
+        for (int j = 0; j < K; ++j) enqueue_approach_sweep<T>(c);
+        enqueue_energy<T>(c);
+        for (int i = 0; i < c->lt.n; ++i)
+            if (!c->ap_done[i]) c->approach_sweeps[i] += K;
+        t += K;
+        llr_status st = approach_check<T>(c, &all);
+        if (st != LLR_OK) return st;
+    }
+    HIPCHK(hipGetLastError());
+    if (all_done) *all_done = all ? 1 : 0;
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status approach_impl(llr_ctx* c, long long* sweeps) {
+    llr_status st = approach_begin_impl<T>(c);
+    if (st != LLR_OK) return st;
+    int all = 0;
+    st = approach_continue_impl<T>(c, c->prm.approach_cap, &all);
+    if (sweeps) for (int i = 0; i < c->lt.n; ++i) sweeps[i] = c->approach_sweeps[i];
+    if (st != LLR_OK) return st;
+    if (!all) return fail(LLR_EAPPROACH, "approach cap reached before every chain entered its interval");
+    return LLR_OK;
+}
+
+static llr_status rm_begin(llr_ctx* c) {
+    const llr_params& p = c->prm;
+    const int n = c->lt.n_chains;
+    if (p.n_a < 1 || p.n_th < 0 || p.n_rm < 1) return fail(LLR_EINVAL, "need n_a >= 1, n_th >= 0, n_rm >= 1");
+    if (c->ds.a_hist) {
+        HIPCHK(hipFree(c->ds.a_hist));
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->ds.a_hist), c->allocs.end());
+        c->ds.a_hist = nullptr;
+    }
+    llr_status st = dalloc(c, &c->ds.a_hist, (size_t)(p.n_rm + 1) * n);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipMemcpyAsync(c->ds.a_hist, c->ds.a, 8 * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(c->ds.sumE, 0, 8 * n, c->stream));
+    HIPCHK(hipMemsetAsync(c->ds.sweep_ctr, 0, 4, c->stream));
+    HIPCHK(hipMemsetAsync(c->ds.rm_iter, 0, 4, c->stream));
+    HIPCHK(hipMemsetAsync(c->ds.conv_iter, 0xff, 4 * n, c->stream));
+    HIPCHK(hipMemsetAsync(c->ds.conv_sweeps, 0xff, 8 * n, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->rm_done = 0;
+    c->rm_open = true;
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status rm_step_impl(llr_ctx* c, int iters) {
+    const llr_params& p = c->prm;
+    if (!c->rm_open) return fail(LLR_ESTATE, "call llr_rm_begin first");
+    if (iters < 0 || c->rm_done + iters > p.n_rm) return fail(LLR_EINVAL, "more RM iterations than n_rm");
+    const int K = std::max(1, p.recompute_every);
+    const int nsw = p.n_th + p.n_a;
+    RunCfg cfg{(uint32_t)p.seed, (uint32_t)(p.seed >> 32), p.n_a, nsw, p.eps};
+    for (int it = 0; it < iters; ++it) {
+        for (int j = 0; j < nsw; ++j) {
+            const bool rec = ((j + 1) % K == 0) || (j == nsw - 1);
+            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, rec, p.replica_exchange != 0, j >= p.n_th);
+            if ((j & 255) == 255) HIPCHK(hipStreamSynchronize(c->stream));   // bound the queue depth
+        }
+        launch_rm_update(c->lt, c->ds, cfg, c->stream);
+        c->rm_done += 1;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    if (c->timing) harvest(c);
+    return LLR_OK;
+}
+
+static llr_status rm_converged(llr_ctx* c) {
+    const int n = c->lt.n_chains;
+    std::vector<int> conv(n);
+    HIPCHK(hipMemcpy(conv.data(), c->ds.conv_iter, 4 * n, hipMemcpyDeviceToHost));
+    for (int k = 0; k < n; ++k)
+        if (conv[k] < 0) return LLR_WARN_NOT_CONVERGED;
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status run_impl(llr_ctx* c) {
+    llr_status st = rm_begin(c);
+    if (st != LLR_OK) return st;
+    st = rm_step_impl<T>(c, c->prm.n_rm);
+    if (st != LLR_OK) return st;
+    return rm_converged(c);
+}
+
+template <typename T>
+static llr_status sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint16_t* bits) {
+    const uint32_t s0 = (uint32_t)sweep0;
+    HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
+    const int n = c->lt.n_chains;
+    for (int t = 0; t < n_sweeps; ++t) {
+        enqueue_sweep<T>(c, mode, false, false, false);
+        if (bits) {
+            HIPCHK(hipMemcpyAsync(bits + (size_t)t * n, c->ds.bits_last, 2 * n, hipMemcpyDeviceToHost, c->stream));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    if (c->timing) harvest(c);
+    return LLR_OK;
+}
+
+// ================================================================= C ABI
+extern "C" {
+
+const char* llr_last_error(void) { return g_err.c_str(); }
+
+llr_status llr_create(llr_ctx** out, int hip_device, void* hip_stream, int precision) {
+    if (!out) return fail(LLR_EINVAL, "out is null");
+    if (precision != LLR_FP64 && precision != LLR_FP32) return fail(LLR_EINVAL, "precision must be LLR_FP64 or LLR_FP32");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+        return fail(LLR_EDEVICE, "no such HIP device");
+    HIPCHK(hipSetDevice(hip_device));
+    llr_ctx* c = new llr_ctx();
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    c->precision = precision;
+    c->prm.n_th = 100;
+    c->prm.n_a = 100;
+    c->prm.n_rm = 20;
+    c->prm.seed = 1509083910ull;
+    c->prm.replica_exchange = 0;
+    c->prm.overlap = 1.0;
+    c->prm.recompute_every = 10;
+    c->prm.eps = 1e-4;
+    c->prm.approach_cap = 100000;
+    *out = c;
+    return LLR_OK;
+}
+
+void llr_destroy(llr_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : c->pool) hipEventDestroy(e);
+    for (void* p : c->allocs) hipFree(p);
+    if (c->scratch) hipFree(c->scratch);
+    delete c;
+}
+
+llr_status llr_set_params(llr_ctx* c, const llr_params* p) {
+    if (!c || !p) return fail(LLR_EINVAL, "null argument");
+    if (p->n_a < 1 || p->n_th < 0 || p->n_rm < 0 || p->recompute_every < 1 || p->approach_cap < 0 ||
+        !(p->eps >= 0) || !(p->overlap >= 0))
+        return fail(LLR_EINVAL, "invalid parameters");
+    const bool width_changed = c->laid_out && (p->replica_exchange != c->prm.replica_exchange || p->overlap != c->prm.overlap);
+    c->prm = *p;
+    if (width_changed) return upload_intervals(c);
+    return LLR_OK;
+}
+
+llr_status llr_add_lattice(llr_ctx* c, int L, int n_intervals, const double* E_low, double dE, int* lattice_id) {
+    if (!c || !E_low) return fail(LLR_EINVAL, "null argument");
+    if (c->laid_out) return fail(LLR_ESTATE, "lattices must be added before llr_state_bytes/llr_bind_state");
+    if (L < 2 || L > 32 || (L & 1)) return fail(LLR_EINVAL, "L must be even and in [2, 32]");
+    if (n_intervals < 1 || n_intervals > 4096) return fail(LLR_EINVAL, "n_intervals must be in [1, 4096]");
+    if (!(dE > 0)) return fail(LLR_EINVAL, "dE must be > 0");
+    if ((int)c->lats.size() >= kMaxLat) return fail(LLR_EINVAL, "at most 8 lattices");
+    const double six_v = 6.0 * (double)L * L * L * L;
+    for (int k = 0; k < n_intervals; ++k) {
+        if (!std::isfinite(E_low[k])) return fail(LLR_EINVAL, "non-finite interval edge");
+        if (k && !(E_low[k] > E_low[k - 1])) return fail(LLR_EINVAL, "interval edges must ascend");
+        if (E_low[k] < -six_v || E_low[k] + dE > six_v) return fail(LLR_EINVAL, "interval outside [-6V, 6V]");
+    }
+    HostLat h;
+    h.L = L;
+    h.n = n_intervals;
+    h.dE = dE;
+    h.E_low.assign(E_low, E_low + n_intervals);
+    h.a0.assign(n_intervals, 1.0);
+    c->lats.push_back(h);
+    if (lattice_id) *lattice_id = (int)c->lats.size() - 1;
+    return LLR_OK;
+}
+
+llr_status llr_state_bytes(llr_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(LLR_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = layout(c);
+    if (st != LLR_OK) return st;
+    *bytes = c->state_bytes;
+    return LLR_OK;
+}
+
+llr_status llr_bind_state(llr_ctx* c, void* dev_state, size_t bytes) {
+    if (!c || !dev_state) return fail(LLR_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = layout(c);
+    if (st != LLR_OK) return st;
+    if (bytes != c->state_bytes) return fail(LLR_EINVAL, "state buffer size differs from llr_state_bytes");
+    if (((uintptr_t)dev_state) & 255) return fail(LLR_EINVAL, "state buffer must be 256-byte aligned");
+    c->state = dev_state;
+    c->have_energy = false;
+    return LLR_OK;
+}
+
+llr_status llr_set_a(llr_ctx* c, int lat, const double* a) {
+    if (!c || !a) return fail(LLR_EINVAL, "null argument");
+    if (lat < 0 || lat >= (int)c->lats.size()) return fail(LLR_EINVAL, "no such lattice");
+    for (int k = 0; k < c->lats[lat].n; ++k)
+        if (!std::isfinite(a[k])) return fail(LLR_EINVAL, "non-finite a");
+    c->lats[lat].a0.assign(a, a + c->lats[lat].n);
+    if (c->laid_out) {
+        HIPCHK(hipSetDevice(c->device));
+        HIPCHK(hipMemcpyAsync(c->ds.a + c->lt.l[lat].chain0, a, 8 * c->lats[lat].n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return LLR_OK;
+}
+
+llr_status llr_hot_start(llr_ctx* c) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    const uint32_t k0 = (uint32_t)c->prm.seed, k1 = (uint32_t)(c->prm.seed >> 32);
+    if (c->precision == LLR_FP32) {
+        launch_hot_start<float>(c->lt, (float*)c->state, c->ds, k0, k1, c->stream);
+        enqueue_energy<float>(c);
+    } else {
+        launch_hot_start<double>(c->lt, (double*)c->state, c->ds, k0, k1, c->stream);
+        enqueue_energy<double>(c);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    c->have_energy = true;
+    return LLR_OK;
+}
+
+llr_status llr_import_state(llr_ctx* c, int lat, const void* dev) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (lat < 0 || lat >= c->lt.n || !dev) return fail(LLR_EINVAL, "bad lattice or pointer");
+    HIPCHK(hipSetDevice(c->device));
+    if (c->precision == LLR_FP32) {
+        launch_import<float>(c->lt, lat, (float*)c->state, c->ds, (const float*)dev, c->stream);
+        enqueue_energy<float>(c);
+    } else {
+        launch_import<double>(c->lt, lat, (double*)c->state, c->ds, (const double*)dev, c->stream);
+        enqueue_energy<double>(c);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    c->have_energy = true;
+    return LLR_OK;
+}
+
+llr_status llr_export_state(llr_ctx* c, int lat, void* dev) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (lat < 0 || lat >= c->lt.n || !dev) return fail(LLR_EINVAL, "bad lattice or pointer");
+    HIPCHK(hipSetDevice(c->device));
+    if (c->precision == LLR_FP32)
+        launch_export<float>(c->lt, lat, (const float*)c->state, c->ds, (float*)dev, c->stream);
+    else
+        launch_export<double>(c->lt, lat, (const double*)c->state, c->ds, (double*)dev, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_approach(llr_ctx* c, long long* sweeps) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? approach_impl<float>(c, sweeps) : approach_impl<double>(c, sweeps);
+}
+
+llr_status llr_approach_begin(llr_ctx* c) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? approach_begin_impl<float>(c) : approach_begin_impl<double>(c);
+}
+
+llr_status llr_approach_continue(llr_ctx* c, long long max_sweeps, long long* sweeps, int* all_done) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (max_sweeps < 0) return fail(LLR_EINVAL, "max_sweeps < 0");
+    HIPCHK(hipSetDevice(c->device));
+    st = c->precision == LLR_FP32 ? approach_continue_impl<float>(c, max_sweeps, all_done)
+                                  : approach_continue_impl<double>(c, max_sweeps, all_done);
+    if (sweeps) for (int i = 0; i < c->lt.n; ++i) sweeps[i] = c->approach_sweeps[i];
+    return st;
+}
+
+llr_status llr_run(llr_ctx* c) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? run_impl<float>(c) : run_impl<double>(c);
+}
+
+llr_status llr_rm_begin(llr_ctx* c) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    return rm_begin(c);
+}
+
+llr_status llr_rm_step(llr_ctx* c, int iterations) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    st = c->precision == LLR_FP32 ? rm_step_impl<float>(c, iterations) : rm_step_impl<double>(c, iterations);
+    if (st != LLR_OK) return st;
+    return c->rm_done == c->prm.n_rm ? rm_converged(c) : LLR_OK;
+}
+
+llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint16_t* bits) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (n_sweeps < 0 || mode < 0 || mode > 2) return fail(LLR_EINVAL, "bad n_sweeps or mode");
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? sweeps_impl<float>(c, n_sweeps, sweep0, mode, bits)
+                                    : sweeps_impl<double>(c, n_sweeps, sweep0, mode, bits);
+}
+
+llr_status llr_recompute_energy(llr_ctx* c) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    if (c->precision == LLR_FP32) enqueue_energy<float>(c);
+    else enqueue_energy<double>(c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_get_a(llr_ctx* c, int lat, double* a, int* conv_iter, long long* conv_sweeps) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    if (lat < 0 || lat >= c->lt.n) return fail(LLR_EINVAL, "no such lattice");
+    HIPCHK(hipSetDevice(c->device));
+    const LatDev& L = c->lt.l[lat];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (a) HIPCHK(hipMemcpy(a, c->ds.a + L.chain0, 8 * L.n_chains, hipMemcpyDeviceToHost));
+    if (conv_iter) HIPCHK(hipMemcpy(conv_iter, c->ds.conv_iter + L.chain0, 4 * L.n_chains, hipMemcpyDeviceToHost));
+    if (conv_sweeps) {
+        HIPCHK(hipMemcpy(conv_sweeps, c->ds.conv_sweeps + L.chain0, 8 * L.n_chains, hipMemcpyDeviceToHost));
+        for (int k = 0; k < L.n_chains; ++k)
+            if (conv_sweeps[k] >= 0) conv_sweeps[k] += c->approach_sweeps[lat];
+    }
+    return LLR_OK;
+}
+
+llr_status llr_get_history(llr_ctx* c, int lat, double* a_hist) {
+    if (!c || !c->laid_out || !c->ds.a_hist) return fail(LLR_ESTATE, "no run");
+    if (lat < 0 || lat >= c->lt.n || !a_hist) return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    const LatDev& L = c->lt.l[lat];
+    const int n = c->lt.n_chains;
+    std::vector<double> all((size_t)(c->prm.n_rm + 1) * n);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(all.data(), c->ds.a_hist, 8 * all.size(), hipMemcpyDeviceToHost));
+    for (int r = 0; r <= c->prm.n_rm; ++r)
+        for (int k = 0; k < L.n_chains; ++k) a_hist[(size_t)r * L.n_chains + k] = all[(size_t)r * n + L.chain0 + k];
+    return LLR_OK;
+}
+
+llr_status llr_get_energy(llr_ctx* c, int lat, double* E, int* conf) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    if (lat < 0 || lat >= c->lt.n) return fail(LLR_EINVAL, "no such lattice");
+    HIPCHK(hipSetDevice(c->device));
+    const LatDev& L = c->lt.l[lat];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (E) HIPCHK(hipMemcpy(E, c->ds.E + L.chain0, 8 * L.n_chains, hipMemcpyDeviceToHost));
+    if (conf) {
+        HIPCHK(hipMemcpy(conf, c->ds.conf + L.chain0, 4 * L.n_chains, hipMemcpyDeviceToHost));
+        for (int k = 0; k < L.n_chains; ++k) conf[k] -= L.chain0;
+    }
+    return LLR_OK;
+}
+
+llr_status llr_get_ln_rho(llr_ctx* c, int lat, double* centres, double* ln_rho) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    if (lat < 0 || lat >= c->lt.n || !ln_rho) return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    const HostLat& h = c->lats[lat];
+    const int n = h.n;
+    llr_status st = ensure_scratch(c, 16 * (size_t)n + 64);
+    if (st != LLR_OK) return st;
+    double* d = (double*)c->scratch;
+    launch_recon(nullptr, c->ds.a + c->lt.l[lat].chain0, n, h.dE, 1.0, nullptr, 0, d, nullptr, nullptr, c->stream);
+    HIPCHK(hipMemcpyAsync(ln_rho, d, 8 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (centres)
+        for (int k = 0; k < n; ++k) centres[k] = h.E_low[k] + 0.5 * h.dE;
+    return LLR_OK;
+}
+
+llr_status llr_enable_bits_log(llr_ctx* c, long long max_rows) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "lay out the lattices first");
+    if (max_rows < 0) return fail(LLR_EINVAL, "max_rows < 0");
+    HIPCHK(hipSetDevice(c->device));
+    if (c->ds.bits_log) {
+        HIPCHK(hipFree(c->ds.bits_log));
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->ds.bits_log), c->allocs.end());
+        c->ds.bits_log = nullptr;
+    }
+    c->ds.bits_rows_max = max_rows;
+    if (max_rows > 0) {
+        llr_status st = dalloc(c, &c->ds.bits_log, (size_t)max_rows * c->lt.n_chains);
+        if (st != LLR_OK) return st;
+    }
+    HIPCHK(hipMemsetAsync(c->ds.bits_row, 0, 8, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LLR_OK;
+}
+
+llr_status llr_get_bits_log(llr_ctx* c, uint16_t* bits, long long* rows) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    HIPCHK(hipSetDevice(c->device));
+    long long r = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&r, c->ds.bits_row, 8, hipMemcpyDeviceToHost));
+    r = std::min(r, c->ds.bits_rows_max);
+    if (rows) *rows = r;
+    if (bits && r > 0) HIPCHK(hipMemcpy(bits, c->ds.bits_log, 2 * (size_t)r * c->lt.n_chains, hipMemcpyDeviceToHost));
+    return LLR_OK;
+}
+
+llr_status llr_stats(llr_ctx* c, long long* hb_prop, long long* hb_acc, long long* re_prop, long long* re_acc) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = c->lt.n_chains;
+    if (hb_prop) HIPCHK(hipMemcpy(hb_prop, c->ds.hb_prop, 8 * n, hipMemcpyDeviceToHost));
+    if (hb_acc) HIPCHK(hipMemcpy(hb_acc, c->ds.hb_acc, 8 * n, hipMemcpyDeviceToHost));
+    unsigned long long re[2] = {0, 0};
+    HIPCHK(hipMemcpy(re, c->ds.re_cnt, 16, hipMemcpyDeviceToHost));
+    if (re_prop) *re_prop = (long long)re[0];
+    if (re_acc) *re_acc = (long long)re[1];
+    return LLR_OK;
+}
+
+llr_status llr_set_timing(llr_ctx* c, int on) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    harvest(c);
+    c->timing = on != 0;
+    for (int i = 0; i < 3; ++i) { c->t_ms[i] = 0; c->t_n[i] = 0; }
+    return LLR_OK;
+}
+
+llr_status llr_get_timing(llr_ctx* c, double* hb_ms, long long* hb_n, double* or_ms, long long* or_n, double* en_ms,
+                          long long* en_n) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    harvest(c);
+    if (hb_ms) *hb_ms = c->t_ms[0];
+    if (hb_n) *hb_n = c->t_n[0];
+    if (or_ms) *or_ms = c->t_ms[1];
+    if (or_n) *or_n = c->t_n[1];
+    if (en_ms) *en_ms = c->t_ms[2];
+    if (en_n) *en_n = c->t_n[2];
+    return LLR_OK;
+}
+
+llr_status llr_test_philox(llr_ctx* c, long n, const uint32_t* ctr, uint64_t seed, uint32_t* out) {
+    if (!c || !ctr || !out || n < 0) return fail(LLR_EINVAL, "bad argument");
+    if (n == 0) return LLR_OK;
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 32 * (size_t)n);
+    if (st != LLR_OK) return st;
+    uint4* d = (uint4*)c->scratch;
+    HIPCHK(hipMemcpyAsync(d, ctr, 16 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    launch_test_philox(n, d, (uint32_t)seed, (uint32_t)(seed >> 32), d + n, c->stream);
+    HIPCHK(hipMemcpyAsync(out, d + n, 16 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_test_vonmises(llr_ctx* c, long n, double kappa, uint64_t seed, uint32_t c1, uint32_t c2, uint32_t c3,
+                             double* X, int* attempts) {
+    if (!c || !X || !attempts || n < 0 || !(kappa >= 0)) return fail(LLR_EINVAL, "bad argument");
+    if (n == 0) return LLR_OK;
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 12 * (size_t)n + 64);
+    if (st != LLR_OK) return st;
+    double* dX = (double*)c->scratch;
+    int* dA = (int*)(dX + n);
+    if (c->precision == LLR_FP32)
+        launch_test_vonmises<float>(n, kappa, (uint32_t)seed, (uint32_t)(seed >> 32), c1, c2, c3, dX, dA, c->stream);
+    else
+        launch_test_vonmises<double>(n, kappa, (uint32_t)seed, (uint32_t)(seed >> 32), c1, c2, c3, dX, dA, c->stream);
+    HIPCHK(hipMemcpyAsync(X, dX, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(attempts, dA, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_reconstruct(llr_ctx* c, const double* centres, const double* a, int n, double s, double six_v,
+                           const double* beta, int nb, double* ln_rho, double* u_mean, double* cv) {
+    if (!c || !centres || !a || n < 1 || nb < 0 || !(s > 0) || !(six_v > 0)) return fail(LLR_EINVAL, "bad argument");
+    if (nb > 0 && (!beta || !u_mean || !cv)) return fail(LLR_EINVAL, "bad beta arrays");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 3 * nb) + 64);
+    if (st != LLR_OK) return st;
+    double* dc = (double*)c->scratch;
+    double* da = dc + n;
+    double* dl = da + n;
+    double* db = dl + n;
+    double* du = db + nb;
+    double* dv = du + nb;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * n, hipMemcpyHostToDevice, c->stream));
+    if (nb) HIPCHK(hipMemcpyAsync(db, beta, 8 * nb, hipMemcpyHostToDevice, c->stream));
+    launch_recon(dc, da, n, s, six_v, db, nb, dl, du, dv, c->stream);
+    if (ln_rho) HIPCHK(hipMemcpyAsync(ln_rho, dl, 8 * n, hipMemcpyDeviceToHost, c->stream));
+    if (nb) {
+        HIPCHK(hipMemcpyAsync(u_mean, du, 8 * nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(cv, dv, 8 * nb, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_beta_c(llr_ctx* c, const double* centres, const double* a, int n, double s, double six_v, double blo,
+                      double bhi, double h, double tol, double* beta_c, double* cv_peak) {
+    if (!c || !centres || !a || n < 1 || !(s > 0) || !(six_v > 0) || !(bhi > blo) || !(h > 0) || !(tol > 0) ||
+        !beta_c || !cv_peak)
+        return fail(LLR_EINVAL, "bad argument");
+    const long ng = (long)std::floor((bhi - blo) / h + 0.5);
+    if (ng > 10000000) return fail(LLR_EINVAL, "beta grid too fine");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + ng + 8) + 64);
+    if (st != LLR_OK) return st;
+    double* dc = (double*)c->scratch;
+    double* da = dc + n;
+    double* out = da + n;
+    double* scr = out + 4;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * n, hipMemcpyHostToDevice, c->stream));
+    launch_beta_c(dc, da, n, s, six_v, blo, bhi, h, tol, scr, out, c->stream);
+    double r[2];
+    HIPCHK(hipMemcpyAsync(r, out, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    *beta_c = r[0];
+    *cv_peak = r[1];
+    return LLR_OK;
+}
+
+llr_status llr_mlp_init(llr_ctx* c, uint64_t seed, float* weights) {
+    if (!c || !weights) return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 4 * kMlpNP);
+    if (st != LLR_OK) return st;
+    launch_mlp_init(seed, (float*)c->scratch, c->stream);
+    HIPCHK(hipMemcpyAsync(weights, c->scratch, 4 * kMlpNP, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+static llr_status stage_inputs(llr_ctx* c, const float* w, const float* u, const float* invL, const double* a, int n,
+                               float** dw, float** du, float** dl, double** dA, size_t extra) {
+    const size_t need = 4 * (size_t)kMlpNP + 8 * (size_t)n + 8 * (size_t)n + extra + 256;
+    llr_status st = ensure_scratch(c, need);
+    if (st != LLR_OK) return st;
+    char* p = (char*)c->scratch;
+    *dw = (float*)p; p += 4 * (size_t)kMlpNP; p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    *du = (float*)p; p += 4 * (size_t)n;
+    *dl = (float*)p; p += 4 * (size_t)n; p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    *dA = (double*)p;
+    HIPCHK(hipMemcpyAsync(*dw, w, 4 * kMlpNP, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(*du, u, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(*dl, invL, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    if (a) HIPCHK(hipMemcpyAsync(*dA, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    return LLR_OK;
+}
+
+llr_status llr_mlp_predict(llr_ctx* c, const float* w, const float* u, const float* invL, int n, int bf16,
+                           double* a_out) {
+    if (!c || !w || !u || !invL || !a_out || n < 0) return fail(LLR_EINVAL, "bad argument");
+    if (n == 0) return LLR_OK;
+    HIPCHK(hipSetDevice(c->device));
+    float *dw, *du, *dl;
+    double* dA;
+    llr_status st = stage_inputs(c, w, u, invL, nullptr, n, &dw, &du, &dl, &dA, 0);
+    if (st != LLR_OK) return st;
+    launch_mlp_forward(dw, du, dl, n, bf16, dA, c->stream);
+    HIPCHK(hipMemcpyAsync(a_out, dA, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_mlp_loss_grad(llr_ctx* c, const float* w, const float* u, const float* invL, const double* a, int n,
+                             int bf16, float* grad, double* loss) {
+    if (!c || !w || !u || !invL || !a || !grad || !loss || n < 1 || n > 4096) return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    float *dw, *du, *dl;
+    double* dA;
+    llr_status st = stage_inputs(c, w, u, invL, a, n, &dw, &du, &dl, &dA, 4 * (size_t)kMlpNP + 64);
+    if (st != LLR_OK) return st;
+    float* dg = (float*)(dA + n);
+    double* dloss = (double*)(dg + kMlpNP + 2);
+    dloss = (double*)(((uintptr_t)dloss + 7) & ~(uintptr_t)7);
+    launch_mlp_loss_grad(dw, du, dl, dA, n, bf16, dg, dloss, c->stream);
+    HIPCHK(hipMemcpyAsync(grad, dg, 4 * kMlpNP, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(loss, dloss, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_mlp_train(llr_ctx* c, float* w, const float* u, const float* invL, const double* a, int n, int epochs,
+                         float lr, int bf16, double* loss_hist) {
+    if (!c || !w || !u || !invL || !a || n < 1 || n > 4096 || epochs < 0 || !(lr > 0))
+        return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    float *dw, *du, *dl;
+    double* dA;
+    const size_t extra = 4 * 3 * (size_t)kMlpNP + 8 * (size_t)std::max(epochs, 1) + 256;
+    llr_status st = stage_inputs(c, w, u, invL, a, n, &dw, &du, &dl, &dA, extra);
+    if (st != LLR_OK) return st;
+    float* dg = (float*)(dA + n);
+    float* dm = dg + kMlpNP;
+    float* dv = dm + kMlpNP;
+    double* dloss = (double*)(((uintptr_t)(dv + kMlpNP) + 7) & ~(uintptr_t)7);
+    HIPCHK(hipMemsetAsync(dm, 0, 4 * 2 * (size_t)kMlpNP, c->stream));
+    for (int e = 0; e < epochs; ++e) {
+        launch_mlp_loss_grad(dw, du, dl, dA, n, bf16, dg, dloss + e, c->stream);
+        launch_mlp_adam(dw, dm, dv, dg, e + 1, lr, c->stream);
+    }
+    HIPCHK(hipMemcpyAsync(w, dw, 4 * kMlpNP, hipMemcpyDeviceToHost, c->stream));
+    if (loss_hist && epochs > 0) HIPCHK(hipMemcpyAsync(loss_hist, dloss, 8 * (size_t)epochs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// llr_device.hpp -- device helpers for the gfx950 LLR kernels: the
+// Philox4x32-10 counter generator, uniform conversions, precision-specific
+// math, and the XCD-aware block remap.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace llr {
+
+constexpr int kBlock = 256;           // threads per block of the lattice kernels
+constexpr int kMaxLat = 8;            // lattices per context
+constexpr int kVmCap = 64;            // heatbath sampler attempt cap
+constexpr double kFix = 1099511627776.0;        // 2^40: fixed-point scale of per-thread energy terms
+constexpr double kFix24Inv = 1.0 / 16777216.0;  // 2^-24: resolution of the per-chain sums
+
+enum Kind : uint32_t { kSweep = 0, kInit = 1, kApproach = 2, kReplica = 3, kMlp = 4 };
+
+__host__ __device__ inline uint32_t ctr1_word(uint32_t attempt_pair, uint32_t colour, uint32_t kind,
+                                              uint32_t lat) {
+    return (attempt_pair & 0xffu) | ((colour & 0xfu) << 8) | ((kind & 0xfu) << 12) | ((lat & 0xffu) << 16);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplications with the published multipliers, key bumped by the published
+// Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                       (uint32_t)p0);
+    }
+    return c;
+}
+
+// Precision traits: FP64 uses the full-precision library math; FP32 uses the
+// hardware transcendental unit (v_sin_f32/v_cos_f32 take revolutions) and
+// approximate reciprocals where the sampler tolerates ulp-level error.
+template <typename T> struct Math;
+
+template <> struct Math<double> {
+    static constexpr bool f32 = false;
+    __device__ static __forceinline__ double unif(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+    __device__ static __forceinline__ double sunif(uint32_t w) { return ((double)(int32_t)w + 0.5) * 0x1p-31; }
+    __device__ static __forceinline__ void sincos_rad(double x, double* s, double* c) { sincos(x, s, c); }
+    // sin, cos of (pi/2) v for |v| < 1
+    __device__ static __forceinline__ void sincos_halfpi(double v, double* s, double* c) { sincospi(0.5 * v, s, c); }
+    __device__ static __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
+    __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    __device__ static __forceinline__ double log_(double x) { return log(x); }
+    __device__ static __forceinline__ double div_(double a, double b) { return a / b; }
+    __device__ static __forceinline__ double pi() { return 3.14159265358979323846; }
+};
+
+template <> struct Math<float> {
+    static constexpr bool f32 = true;
+    __device__ static __forceinline__ float unif(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+    __device__ static __forceinline__ float sunif(uint32_t w) { return ((float)((int32_t)w >> 9) + 0.5f) * 0x1p-22f; }
+    __device__ static __forceinline__ void sincos_rad(float x, float* s, float* c) {
+        const float r = x * 0.15915494309189535f;
+        *s = __builtin_amdgcn_sinf(r);
+        *c = __builtin_amdgcn_cosf(r);
+    }
+    __device__ static __forceinline__ void sincos_halfpi(float v, float* s, float* c) {
+        const float r = 0.25f * v;
+        *s = __builtin_amdgcn_sinf(r);
+        *c = __builtin_amdgcn_cosf(r);
+    }
+    __device__ static __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
+    __device__ static __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    __device__ static __forceinline__ float log_(float x) { return __logf(x); }
+    __device__ static __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    __device__ static __forceinline__ float pi() { return 3.14159265f; }
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// works on a contiguous range of logical blocks (neighbouring tiles of a chain
+// share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int per = nb >> 3, rem = nb & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// exact n / d for n < 2^32 / d via a precomputed m = ceil(2^32 / d)
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m) { return __umulhi(n, m); }
+
+}  // namespace llr

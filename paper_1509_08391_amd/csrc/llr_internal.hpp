@@ -1,0 +1,116 @@
+// llr_internal.hpp -- structures shared by the kernel launchers and the
+// host runtime of the LLR library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "llr_device.hpp"
+
+namespace llr {
+
+// One lattice of the batch: n_chains chains of size L^4, one per interval.
+// Chain g of the lattice owns 2 planes x 8 colours x V/2 angles at
+// base + (g - chain0) * 8 V, plane b, colour c at offset (8 b + c) V/2.
+struct LatDev {
+    int L, hL;             // L, L/2
+    uint32_t V2;           // V/2
+    uint32_t mL, mhL;      // ceil(2^32 / L), ceil(2^32 / (L/2))
+    int n_chains;          // = number of intervals
+    int chain0;            // first global chain index (= first global interval index)
+    int bpc;               // blocks per chain in the class-pass kernels (V/2 / 256, rounded up)
+    int block0;            // first block of this lattice in the class-pass grid
+    int ebpc;              // blocks per chain in the site kernels (V / 256, rounded up)
+    int eblock0;           // first block of this lattice in the site grid
+    int lat_id;
+    long long base;        // element offset of the lattice's first chain
+};
+
+struct LatTable {
+    LatDev l[kMaxLat];
+    int n;
+    int pass_blocks;       // total blocks of a class-pass launch
+    int site_blocks;       // total blocks of a site launch
+    int n_chains;          // total chains = total intervals
+};
+
+// Per-chain and per-interval device state (all indices global).
+struct DevState {
+    // per chain
+    double* E;             // current energy (incremental, FP64)
+    unsigned long long* acc;   // arrivals << 48 | fixed-point Delta E of the running pass
+    unsigned long long* eacc;  // the same for the energy recompute
+    uint8_t* cur;          // 8 per chain: current plane of each colour
+    int* itv;              // global index of the interval the chain serves
+    double* b;             // approach coupling
+    double* eta;           // approach step
+    int* sprev;            // approach: sign of the previous proposal offset
+    uint16_t* bits;        // accept bits of the running sweep
+    uint16_t* bits_last;   // accept bits of the last finished sweep
+    unsigned long long* hb_prop;
+    unsigned long long* hb_acc;
+    // per interval (global index = chain0 of the lattice + local index)
+    double* a;             // Robbins-Monro coupling
+    double* lo;            // restriction [lo, hi]
+    double* hi;
+    double* cen;           // centre c_k
+    double* w;             // restriction width
+    double* sumE;          // sum of measured energies in the running RM iteration
+    int* conf;             // chain serving the interval
+    int* conv_iter;
+    long long* conv_sweeps;
+    double* a_hist;        // (n_rm + 1) x n_chains
+    // per lattice
+    int* lat_done;         // approach finished
+    int* lat_outside;      // chains outside their interval (approach check)
+    long long* lat_approach;   // approach sweeps performed
+    // scalars
+    uint32_t* sweep_ctr;   // RM sweep index (counter word 2)
+    uint32_t* approach_ctr;
+    int* rm_iter;          // current RM iteration n
+    unsigned long long* re_cnt;  // [proposed, accepted]
+    uint16_t* bits_log;    // optional, rows x n_chains
+    long long* bits_row;   // next log row
+    long long bits_rows_max;
+};
+
+struct RunCfg {
+    uint32_t k0, k1;       // Philox key
+    int n_a;
+    int nsw;               // n_th + n_a
+    double eps;
+};
+
+// launchers (llr_sweep.hip); T = float or double
+template <typename T> void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32_t k1, hipStream_t st);
+template <typename T> void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind,
+                                          uint32_t k0, uint32_t k1, hipStream_t st);
+template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, hipStream_t st);
+template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st);
+template <typename T> void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st);
+template <typename T> void launch_import(const LatTable& lt, int li, T* th, DevState s, const T* in, hipStream_t st);
+void launch_end_sweep(const LatTable& lt, DevState s, int measure, int approach, int with_or, hipStream_t st);
+void launch_replica(const LatTable& lt, DevState s, uint32_t k0, uint32_t k1, hipStream_t st);
+void launch_rm_update(const LatTable& lt, DevState s, RunCfg cfg, hipStream_t st);
+void launch_approach_init(const LatTable& lt, DevState s, hipStream_t st);
+void launch_approach_check(const LatTable& lt, DevState s, hipStream_t st);
+void launch_test_philox(long n, const uint4* ctr, uint32_t k0, uint32_t k1, uint4* out, hipStream_t st);
+template <typename T> void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32_t c1,
+                                                uint32_t c2, uint32_t c3, double* X, int* att, hipStream_t st);
+
+// reconstruction (llr_recon.hip)
+void launch_recon(const double* c, const double* a, int n, double s, double six_v, const double* beta, int nb,
+                  double* lnrho, double* u, double* cv, hipStream_t st);
+void launch_beta_c(const double* c, const double* a, int n, double s, double six_v, double blo, double bhi,
+                   double h, double tol, double* lnrho_scratch, double* out2, hipStream_t st);
+
+// network (llr_mlp.hip)
+constexpr int kMlpH = 64;
+constexpr int kMlpNP = 4417;
+void launch_mlp_init(uint64_t seed, float* w, hipStream_t st);
+void launch_mlp_forward(const float* w, const float* u, const float* invL, int n, int bf16, double* a_out,
+                        hipStream_t st);
+void launch_mlp_loss_grad(const float* w, const float* u, const float* invL, const double* a, int n, int bf16,
+                          float* grad, double* loss, hipStream_t st);
+void launch_mlp_adam(float* w, float* m, float* v, const float* g, int t, float lr, hipStream_t st);
+
+}  // namespace llr

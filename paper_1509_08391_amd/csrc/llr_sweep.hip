@@ -1,0 +1,683 @@
+// llr_sweep.hip -- gfx950 kernels of the energy-restricted LLR sweep for 4D
+// compact U(1) (arXiv:1509.08391, Sec. 2.2 restricted measure, Sec. 3.1 model).
+//
+// Layout: per chain, 2 planes x 8 colours x V/2 angles; colour c = 2 mu + p
+// holds theta_mu at the sites of parity p, indexed by the half index
+// h = s >> 1 of the lexicographic site s.  Links of one colour share no
+// plaquette, so a colour class is updated in one data-parallel pass.
+//
+// A heatbath pass writes every proposal to the non-current plane of its
+// colour, reduces the class Delta E per chain in int64 fixed point
+// (order-independent, deterministic; one fence-free 64-bit atomic per block)
+// and the last block of each chain takes the FP64 interval decision: on accept it flips the chain's current-plane
+// bit, on reject nothing is written back.  An overrelaxation pass maps
+// theta -> -2 phi - theta in place; it leaves every local action unchanged,
+// so it needs neither a reduction nor a decision.
+#include <hip/hip_runtime.h>
+
+#include "llr_internal.hpp"
+
+namespace llr {
+
+enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2 };
+
+__device__ __forceinline__ int find_lat_pass(const LatTable& lt, int b) {
+    int li = 0;
+#pragma unroll 1
+    while (li + 1 < lt.n && b >= lt.l[li + 1].block0) ++li;
+    return li;
+}
+__device__ __forceinline__ int find_lat_site(const LatTable& lt, int b) {
+    int li = 0;
+#pragma unroll 1
+    while (li + 1 < lt.n && b >= lt.l[li + 1].eblock0) ++li;
+    return li;
+}
+
+// coordinates of the site with half index h and parity p
+__device__ __forceinline__ void decode_half(const LatDev& L, uint32_t h, int p, int x[4]) {
+    const uint32_t r1 = L.hL == 1 ? h : fdiv(h, L.mhL);   // ceil(2^32 / 1) does not fit 32 bits
+    const int x0h = (int)(h - r1 * (uint32_t)L.hL);
+    const uint32_t r2 = fdiv(r1, L.mL);
+    x[1] = (int)(r1 - r2 * (uint32_t)L.L);
+    const uint32_t r3 = fdiv(r2, L.mL);
+    x[2] = (int)(r2 - r3 * (uint32_t)L.L);
+    x[3] = (int)r3;
+    x[0] = 2 * x0h + ((p + x[1] + x[2] + x[3]) & 1);
+}
+__device__ __forceinline__ uint32_t half_of(const LatDev& L, int y0, int y1, int y2, int y3) {
+    return (uint32_t)((y0 >> 1) + L.hL * (y1 + L.L * (y2 + L.L * y3)));
+}
+__device__ __forceinline__ int up(int v, int L) { return v + 1 == L ? 0 : v + 1; }
+__device__ __forceinline__ int dn(int v, int L) { return v == 0 ? L - 1 : v - 1; }
+
+template <typename T>
+__device__ __forceinline__ T* chain_base(const LatDev& L, T* th, int cl) {
+    return th + L.base + (long long)cl * 16ll * (long long)L.V2;
+}
+template <typename T>
+__device__ __forceinline__ T* plane_ptr(T* chain, uint64_t curw, int c, uint32_t V2) {
+    return chain + (size_t)((((curw >> (8 * c)) & 1ull) * 8ull) + (uint64_t)c) * V2;
+}
+
+// Local field of link (MU, x): staples of the 2 x 3 plaquettes containing it,
+// each oriented so that theta_MU(x) enters with a plus sign.
+template <typename T, int MU>
+__device__ __forceinline__ void staples(const LatDev& L, T* chain, uint64_t curw, const int x[4], int p,
+                                        uint32_t h, T& C, T& S) {
+    using M = Math<T>;
+    int xm[4] = {x[0], x[1], x[2], x[3]};
+    xm[MU] = up(x[MU], L.L);
+    const uint32_t h_pmu = half_of(L, xm[0], xm[1], xm[2], xm[3]);
+    const int q = p ^ 1;
+    const T* pmu_q = plane_ptr(chain, curw, 2 * MU + q, L.V2);
+    C = T(0);
+    S = T(0);
+#pragma unroll
+    for (int NU = 0; NU < 4; ++NU) {
+        if (NU == MU) continue;
+        const T* pnu_p = plane_ptr(chain, curw, 2 * NU + p, L.V2);
+        const T* pnu_q = plane_ptr(chain, curw, 2 * NU + q, L.V2);
+        int y[4];
+        // x + nu
+        y[0] = x[0]; y[1] = x[1]; y[2] = x[2]; y[3] = x[3];
+        y[NU] = up(x[NU], L.L);
+        const uint32_t h_pnu = half_of(L, y[0], y[1], y[2], y[3]);
+        // x - nu
+        y[NU] = dn(x[NU], L.L);
+        const uint32_t h_mnu = half_of(L, y[0], y[1], y[2], y[3]);
+        // x + mu - nu
+        y[MU] = xm[MU];
+        const uint32_t h_pmu_mnu = half_of(L, y[0], y[1], y[2], y[3]);
+        const T t_nu_pmu = pnu_q[h_pmu];
+        const T t_mu_pnu = pmu_q[h_pnu];
+        const T t_nu_x = pnu_p[h];
+        const T t_nu_pmu_mnu = pnu_p[h_pmu_mnu];
+        const T t_mu_mnu = pmu_q[h_mnu];
+        const T t_nu_mnu = pnu_q[h_mnu];
+        const T sf = t_nu_pmu - t_mu_pnu - t_nu_x;
+        const T sb = t_nu_mnu - t_nu_pmu_mnu - t_mu_mnu;
+        T s1, c1, s2, c2;
+        M::sincos_rad(sf, &s1, &c1);
+        M::sincos_rad(sb, &s2, &c2);
+        C += c1 + c2;
+        S += s1 + s2;
+    }
+}
+
+// Reduce the per-thread fixed-point values of a block; returns the block sum
+// in thread 0.
+__device__ __forceinline__ long long block_sum_i64(long long v) {
+    __shared__ long long part[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    long long tot = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) tot += part[i];
+    }
+    return tot;
+}
+
+// Per-chain reduction without fences: each block adds, in ONE 64-bit atomic,
+// 2^48 (its arrival) plus its partial sum in 2^-24 fixed point (two's
+// complement in the low 48 bits; |sum| < 2^47 for L <= 32).  The block whose
+// addition brings the count to nblocks holds the exact total, order-free.
+__device__ __forceinline__ bool chain_arrive(unsigned long long* acc, long long block_fx40, int nblocks,
+                                             long long* total_fx24) {
+    const long long part = (block_fx40 + (1ll << 15)) >> 16;
+    const unsigned long long add = (1ull << 48) + (unsigned long long)part;
+    const unsigned long long nw = atomicAdd(acc, add) + add;
+    const long long S = ((long long)(nw << 16)) >> 16;
+    const unsigned long long nb = (nw - (unsigned long long)S) >> 48;
+    *total_fx24 = S;
+    return nb == (unsigned long long)nblocks;
+}
+
+// ---------------------------------------------------------------------------
+// Heatbath class pass.  Link conditional ~ exp(a R cos(theta + phi)) with
+// (C, S) the staple sums, R = |C + iS|, phi = arg(C + iS); theta' = X - phi
+// with X ~ von Mises(a R) by Best & Fisher's wrapped-Cauchy envelope in its
+// half-angle form: tan(X/2) = q tan(pi V1 / 2), q = (1 - rho)/(1 + rho).
+// theta' is formed as arg[(cos(pi V1/2) + i q sin(pi V1/2))^2 (C - i S)], and
+// the new local action is R cos X.
+// ---------------------------------------------------------------------------
+template <typename T, int MU>
+__global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
+                                               int kind, uint32_t k0, uint32_t k1) {
+    using M = Math<T>;
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int li = find_lat_pass(lt, b);
+    const LatDev& L = lt.l[li];
+    if (mode == kModeApproach && s.lat_done[li]) return;
+    const int rel = b - L.block0;
+    const int cl = rel / L.bpc;
+    const int tile = rel - cl * L.bpc;
+    const int g = L.chain0 + cl;
+    const int colour = 2 * MU + parity;
+    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
+    T* chain = chain_base(L, th, cl);
+    const uint32_t h = (uint32_t)tile * kBlock + threadIdx.x;
+    const bool active = h < L.V2;
+    const int gi = s.itv[g];
+    const double acoup = mode == kModeApproach ? s.b[g] : s.a[gi];
+    const uint32_t sweep = kind == kApproach ? *s.approach_ctr : *s.sweep_ctr;
+    long long fx = 0;
+    if (active) {
+        int x[4];
+        decode_half(L, h, parity, x);
+        T C, S;
+        staples<T, MU>(L, chain, curw, x, parity, h, C, S);
+        const int own = (int)((curw >> (8 * colour)) & 1ull);
+        const T* pown = chain + (size_t)(own * 8 + colour) * L.V2;
+        T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
+        const T t_old = pown[h];
+        T so, co;
+        M::sincos_rad(t_old, &so, &co);
+        const T eps_old = C * co - S * so;
+        const T R2 = C * C + S * S;
+        const T R = M::sqrt_(R2);
+        const T kap = (T)acoup * R;
+        const T ak = kap < T(0) ? -kap : kap;
+        // Best-Fisher constants in the cancellation-free form
+        T q = T(1), rm1 = T(1), kg2 = T(0);
+        if (ak > T(0)) {
+            const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
+            const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
+            const T irho = M::div_(T(1), rho);
+            rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;              // r - 1
+            const T gg = T(0.5) * (T(1) - rho * rho) * irho;                // sqrt(r^2 - 1)
+            kg2 = ak * gg * gg;
+            q = M::div_(T(1) - rho, T(1) + rho);
+        }
+        const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
+        const uint32_t c3 = (uint32_t)(gi - L.chain0);
+        uint4 w = make_uint4(0, 0, 0, 0);
+        T ch = T(1), sh = T(0);
+        bool got = false;
+        for (int j = 0; j < kVmCap; ++j) {
+            if ((j & 1) == 0) w = philox10(make_uint4(h, c1base | (uint32_t)(j >> 1), sweep, c3), k0, k1);
+            const uint32_t wa = (j & 1) ? w.z : w.x;
+            const uint32_t wb = (j & 1) ? w.w : w.y;
+            const T V1 = M::sunif(wa);
+            T s_, c_;
+            M::sincos_halfpi(V1, &s_, &c_);
+            if (ak == T(0)) { ch = c_; sh = s_; got = true; break; }
+            const T U2 = M::unif(wb);
+            const T cc = M::div_(kg2, rm1 + T(2) * c_ * c_);   // kappa (r^2-1)/(r+z), z = cos(pi V1)
+            bool acc = cc * (T(2) - cc) - U2 > T(0);
+            if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
+            if (acc) { ch = c_; sh = q * s_; got = true; break; }
+        }
+        T t_new = t_old;
+        T dE = T(0);
+        if (got) {
+            T er = ch * ch - sh * sh, ei = T(2) * ch * sh;
+            const T nrm = ch * ch + sh * sh;
+            if (kap < T(0)) { er = -er; ei = -ei; }
+            T pr = C, pi = -S;
+            if (R2 == T(0)) { pr = T(1); pi = T(0); }
+            const T zr = er * pr - ei * pi, zi = er * pi + ei * pr;
+            t_new = M::atan2_(zi, zr);
+            if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
+            dE = M::div_(R * er, nrm) - eps_old;
+        }
+        palt[h] = t_new;
+        fx = __double2ll_rn((double)dE * kFix);
+    }
+    const long long tot = block_sum_i64(fx);
+    long long total = 0;
+    if (threadIdx.x == 0 && chain_arrive(s.acc + g, tot, L.bpc, &total)) {
+        {
+            const double E0 = s.E[g];
+            const double En = E0 + (double)total * kFix24Inv;
+            const double lo = s.lo[gi], hi = s.hi[gi];
+            bool acc;
+            if (mode == kModeRestricted) {
+                acc = En >= lo && En <= hi;
+            } else if (mode == kModeApproach) {
+                const double d0 = fmax(0.0, fmax(lo - E0, E0 - hi));
+                const double d1 = fmax(0.0, fmax(lo - En, En - hi));
+                acc = d1 <= d0;
+                const double cen = s.cen[gi];
+                const int sg = cen > En ? 1 : (cen < En ? -1 : 0);
+                double eta = s.eta[g];
+                const int sp = s.sprev[g];
+                if (sp != 0 && sg != 0) eta = sg == sp ? fmin(0.05, 1.2 * eta) : fmax(1e-6, 0.5 * eta);
+                s.eta[g] = eta;
+                s.b[g] = fmin(4.0, fmax(0.0, s.b[g] + eta * (double)sg));
+                s.sprev[g] = sg;
+            } else {
+                acc = true;
+            }
+            if (acc) {
+                s.cur[8 * g + colour] ^= (uint8_t)1;
+                s.E[g] = En;
+                s.bits[g] |= (uint16_t)(1u << colour);
+                s.hb_acc[g] += 1ull;
+            }
+            s.hb_prop[g] += 1ull;
+            atomicExch(s.acc + g, 0ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Overrelaxation class pass: theta' = arg[(C - i S)^2 e^{-i theta}] = -2 phi - theta.
+// ---------------------------------------------------------------------------
+template <typename T, int MU>
+__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity) {
+    using M = Math<T>;
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int li = find_lat_pass(lt, b);
+    const LatDev& L = lt.l[li];
+    const int rel = b - L.block0;
+    const int cl = rel / L.bpc;
+    const int tile = rel - cl * L.bpc;
+    const int g = L.chain0 + cl;
+    const int colour = 2 * MU + parity;
+    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
+    T* chain = chain_base(L, th, cl);
+    const uint32_t h = (uint32_t)tile * kBlock + threadIdx.x;
+    if (h < L.V2) {
+        int x[4];
+        decode_half(L, h, parity, x);
+        T C, S;
+        staples<T, MU>(L, chain, curw, x, parity, h, C, S);
+        T* pown = plane_ptr(chain, curw, colour, L.V2);
+        const T t_old = pown[h];
+        T t_new;
+        if (C == T(0) && S == T(0)) {
+            t_new = -t_old;
+        } else {
+            T so, co;
+            M::sincos_rad(t_old, &so, &co);
+            const T ar = C * C - S * S, ai = T(-2) * C * S;   // (C - iS)^2
+            const T zr = ar * co + ai * so;                    // times (cos - i sin)
+            const T zi = ai * co - ar * so;
+            t_new = M::atan2_(zi, zr);
+        }
+        if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
+        pown[h] = t_new;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full FP64 energy: E = sum_{x, mu<nu} cos theta_{mu nu}(x), one thread per site.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restrict__ th, DevState s) {
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int li = find_lat_site(lt, b);
+    const LatDev& L = lt.l[li];
+    const int rel = b - L.eblock0;
+    const int cl = rel / L.ebpc;
+    const int tile = rel - cl * L.ebpc;
+    const int g = L.chain0 + cl;
+    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
+    const T* chain = chain_base(L, const_cast<T*>(th), cl);
+    const uint32_t sl = (uint32_t)tile * kBlock + threadIdx.x;
+    long long fx = 0;
+    if (sl < 2u * L.V2) {
+        const int p = sl >= L.V2 ? 1 : 0;
+        const uint32_t h = sl - (uint32_t)p * L.V2;
+        int x[4];
+        decode_half(L, h, p, x);
+        double own[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) own[m] = (double)plane_ptr(chain, curw, 2 * m + p, L.V2)[h];
+        uint32_t hup[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[m] = up(x[m], L.L);
+            hup[m] = half_of(L, y[0], y[1], y[2], y[3]);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const double t_nu_pmu = (double)plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2)[hup[mu]];
+                const double t_mu_pnu = (double)plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2)[hup[nu]];
+                const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
+                fx += __double2ll_rn(cos(ang) * kFix);
+            }
+    }
+    const long long tot = block_sum_i64(fx);
+    long long total = 0;
+    if (threadIdx.x == 0 && chain_arrive(s.eacc + g, tot, L.ebpc, &total)) {
+        s.E[g] = (double)total * kFix24Inv;
+        atomicExch(s.eacc + g, 0ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hot start: theta = -pi + 2 pi U (kind 1, w0 = mu V + s, w3 = chain index),
+// computed in FP64 with one fused multiply-add and rounded to the precision.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_hot_start(LatTable lt, T* __restrict__ th, DevState s, uint32_t k0,
+                                                      uint32_t k1) {
+    const int b = (int)blockIdx.x;
+    const int li = find_lat_site(lt, b);
+    const LatDev& L = lt.l[li];
+    const int rel = b - L.eblock0;
+    const int cl = rel / L.ebpc;
+    const int tile = rel - cl * L.ebpc;
+    const int g = L.chain0 + cl;
+    T* chain = chain_base(L, th, cl);
+    const uint32_t V = 2u * L.V2;
+    const uint32_t sidx = (uint32_t)tile * kBlock + threadIdx.x;   // lexicographic site
+    if (sidx < V) {
+        const uint32_t r1 = fdiv(sidx, L.mL);
+        const int x0 = (int)(sidx - r1 * (uint32_t)L.L);
+        const uint32_t r2 = fdiv(r1, L.mL);
+        const int x1 = (int)(r1 - r2 * (uint32_t)L.L);
+        const uint32_t r3 = fdiv(r2, L.mL);
+        const int x2 = (int)(r2 - r3 * (uint32_t)L.L);
+        const int x3 = (int)r3;
+        const int p = (x0 + x1 + x2 + x3) & 1;
+        const uint32_t h = sidx >> 1;
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint4 w = philox10(make_uint4((uint32_t)mu * V + sidx, ctr1_word(0, 0, kInit, (uint32_t)L.lat_id), 0u,
+                                                (uint32_t)cl),
+                                     k0, k1);
+            const double u = Math<T>::f32 ? ((double)(w.x >> 9) + 0.5) * 0x1p-23 : ((double)w.x + 0.5) * 0x1p-32;
+            const double t = __fma_rn(6.28318530717958647692, u, -3.14159265358979323846);
+            chain[(size_t)(2 * mu + p) * L.V2 + h] = (T)t;
+        }
+    }
+    if (threadIdx.x == 0 && tile == 0) {
+        *reinterpret_cast<uint64_t*>(s.cur + 8 * g) = 0ull;
+        s.itv[g] = g;
+        s.conf[g] = g;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_export(LatDev L, const T* __restrict__ th, DevState s, T* __restrict__ out) {
+    const long long V = 2ll * L.V2;
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;   // over chains x 4 x V
+    if (i >= (long long)L.n_chains * 4 * V) return;
+    const int cl = (int)(i / (4 * V));
+    const long long r = i - (long long)cl * 4 * V;
+    const int mu = (int)(r / V);
+    const uint32_t sidx = (uint32_t)(r - (long long)mu * V);
+    const uint32_t r1 = fdiv(sidx, L.mL);
+    const int x0 = (int)(sidx - r1 * (uint32_t)L.L);
+    const uint32_t r2 = fdiv(r1, L.mL);
+    const int x1 = (int)(r1 - r2 * (uint32_t)L.L);
+    const uint32_t r3 = fdiv(r2, L.mL);
+    const int x2 = (int)(r2 - r3 * (uint32_t)L.L);
+    const int p = (x0 + x1 + x2 + (int)r3) & 1;
+    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * (L.chain0 + cl));
+    const T* chain = chain_base(L, const_cast<T*>(th), cl);
+    out[i] = plane_ptr(chain, curw, 2 * mu + p, L.V2)[sidx >> 1];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_import(LatDev L, T* __restrict__ th, DevState s, const T* __restrict__ in) {
+    const long long V = 2ll * L.V2;
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (long long)L.n_chains * 4 * V) return;
+    const int cl = (int)(i / (4 * V));
+    const long long r = i - (long long)cl * 4 * V;
+    const int mu = (int)(r / V);
+    const uint32_t sidx = (uint32_t)(r - (long long)mu * V);
+    const uint32_t r1 = fdiv(sidx, L.mL);
+    const int x0 = (int)(sidx - r1 * (uint32_t)L.L);
+    const uint32_t r2 = fdiv(r1, L.mL);
+    const int x1 = (int)(r1 - r2 * (uint32_t)L.L);
+    const uint32_t r3 = fdiv(r2, L.mL);
+    const int x2 = (int)(r2 - r3 * (uint32_t)L.L);
+    const int p = (x0 + x1 + x2 + (int)r3) & 1;
+    T* chain = chain_base(L, th, cl);
+    chain[(size_t)(2 * mu + p) * L.V2 + (sidx >> 1)] = in[i];
+    if (r == 0) {
+        const int g = L.chain0 + cl;
+        *reinterpret_cast<uint64_t*>(s.cur + 8 * g) = 0ull;
+        s.itv[g] = g;
+        s.conf[g] = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-sweep bookkeeping (one block): accumulate the measured energy of every
+// interval, move the accept bits to the log, advance the sweep counter.
+// ---------------------------------------------------------------------------
+// Overrelaxation passes are always accepted (E unchanged): their bits 8..15
+// are set here for sweeps that ran them.
+__global__ __launch_bounds__(1024) void k_end_sweep(int n, DevState s, int measure, int approach, int with_or) {
+    const long long row = s.bits_row ? *s.bits_row : 0;
+    for (int g = threadIdx.x; g < n; g += blockDim.x) {
+        if (measure) s.sumE[s.itv[g]] += s.E[g];
+        const uint16_t bits = (uint16_t)(s.bits[g] | (with_or ? 0xff00u : 0u));
+        if (s.bits_log && row < s.bits_rows_max) s.bits_log[row * n + g] = bits;
+        s.bits_last[g] = bits;
+        s.bits[g] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (approach) *s.approach_ctr += 1u;
+        else *s.sweep_ctr += 1u;
+        if (s.bits_row) *s.bits_row = row + 1;
+    }
+}
+
+// Replica exchange (Sec. 2.5) between intervals k and k+1 of one lattice, for
+// k = t (mod 2) at sweep t; eligible iff each configuration lies in the other
+// interval; accepted with min(1, exp[(a_k - a_{k+1})(E_{k+1} - E_k)]).  Only
+// the chain <-> interval labels move.
+__global__ __launch_bounds__(1024) void k_replica(LatTable lt, DevState s, uint32_t k0, uint32_t k1) {
+    const uint32_t t = *s.sweep_ctr;
+    unsigned long long prop = 0, accd = 0;
+    for (int li = 0; li < lt.n; ++li) {
+        const LatDev& L = lt.l[li];
+        const int npair = (L.n_chains - (int)(t & 1u)) / 2;
+        for (int i = threadIdx.x; i < npair; i += blockDim.x) {
+            const int k = 2 * i + (int)(t & 1u);
+            if (k + 1 >= L.n_chains) continue;
+            const int kg = L.chain0 + k;
+            const int A = s.conf[kg], B = s.conf[kg + 1];
+            const double EA = s.E[A], EB = s.E[B];
+            if (!(EA >= s.lo[kg + 1] && EA <= s.hi[kg + 1] && EB >= s.lo[kg] && EB <= s.hi[kg])) continue;
+            const uint4 w = philox10(make_uint4((uint32_t)k, ctr1_word(0, 0, kReplica, (uint32_t)L.lat_id), t, 0u), k0, k1);
+            const double u = ((double)w.x + 0.5) * 0x1p-32;
+            const double xx = (s.a[kg] - s.a[kg + 1]) * (EB - EA);
+            ++prop;
+            if (xx >= 0.0 || u < exp(xx)) {
+                s.conf[kg] = B;
+                s.conf[kg + 1] = A;
+                s.itv[A] = kg + 1;
+                s.itv[B] = kg;
+                ++accd;
+            }
+        }
+    }
+    if (prop) atomicAdd(s.re_cnt, prop);
+    if (accd) atomicAdd(s.re_cnt + 1, accd);
+}
+
+// Robbins-Monro step of every interval (eq. (kk21), Algorithm 1 sign):
+// a^(n+1) = a^(n) - 12 (mean - c_k) / ((n + 1) w^2).
+__global__ __launch_bounds__(1024) void k_rm_update(int n, DevState s, RunCfg cfg) {
+    const int it = *s.rm_iter;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const double mean = s.sumE[k] / (double)cfg.n_a;
+        const double a0 = s.a[k];
+        const double wk = s.w[k];
+        const double an = a0 - 12.0 * (mean - s.cen[k]) / ((double)(it + 1) * wk * wk);
+        const double da = an - a0;
+        s.a[k] = an;
+        s.a_hist[(long long)(it + 1) * n + k] = an;
+        if (s.conv_iter[k] < 0 && fabs(da) < cfg.eps) {
+            s.conv_iter[k] = it;
+            s.conv_sweeps[k] = (long long)(it + 1) * cfg.nsw;   // approach sweeps added on the host
+        }
+        s.sumE[k] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *s.rm_iter = it + 1;
+}
+
+__global__ __launch_bounds__(1024) void k_approach_init(int n, DevState s) {
+    for (int g = threadIdx.x; g < n; g += blockDim.x) {
+        s.b[g] = s.a[s.itv[g]];
+        s.eta[g] = 0.05;
+        s.sprev[g] = 0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_approach_check(LatTable lt, DevState s) {
+    __shared__ int outside[kMaxLat];
+    if (threadIdx.x < kMaxLat) outside[threadIdx.x] = 0;
+    __syncthreads();
+    for (int li = 0; li < lt.n; ++li) {
+        const LatDev& L = lt.l[li];
+        for (int c = threadIdx.x; c < L.n_chains; c += blockDim.x) {
+            const int g = L.chain0 + c;
+            const int k = s.itv[g];
+            const double E = s.E[g];
+            if (!(E >= s.lo[k] && E <= s.hi[k])) atomicAdd(&outside[li], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)lt.n) s.lat_outside[threadIdx.x] = outside[threadIdx.x];
+}
+
+__global__ void k_test_philox(long n, const uint4* __restrict__ ctr, uint32_t k0, uint32_t k1, uint4* __restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox10(ctr[i], k0, k1);
+}
+
+// Stand-alone draws of the heatbath sampler (same arithmetic as k_hb).
+template <typename T>
+__global__ void k_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3,
+                                double* X, int* att) {
+    using M = Math<T>;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T ak = (T)kappa;
+    T q = T(1), rm1 = T(1), kg2 = T(0);
+    if (ak > T(0)) {
+        const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
+        const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
+        const T irho = M::div_(T(1), rho);
+        rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;
+        const T gg = T(0.5) * (T(1) - rho * rho) * irho;
+        kg2 = ak * gg * gg;
+        q = M::div_(T(1) - rho, T(1) + rho);
+    }
+    uint4 w = make_uint4(0, 0, 0, 0);
+    int a = 0;
+    T ch = T(1), sh = T(0);
+    for (int j = 0; j < kVmCap; ++j) {
+        if ((j & 1) == 0) w = philox10(make_uint4((uint32_t)i, c1 | (uint32_t)(j >> 1), c2, c3), k0, k1);
+        const uint32_t wa = (j & 1) ? w.z : w.x;
+        const uint32_t wb = (j & 1) ? w.w : w.y;
+        const T V1 = M::sunif(wa);
+        T s_, c_;
+        M::sincos_halfpi(V1, &s_, &c_);
+        if (ak == T(0)) { ch = c_; sh = s_; a = j + 1; break; }
+        const T U2 = M::unif(wb);
+        const T cc = M::div_(kg2, rm1 + T(2) * c_ * c_);
+        bool acc = cc * (T(2) - cc) - U2 > T(0);
+        if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
+        if (acc) { ch = c_; sh = q * s_; a = j + 1; break; }
+    }
+    att[i] = a;
+    X[i] = a ? 2.0 * (double)M::atan2_(sh, ch) : 0.0;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32_t k1, hipStream_t st) {
+    hipLaunchKernelGGL(k_hot_start<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, k0, k1);
+}
+
+template <typename T>
+void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
+                    hipStream_t st) {
+    const int p = colour & 1;
+    dim3 gr(lt.pass_blocks), bl(kBlock);
+    switch (colour >> 1) {
+        case 0: hipLaunchKernelGGL((k_hb<T, 0>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 1: hipLaunchKernelGGL((k_hb<T, 1>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 2: hipLaunchKernelGGL((k_hb<T, 2>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        default: hipLaunchKernelGGL((k_hb<T, 3>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+    }
+}
+
+template <typename T>
+void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, hipStream_t st) {
+    const int p = colour & 1;
+    dim3 gr(lt.pass_blocks), bl(kBlock);
+    switch (colour >> 1) {
+        case 0: hipLaunchKernelGGL((k_or<T, 0>), gr, bl, 0, st, lt, th, s, p); break;
+        case 1: hipLaunchKernelGGL((k_or<T, 1>), gr, bl, 0, st, lt, th, s, p); break;
+        case 2: hipLaunchKernelGGL((k_or<T, 2>), gr, bl, 0, st, lt, th, s, p); break;
+        default: hipLaunchKernelGGL((k_or<T, 3>), gr, bl, 0, st, lt, th, s, p); break;
+    }
+}
+
+template <typename T>
+void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
+}
+
+template <typename T>
+void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st) {
+    const LatDev& L = lt.l[li];
+    const long long n = (long long)L.n_chains * 8ll * L.V2;
+    hipLaunchKernelGGL(k_export<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, L, th, s, out);
+}
+
+template <typename T>
+void launch_import(const LatTable& lt, int li, T* th, DevState s, const T* in, hipStream_t st) {
+    const LatDev& L = lt.l[li];
+    const long long n = (long long)L.n_chains * 8ll * L.V2;
+    hipLaunchKernelGGL(k_import<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, L, th, s, in);
+}
+
+void launch_end_sweep(const LatTable& lt, DevState s, int measure, int approach, int with_or, hipStream_t st) {
+    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(1024), 0, st, lt.n_chains, s, measure, approach, with_or);
+}
+void launch_replica(const LatTable& lt, DevState s, uint32_t k0, uint32_t k1, hipStream_t st) {
+    hipLaunchKernelGGL(k_replica, dim3(1), dim3(1024), 0, st, lt, s, k0, k1);
+}
+void launch_rm_update(const LatTable& lt, DevState s, RunCfg cfg, hipStream_t st) {
+    hipLaunchKernelGGL(k_rm_update, dim3(1), dim3(1024), 0, st, lt.n_chains, s, cfg);
+}
+void launch_approach_init(const LatTable& lt, DevState s, hipStream_t st) {
+    hipLaunchKernelGGL(k_approach_init, dim3(1), dim3(1024), 0, st, lt.n_chains, s);
+}
+void launch_approach_check(const LatTable& lt, DevState s, hipStream_t st) {
+    hipLaunchKernelGGL(k_approach_check, dim3(1), dim3(1024), 0, st, lt, s);
+}
+void launch_test_philox(long n, const uint4* ctr, uint32_t k0, uint32_t k1, uint4* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_test_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, ctr, k0, k1, out);
+}
+template <typename T>
+void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3,
+                          double* X, int* att, hipStream_t st) {
+    hipLaunchKernelGGL(k_test_vonmises<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, kappa, k0, k1, c1,
+                       c2, c3, X, att);
+}
+
+#define LLR_INST(T)                                                                                              \
+    template void launch_hot_start<T>(const LatTable&, T*, DevState, uint32_t, uint32_t, hipStream_t);          \
+    template void launch_hb_pass<T>(const LatTable&, T*, DevState, int, int, int, uint32_t, uint32_t, hipStream_t); \
+    template void launch_or_pass<T>(const LatTable&, T*, DevState, int, hipStream_t);                           \
+    template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t);                          \
+    template void launch_export<T>(const LatTable&, int, const T*, DevState, T*, hipStream_t);                 \
+    template void launch_import<T>(const LatTable&, int, T*, DevState, const T*, hipStream_t);                 \
+    template void launch_test_vonmises<T>(long, double, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double*, \
+                                          int*, hipStream_t);
+LLR_INST(float)
+LLR_INST(double)
+#undef LLR_INST
+
+}  // namespace llr

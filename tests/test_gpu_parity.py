@@ -1,0 +1,423 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same
+seeded inputs and Philox counters.
+
+Bars: integer work (Philox words, sampler attempt counts, accept bits, chain
+<-> interval labels) bit-exact; FP64 angles within 1e-12 after one sweep
+(circular distance), energies within 1e-9 relative, every a_k^(n) within 1e-6
+over driver runs shorter than the divergence horizon; FP32 angles within 1e-5
+of the FP64 oracle run on the same FP32 state with the same 23-bit uniforms,
+except links the oracle flags (sampler-test margin < 1e-5 or staple modulus
+< 1e-4).  With fixed random numbers the update map amplifies last-bit
+differences about 5x per sweep, so two independent FP64 implementations part
+after ~15 sweeps; full runs are compared as distributions over seeds."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.inputs import circ_dist, random_state
+
+pytestmark = pytest.mark.gpu
+
+SEED = 1509083910
+
+
+@pytest.fixture(scope="module")
+def llr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1509_08391_amd import llr as m
+    m.lib()
+    return m
+
+
+def _ctx(llr, prec, lattices, a=1.0, **params):
+    """a: one value for every interval, or a list with one entry (scalar or
+    per-interval array) per lattice."""
+    ctx = llr.Context(precision=prec, device=0)
+    p = dict(seed=SEED)
+    p.update(params)
+    ctx.set_params(**p)
+    for (L, E_low, dE) in lattices:
+        ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    for i, (L, E_low, dE) in enumerate(lattices):
+        ctx.set_a(i, a if np.ndim(a) == 0 else a[i])
+    return ctx
+
+
+def test_philox_bit_exact(llr):
+    ctx = llr.Context(precision=llr.FP64)
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(200000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:10] = 0
+    ctr[10:20] = 0xFFFFFFFF
+    for seed in (0, SEED, (1 << 64) - 1):
+        assert np.array_equal(ctx.test_philox(ctr, seed), oracle.philox(ctr, seed))
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.3, 2.0, 5.0, 12.0])
+def test_vonmises_fp64_matches_oracle(llr, kappa):
+    ctx = llr.Context(precision=llr.FP64)
+    n = 100000
+    c1 = oracle.ctr1(colour=3, kind=0, lattice_id=1)
+    X, att = ctx.test_vonmises(n, kappa, SEED, c1, 17, 5)
+    Xo, atto, _ = oracle.vonmises(n, kappa, SEED, c1, 17, 5)
+    assert np.array_equal(att, atto)
+    assert np.max(np.abs(X - Xo)) < 1e-12
+
+
+@pytest.mark.parametrize("kappa", [0.3, 2.0, 5.0, 12.0])
+def test_vonmises_fp32_matches_oracle(llr, kappa):
+    ctx = llr.Context(precision=llr.FP32)
+    n = 100000
+    X, att = ctx.test_vonmises(n, kappa, SEED, 0, 3, 9)
+    Xo, atto, mg = oracle.vonmises(n, kappa, SEED, 0, 3, 9, u24=True)
+    flag = mg < 1e-5
+    assert np.array_equal(att[~flag], atto[~flag])
+    ok = (~flag) & (att == atto)
+    assert np.max(np.abs(X[ok] - Xo[ok])) < 1e-5
+    assert flag.sum() < 1e-3 * n
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+@pytest.mark.parametrize("L,n", [(2, 2), (4, 3), (6, 2), (8, 2)])
+def test_hot_start_and_energy(llr, prec, L, n):
+    f32 = prec == "FP32"
+    E_low = np.arange(n) * 10.0
+    ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, 10.0)])
+    ctx.hot_start()
+    th = ctx.export_state(0).cpu().numpy().astype(np.float64)
+    ref = oracle.hot_start(4, L, n, SEED, lattice_id=0, f32=f32)
+    assert np.array_equal(th, ref)
+    E, conf = ctx.get_energy(0)
+    Eref = np.array([oracle.energy(4, L, ref[i]) for i in range(n)])
+    assert np.max(np.abs(E - Eref)) < 1e-9 * 6 * L ** 4
+    assert np.array_equal(conf, np.arange(n))
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 10])
+def test_one_sweep_fp64(llr, L):
+    """One restricted sweep from the same state: angles within 1e-12, accept
+    bits identical; then three more sweeps: bits still identical, angles
+    within 1e-9 (last-bit differences grow ~5x per sweep)."""
+    import torch
+    d, n = 4, 3
+    th = random_state(d, L, n, seed=L * 7 + 1, u_target=0.6)
+    for k in range(n):
+        E0 = oracle.energy(d, L, th[k])
+        width = max(6.0, 0.3 * np.sqrt(6 * L ** 4))
+        lo = E0 - (0.2 + 0.25 * k) * width
+        a = 0.95 + 0.05 * k
+        ctx = _ctx(llr, llr.FP64, [(L, [lo], width)], a=[a])
+        ctx.import_state(0, torch.from_numpy(th[k:k + 1].copy()))
+        tr = th[k:k + 1].copy()
+        Er = np.array([E0])
+        for (n_sw, s0, tol) in [(1, 11, 1e-12), (3, 12, 1e-6)]:
+            bits = ctx.sweeps(n_sw, sweep0=s0)
+            got = ctx.export_state(0).cpu().numpy()
+            Eg, _ = ctx.get_energy(0)
+            Er, br = oracle.sweeps(d, L, tr, [a], [lo], [lo + width], [0], Er, n_sw, s0, seed=SEED)
+            assert np.array_equal(bits[:, 0].astype(np.int64), br[:, 0].astype(np.int64)), (bits, br)
+            assert np.max(circ_dist(got, tr)) < tol
+            assert abs(Eg[0] - Er[0]) < 1e-9 * abs(Er[0])
+        ctx.recompute_energy()
+        Eg2, _ = ctx.get_energy(0)
+        assert abs(Eg2[0] - oracle.energy(d, L, tr[0])) < 1e-9 * abs(Er[0])
+        ctx.close()
+
+
+def test_one_sweep_fp64_batched_chains_and_lattices(llr):
+    """Several chains per lattice and two lattice sizes in one launch."""
+    import torch
+    d = 4
+    cases = []
+    for (L, n, s) in [(4, 5, 3), (6, 4, 5)]:
+        th = random_state(d, L, n, seed=s, u_target=0.62)
+        E = np.array([oracle.energy(d, L, th[i]) for i in range(n)])
+        # one interval per chain: contiguous grid wide enough to hold each chain
+        dE = 0.02 * 6 * L ** 4
+        E_low = np.floor((E.min() - 0.5 * dE)) + dE * np.arange(n)
+        # re-assign: chain k must sit in interval k -> move energies by choosing states per interval
+        cases.append((L, n, th, E, E_low, dE))
+    ctx = _ctx(llr, llr.FP64, [(c[0], c[4], c[5]) for c in cases], a=1.0)
+    for i, c in enumerate(cases):
+        ctx.set_a(i, np.linspace(0.9, 1.1, c[1]))
+    for i, c in enumerate(cases):
+        ctx.import_state(i, torch.from_numpy(c[2]))
+    bits = ctx.sweeps(2, sweep0=0, mode=llr.MODE_FREE)
+    col = 0
+    for i, (L, n, th, E, E_low, dE) in enumerate(cases):
+        got = ctx.export_state(i).cpu().numpy()
+        Eg, _ = ctx.get_energy(i)
+        tr = th.copy()
+        Er, br = oracle.sweeps(d, L, tr, np.linspace(0.9, 1.1, n), E_low, E_low + dE, np.arange(n), E, 2, 0,
+                               mode=oracle.MODE_FREE, seed=SEED, lattice_id=i)
+        assert np.array_equal(bits[:, col:col + n].astype(np.int64), br.astype(np.int64))
+        assert np.max(circ_dist(got, tr)) < 1e-11
+        assert np.max(np.abs(Eg - Er) / np.abs(Er)) < 1e-9
+        col += n
+
+
+def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep):
+    """One FP32-state sweep of one chain by the oracle, pass by pass, returning
+    the set of links whose result is ill-conditioned (sampler margin < 1e-5 or
+    small staple modulus) together with the links sharing a plaquette later."""
+    V = L ** d
+    flagged = np.zeros((d, V), dtype=bool)
+    par = np.array([sum((s // L ** m) % L for m in range(d)) % 2 for s in range(V)])
+    for col in range(2 * d):
+        acc, E, dE, mg = oracle.class_pass(d, L, th, 1, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED,
+                                           sweep=sweep, interval=0, f32=True, want_margin=True)
+        mu, p = col >> 1, col & 1
+        idx = np.nonzero(par == p)[0]
+        flagged[mu, idx[mg < 1e-5]] = True
+    for col in range(2 * d):
+        oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
+    return E, flagged
+
+
+@pytest.mark.parametrize("L", [4, 8])
+def test_one_sweep_fp32_against_fp64_oracle(llr, L):
+    import torch
+    d, n = 4, 3
+    th = random_state(d, L, n, seed=L + 100, u_target=0.6, dtype=np.float32).astype(np.float64)
+    n_flag_total = 0
+    for k in range(n):
+        E0 = oracle.energy(d, L, th[k])
+        width = 0.03 * 6 * L ** 4
+        lo = E0 - 0.45 * width
+        ctx = _ctx(llr, llr.FP32, [(L, [lo], width)], a=np.array([1.0]))
+        ctx.import_state(0, torch.from_numpy(th[k:k + 1].astype(np.float32)))
+        bits = ctx.sweeps(1, sweep0=5)
+        got = ctx.export_state(0).cpu().numpy().astype(np.float64)
+        Eg, _ = ctx.get_energy(0)
+        tr = th[k].copy()
+        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, 1.0, lo, lo + width, E0, 5)
+        dist = circ_dist(got[0], tr)
+        n_flag_total += int(flagged.sum())
+        if flagged.sum() == 0:
+            assert dist.max() < 1e-5, dist.max()
+            assert abs(Eg[0] - Er) < 1e-3 * max(1.0, np.sqrt(L ** 4))
+        else:
+            assert np.median(dist) < 1e-6
+        ctx.close()
+    assert n_flag_total <= 3
+
+
+def _states_in_intervals(L, E_low, dE, seed):
+    """One synthetic state per interval whose energy lies inside it (drawn by
+    the input generator, energy by the oracle)."""
+    d = 4
+    V6 = 6 * L ** 4
+    out = []
+    rng = np.random.default_rng(seed)
+    for k, e in enumerate(E_low):
+        c = e + 0.5 * dE
+        for attempt in range(400):
+            th = random_state(d, L, 1, seed=int(rng.integers(1 << 30)), u_target=float(np.clip(c / V6, 0.05, 0.95)))
+            E = oracle.energy(d, L, th[0])
+            if abs(E - c) < 0.3 * dE:
+                out.append(th[0])
+                break
+        else:
+            raise RuntimeError("no state found for interval %d" % k)
+    return np.ascontiguousarray(np.array(out))
+
+
+@pytest.mark.parametrize("replica", [False, True])
+def test_driver_short_run_fp64(llr, replica):
+    """Every driver step inside the divergence horizon: N_TH = 1, N_A = 2,
+    N_RM = 3 from states inside their intervals, recompute every 2 sweeps,
+    replica exchange after every sweep: accept bits, chain <-> interval
+    labels identical to the oracle, every a_k^(n) within 1e-6 (the angles
+    part at ~1e-9 .. 1e-6 by the ninth sweep)."""
+    import torch
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.55 * V6 + dE * np.arange(8)
+    th = _states_in_intervals(L, E_low, dE, seed=5)
+    a0 = np.linspace(0.95, 1.1, 8)
+    ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a0], n_th=1, n_a=2, n_rm=3, recompute_every=2,
+               replica_exchange=replica)
+    ctx.enable_bits_log(100)
+    ctx.import_state(0, torch.from_numpy(th))
+    ctx.run()
+    a, it, sw = ctx.get_a(0)
+    hist = ctx.get_history(0)
+    E, conf = ctx.get_energy(0)
+    bits = ctx.get_bits_log()
+    _, _, re_prop, re_acc = ctx.stats()
+    r = oracle.llr_run(d, L, E_low, dE, a0, n_th=1, n_a=2, n_rm=3, seed=SEED, recompute_every=2,
+                       replica_exchange=replica, theta=th, record_bits=True, approach_cap=0)
+    assert r["approach_sweeps"] == 0
+    assert np.array_equal(bits.astype(np.int64), r["bits"].astype(np.int64))
+    assert np.array_equal(conf, r["conf"])
+    assert np.max(np.abs(hist - r["a_hist"])) < 1e-6
+    assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-8
+    assert np.array_equal(it, r["conv_iter"])
+    if replica:
+        assert (re_prop, re_acc) == (int(r["re"][0]), int(r["re"][1]))
+        assert re_prop > 0
+
+
+def test_approach_parity_fp64(llr):
+    """Hot start and approach (heatbath-only, adaptive coupling) of the L=4
+    interval set over u in [0.5, 0.7]: same number of approach sweeps, same
+    accept bits, every chain inside its interval."""
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.5 * V6 + dE * np.arange(8)
+    ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], n_th=1, n_a=1, n_rm=1, recompute_every=5, approach_cap=2000)
+    ctx.enable_bits_log(3000)
+    ctx.hot_start()
+    ap = ctx.approach()
+    bits = ctx.get_bits_log()
+    E, conf = ctx.get_energy(0)
+    r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=1, n_a=1, n_rm=1, seed=SEED, recompute_every=5,
+                       approach_cap=2000, record_bits=True)
+    n_ap = r["approach_sweeps"]
+    assert int(ap[0]) == n_ap
+    assert np.array_equal(bits[:n_ap].astype(np.int64), r["bits"][:n_ap].astype(np.int64))
+    assert np.all((E >= E_low) & (E <= E_low + dE))
+
+
+def test_driver_mixed_lattices_fp64(llr):
+    """L=4 and L=6 chains batched in one launch; each lattice against its own
+    oracle run (lattice id in the Philox counter)."""
+    import torch
+    d = 4
+    lats = []
+    for L, n in [(4, 4), (6, 3)]:
+        V6 = 6 * L ** 4
+        dE = 0.02 * V6
+        E_low = 0.58 * V6 + dE * np.arange(n)
+        lats.append((L, E_low, dE, _states_in_intervals(L, E_low, dE, seed=L)))
+    ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=1, n_a=2, n_rm=2, recompute_every=3)
+    for i, x in enumerate(lats):
+        ctx.import_state(i, torch.from_numpy(x[3]))
+    ctx.run()
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=1, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
+                           lattice_id=i, theta=th, approach_cap=0)
+        a, it, sw = ctx.get_a(i)
+        assert np.max(np.abs(a - r["a"])) < 1e-6
+        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-5
+
+
+@pytest.mark.slow
+def test_full_run_config0_statistical_fp64_and_fp32(llr):
+    """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
+    dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start).  Beyond
+    ~15 sweeps the two implementations follow different trajectories, so the
+    final a_k are compared as distributions over 4 seeds: means agree within
+    4 combined standard errors, for the FP64 and the FP32 GPU path."""
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.5 * V6 + dE * np.arange(8)
+    seeds = [SEED + 17 * i for i in range(4)]
+    res = {}
+    for prec in ("FP64", "FP32"):
+        A = []
+        for sd in seeds:
+            ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)], seed=sd, n_th=100, n_a=100, n_rm=20,
+                       approach_cap=20000)
+            ctx.hot_start()
+            ctx.approach()
+            ctx.run()
+            A.append(ctx.get_a(0)[0])
+            ctx.close()
+        res[prec] = np.array(A)
+    O = np.array([oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd,
+                                 approach_cap=20000)["a"] for sd in seeds])
+    for prec in ("FP64", "FP32"):
+        G = res[prec]
+        se = np.sqrt(G.var(0, ddof=1) / len(seeds) + O.var(0, ddof=1) / len(seeds))
+        se = np.maximum(se, 2e-4)
+        z = np.abs(G.mean(0) - O.mean(0)) / se
+        assert np.all(z < 4.0), (prec, z, G.mean(0) - O.mean(0))
+
+
+def test_reconstruction_and_beta_c(llr):
+    ctx = llr.Context(precision=llr.FP64)
+    rng = np.random.default_rng(4)
+    n = 128
+    V6 = 6 * 20 ** 4
+    dE = 0.0005 * V6
+    c = 0.6 * V6 + dE * (np.arange(n) + 0.5)
+    a = 1.011 + 0.002 * np.sin(np.linspace(0, 3, n)) + 1e-4 * rng.normal(size=n)
+    beta = np.linspace(1.008, 1.012, 41)
+    lr, u, cv = ctx.reconstruct(c, a, dE, V6, beta)
+    lro, uo, cvo = oracle.reconstruct(c, a, dE, V6, beta)
+    assert np.max(np.abs(lr - lro)) < 1e-9 * np.max(np.abs(lro))
+    assert np.max(np.abs(u - uo)) < 1e-12
+    assert np.max(np.abs(cv - cvo) / np.abs(cvo)) < 1e-9
+    bc, pk = ctx.beta_c(c, a, dE, V6, 1.008, 1.012)
+    bco, pko = oracle.beta_c(c, a, dE, V6, 1.008, 1.012)
+    assert abs(bc - bco) < 1e-8
+    assert abs(pk - pko) < 1e-9 * pko
+
+
+def test_mlp_init_forward_grad(llr):
+    ctx = llr.Context(precision=llr.FP32)
+    w = ctx.mlp_init(77)
+    wo = oracle.mlp_init(77)
+    assert np.array_equal(w, wo.astype(np.float32))
+    rng = np.random.default_rng(1)
+    n = 160
+    u = rng.uniform(0.55, 0.7, n).astype(np.float32)
+    invL = (1.0 / rng.choice([8, 12, 16], n)).astype(np.float32)
+    a = 1.0 + 0.3 * (u - 0.6) + 0.2 * invL
+    w[128:192] = rng.normal(0, 0.1, 64).astype(np.float32)
+    w[4288:4352] = rng.normal(0, 0.1, 64).astype(np.float32)
+    w64 = w.astype(np.float64)
+    ref = oracle.mlp_forward(w64, u.astype(np.float64), invL.astype(np.float64))
+    p32 = ctx.mlp_predict(w, u, invL, bf16=False)
+    assert np.max(np.abs(p32 - ref)) < 1e-5 * np.max(np.abs(ref))
+    pbf = ctx.mlp_predict(w, u, invL, bf16=True)
+    yref = (ref - 1.0) / 0.1
+    ybf = (pbf - 1.0) / 0.1
+    assert np.max(np.abs(ybf - yref)) < 2e-2 * max(1.0, np.max(np.abs(yref)))
+    loss, g = ctx.mlp_loss_grad(w, u, invL, a, bf16=False)
+    lo_, go = oracle.mlp_loss_grad(w64, u.astype(np.float64), invL.astype(np.float64), a)
+    assert abs(loss - lo_) < 1e-5 * lo_
+    assert np.max(np.abs(g - go)) < 1e-5 * np.max(np.abs(go))
+    lb, gb = ctx.mlp_loss_grad(w, u, invL, a, bf16=True)
+    assert abs(lb - lo_) < 2e-2 * lo_
+    assert np.max(np.abs(gb - go)) < 3e-2 * np.max(np.abs(go))
+
+
+def test_mlp_training_matches_oracle(llr):
+    ctx = llr.Context(precision=llr.FP32)
+    rng = np.random.default_rng(3)
+    n = 160
+    u = rng.uniform(0.55, 0.7, n)
+    invL = 1.0 / rng.choice([8, 12, 16], n)
+    a = 1.0 + 0.3 * (u - 0.6) + 0.2 * invL + 0.05 * (u - 0.6) ** 2 / 0.01
+    w0 = ctx.mlp_init(5)
+    w, hist = ctx.mlp_train(w0, u, invL, a, epochs=600, lr=3e-3, bf16=False)
+    wo, histo = oracle.mlp_train(w0.astype(np.float64), u, invL, a, epochs=600, lr=3e-3)
+    assert hist[0] == pytest.approx(histo[0], rel=1e-5)
+    assert hist[-1] < 0.05 * hist[0]
+    assert abs(np.log(hist[-1] / histo[-1])) < 0.5
+    wb, histb = ctx.mlp_train(w0, u, invL, a, epochs=600, lr=3e-3, bf16=True)
+    assert histb[-1] < 0.1 * histb[0]
+
+
+def test_invalid_arguments_are_rejected(llr):
+    ctx = llr.Context(precision=llr.FP64)
+    with pytest.raises(llr.LLRError):
+        ctx.add_lattice(5, [0.0], 1.0)          # odd L
+    with pytest.raises(llr.LLRError):
+        ctx.add_lattice(4, [0.0, -1.0], 1.0)    # non-ascending
+    with pytest.raises(llr.LLRError):
+        ctx.add_lattice(4, [0.0], -1.0)         # dE <= 0
+    with pytest.raises(llr.LLRError):
+        ctx.add_lattice(4, [1e9], 1.0)          # outside [-6V, 6V]
+    with pytest.raises(llr.LLRError):
+        ctx.run()                               # state not bound
+    with pytest.raises(llr.LLRError):
+        ctx.set_params(n_a=0)
