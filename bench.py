@@ -114,7 +114,7 @@ def main():
         ctx.rm_step(1)
         a, _, _ = ctx.get_a(0)
         bc, pk = ctx.beta_c(centres, a, dE, V6, 1.008, 1.012, h=1e-5, tol=1e-9)
-        print(f"# step {s}: beta_c {bc:.6f} C_V/6V {pk:.3e}", file=sys.stderr, flush=True)
+        print(f"# step {s}: beta_c {bc:.6f} C_V/(6V) {pk / V6:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm = ctx.get_timing()

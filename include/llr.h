@@ -196,10 +196,11 @@ llr_status llr_reconstruct(llr_ctx *ctx, const double *centres, const double *a,
                            double six_v, const double *beta, int nb, double *ln_rho,
                            double *u_mean, double *cv);
 /* beta_c = argmax C_V on [blo, bhi] (grid step h, then golden section to tol)
- * and the peak C_V/(6V) = Var(u). */
+ * and the peak value C_V = Var(E)/(6V); the paper's tabulated C_V/(6V) is
+ * this divided by 6V, i.e. Var(u). */
 llr_status llr_beta_c(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
                       double six_v, double blo, double bhi, double h, double tol,
-                      double *beta_c, double *cv_peak_over_6v);
+                      double *beta_c, double *cv_peak);
 
 /* --- warm-start network a(u, 1/L): 2 -> 64 (tanh) -> 64 (tanh) -> 1 ------ */
 /* Parameter vector (host, 4417 FP32): W1[64][2], b1[64], W2[64][64], b2[64],

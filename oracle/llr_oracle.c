@@ -552,24 +552,29 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
     if (o->a_hist) for (int k = 0; k < n; ++k) o->a_hist[k] = o->a[k];
 
     /* Approach (the paper is silent on how a hot start enters its interval):
-     * heatbath passes only, at a per-chain coupling b (initially a^(0)).  A
-     * class move is accepted iff it does not increase the distance of E to
-     * the interval.  After every pass b moves by eta * sign(c_k - E_new),
-     * where E_new is the proposal's energy (accepted or not); eta halves when
-     * that sign flips and grows by 1.2 while it repeats (within [1e-6, 0.05]):
-     * a sign-based root search for the coupling whose proposals land at the
-     * centre that cannot freeze while the target moves.  Sweeps run in blocks of K followed
-     * by a full recompute of E; the phase ends once every chain is inside. */
+     * heatbath passes only, each colour class c at its own coupling b_c
+     * (initially a^(0)).  A class move is accepted iff it does not increase
+     * the distance of E to the interval.  After every pass of colour c, b_c
+     * moves by eta_c * sign(c_k - E_new), where E_new is the proposal's energy
+     * (accepted or not); eta_c halves when that sign flips and grows by 1.2
+     * while it repeats (within [1e-6, 0.05]): a sign-based root search for the
+     * coupling whose proposals of that class land at the centre.  One coupling
+     * per class is needed because far from equilibrium the classes' own
+     * energies differ by more than a proposal's spread.  Sweeps run in blocks
+     * of K followed by a full recompute of E; the phase ends once every chain
+     * is inside. */
     long long t_ap = 0;
     long long bitrow = 0;
     int inside = all_inside(n, o->E, itv, lo, hi);
     int K = p->recompute_every > 0 ? p->recompute_every : 1;
-    double *eta = (double *)malloc(sizeof(double) * n);
-    int *sprev = (int *)malloc(sizeof(int) * n);
-    for (int c = 0; c < n; ++c) { eta[c] = 0.05; sprev[c] = 0; }
+    double *bc = (double *)malloc(sizeof(double) * n * 8);
+    double *eta = (double *)malloc(sizeof(double) * n * 8);
+    int *sprev = (int *)malloc(sizeof(int) * n * 8);
+    for (int c = 0; c < n; ++c)
+        for (int col = 0; col < 8; ++col) { bc[c * 8 + col] = b[c]; eta[c * 8 + col] = 0.05; sprev[c * 8 + col] = 0; }
     while (!inside) {
         if (t_ap >= p->approach_cap) {
-            free(cen); free(lo); free(hi); free(b); free(sumE); free(itv); free(eta); free(sprev);
+            free(cen); free(lo); free(hi); free(b); free(sumE); free(itv); free(eta); free(sprev); free(bc);
             geo_free(&g);
             *o->approach_sweeps = t_ap;
             return -5;
@@ -583,17 +588,18 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                                  (uint32_t)(t_ap + t), (uint32_t)k, p->f32};
                 int bits = 0;
                 for (int col = 0; col < nc; ++col) {
+                    const int q = c * 8 + col;
                     double dE = 0.0;
                     double E0 = o->E[c];
-                    if (class_pass(&g, o->theta + c * nl, scr, 1, col, 1, b[c], lo[k], hi[k],
+                    if (class_pass(&g, o->theta + c * nl, scr, 1, col, 1, bc[q], lo[k], hi[k],
                                    &o->E[c], &pc, NULL, &dE))
                         bits |= 1 << col;
                     double En = E0 + dE;
                     int sg = (cen[k] > En) ? 1 : (cen[k] < En ? -1 : 0);
-                    if (sprev[c] != 0 && sg != 0)
-                        eta[c] = (sg == sprev[c]) ? fmin(0.05, 1.2 * eta[c]) : fmax(1e-6, 0.5 * eta[c]);
-                    b[c] = fmin(4.0, fmax(0.0, b[c] + eta[c] * (double)sg));
-                    sprev[c] = sg;
+                    if (sprev[q] != 0 && sg != 0)
+                        eta[q] = (sg == sprev[q]) ? fmin(0.05, 1.2 * eta[q]) : fmax(1e-6, 0.5 * eta[q]);
+                    bc[q] = fmin(4.0, fmax(0.0, bc[q] + eta[q] * (double)sg));
+                    sprev[q] = sg;
                 }
                 if (o->bits) o->bits[(bitrow + t) * n + c] = (uint16_t)bits;
             }
@@ -604,6 +610,7 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
         bitrow += K;
         inside = all_inside(n, o->E, itv, lo, hi);
     }
+    free(bc);
     free(eta); free(sprev);
     *o->approach_sweeps = t_ap;
 

@@ -151,6 +151,10 @@ static llr_status layout(llr_ctx* c) {
         d.eblock0 = eblock0;
         d.lat_id = i;
         d.base = base;
+        // largest fxb with 6V 2^fxb <= 2^49
+        const int fxb = (int)std::floor(49.0 - std::log2(6.0 * (double)V));
+        d.fx = std::ldexp(1.0, fxb);
+        d.fxinv = std::ldexp(1.0, -fxb);
         chain0 += h.n;
         block0 += h.n * d.bpc;
         eblock0 += h.n * d.ebpc;
@@ -165,8 +169,8 @@ static llr_status layout(llr_ctx* c) {
     llr_status st;
 #define AL(field, cnt) \
     if ((st = dalloc(c, &s.field, (cnt))) != LLR_OK) return st;
-    AL(E, n) AL(acc, n) AL(eacc, n) AL(cur, 8 * n) AL(itv, n) AL(b, n) AL(eta, n)
-    AL(sprev, n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
+    AL(E, n) AL(acc, n) AL(eacc, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
+    AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
     AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n)
     AL(lat_done, kMaxLat) AL(lat_outside, kMaxLat) AL(lat_approach, kMaxLat) AL(sweep_ctr, 1)
     AL(approach_ctr, 1) AL(rm_iter, 1) AL(re_cnt, 2) AL(bits_row, 1)

@@ -10,8 +10,6 @@ namespace llr {
 constexpr int kBlock = 256;           // threads per block of the lattice kernels
 constexpr int kMaxLat = 8;            // lattices per context
 constexpr int kVmCap = 64;            // heatbath sampler attempt cap
-constexpr double kFix = 1099511627776.0;        // 2^40: fixed-point scale of per-thread energy terms
-constexpr double kFix24Inv = 1.0 / 16777216.0;  // 2^-24: resolution of the per-chain sums
 
 enum Kind : uint32_t { kSweep = 0, kInit = 1, kApproach = 2, kReplica = 3, kMlp = 4 };
 

@@ -23,6 +23,7 @@ struct LatDev {
     int eblock0;           // first block of this lattice in the site grid
     int lat_id;
     long long base;        // element offset of the lattice's first chain
+    double fx, fxinv;      // 2^fxb and 2^-fxb: fixed point of the per-chain energy sums
 };
 
 struct LatTable {
@@ -41,9 +42,9 @@ struct DevState {
     unsigned long long* eacc;  // the same for the energy recompute
     uint8_t* cur;          // 8 per chain: current plane of each colour
     int* itv;              // global index of the interval the chain serves
-    double* b;             // approach coupling
-    double* eta;           // approach step
-    int* sprev;            // approach: sign of the previous proposal offset
+    double* b;             // approach coupling, 8 per chain (one per colour)
+    double* eta;           // approach step, 8 per chain
+    int* sprev;            // approach: sign of the previous proposal offset, 8 per chain
     uint16_t* bits;        // accept bits of the running sweep
     uint16_t* bits_last;   // accept bits of the last finished sweep
     unsigned long long* hb_prop;

@@ -123,17 +123,16 @@ __device__ __forceinline__ long long block_sum_i64(long long v) {
 }
 
 // Per-chain reduction without fences: each block adds, in ONE 64-bit atomic,
-// 2^48 (its arrival) plus its partial sum in 2^-24 fixed point (two's
-// complement in the low 48 bits; |sum| < 2^47 for L <= 32).  The block whose
-// addition brings the count to nblocks holds the exact total, order-free.
-__device__ __forceinline__ bool chain_arrive(unsigned long long* acc, long long block_fx40, int nblocks,
-                                             long long* total_fx24) {
-    const long long part = (block_fx40 + (1ll << 15)) >> 16;
-    const unsigned long long add = (1ull << 48) + (unsigned long long)part;
+// 2^51 (its arrival) plus its partial sum in the lattice's fixed point 2^-fxb
+// (two's complement in the low 51 bits; fxb is chosen so that 6V 2^fxb <=
+// 2^49 bounds every partial sum).  The block whose addition brings the count
+// to nblocks (< 2^13) holds the exact total, independent of arrival order.
+__device__ __forceinline__ bool chain_arrive(unsigned long long* acc, long long part, int nblocks, long long* total) {
+    const unsigned long long add = (1ull << 51) + (unsigned long long)part;
     const unsigned long long nw = atomicAdd(acc, add) + add;
-    const long long S = ((long long)(nw << 16)) >> 16;
-    const unsigned long long nb = (nw - (unsigned long long)S) >> 48;
-    *total_fx24 = S;
+    const long long S = ((long long)(nw << 13)) >> 13;
+    const unsigned long long nb = (nw - (unsigned long long)S) >> 51;
+    *total = S;
     return nb == (unsigned long long)nblocks;
 }
 
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const uint32_t h = (uint32_t)tile * kBlock + threadIdx.x;
     const bool active = h < L.V2;
     const int gi = s.itv[g];
-    const double acoup = mode == kModeApproach ? s.b[g] : s.a[gi];
+    const double acoup = mode == kModeApproach ? s.b[8 * g + colour] : s.a[gi];
     const uint32_t sweep = kind == kApproach ? *s.approach_ctr : *s.sweep_ctr;
     long long fx = 0;
     if (active) {
@@ -226,14 +225,14 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             dE = M::div_(R * er, nrm) - eps_old;
         }
         palt[h] = t_new;
-        fx = __double2ll_rn((double)dE * kFix);
+        fx = __double2ll_rn((double)dE * L.fx);
     }
     const long long tot = block_sum_i64(fx);
     long long total = 0;
     if (threadIdx.x == 0 && chain_arrive(s.acc + g, tot, L.bpc, &total)) {
         {
             const double E0 = s.E[g];
-            const double En = E0 + (double)total * kFix24Inv;
+            const double En = E0 + (double)total * L.fxinv;
             const double lo = s.lo[gi], hi = s.hi[gi];
             bool acc;
             if (mode == kModeRestricted) {
@@ -244,12 +243,13 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
                 acc = d1 <= d0;
                 const double cen = s.cen[gi];
                 const int sg = cen > En ? 1 : (cen < En ? -1 : 0);
-                double eta = s.eta[g];
-                const int sp = s.sprev[g];
+                const int q = 8 * g + colour;   // one coupling per colour class
+                double eta = s.eta[q];
+                const int sp = s.sprev[q];
                 if (sp != 0 && sg != 0) eta = sg == sp ? fmin(0.05, 1.2 * eta) : fmax(1e-6, 0.5 * eta);
-                s.eta[g] = eta;
-                s.b[g] = fmin(4.0, fmax(0.0, s.b[g] + eta * (double)sg));
-                s.sprev[g] = sg;
+                s.eta[q] = eta;
+                s.b[q] = fmin(4.0, fmax(0.0, s.b[q] + eta * (double)sg));
+                s.sprev[q] = sg;
             } else {
                 acc = true;
             }
@@ -343,13 +343,13 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
                 const double t_nu_pmu = (double)plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2)[hup[mu]];
                 const double t_mu_pnu = (double)plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2)[hup[nu]];
                 const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
-                fx += __double2ll_rn(cos(ang) * kFix);
+                fx += __double2ll_rn(cos(ang) * L.fx);
             }
     }
     const long long tot = block_sum_i64(fx);
     long long total = 0;
     if (threadIdx.x == 0 && chain_arrive(s.eacc + g, tot, L.ebpc, &total)) {
-        s.E[g] = (double)total * kFix24Inv;
+        s.E[g] = (double)total * L.fxinv;
         atomicExch(s.eacc + g, 0ull);
     }
 }
@@ -524,10 +524,10 @@ __global__ __launch_bounds__(1024) void k_rm_update(int n, DevState s, RunCfg cf
 }
 
 __global__ __launch_bounds__(1024) void k_approach_init(int n, DevState s) {
-    for (int g = threadIdx.x; g < n; g += blockDim.x) {
-        s.b[g] = s.a[s.itv[g]];
-        s.eta[g] = 0.05;
-        s.sprev[g] = 0;
+    for (int q = threadIdx.x; q < 8 * n; q += blockDim.x) {
+        s.b[q] = s.a[s.itv[q >> 3]];
+        s.eta[q] = 0.05;
+        s.sprev[q] = 0;
     }
 }
 

@@ -227,11 +227,10 @@ def _states_in_intervals(L, E_low, dE, seed):
 
 @pytest.mark.parametrize("replica", [False, True])
 def test_driver_short_run_fp64(llr, replica):
-    """Every driver step inside the divergence horizon: N_TH = 1, N_A = 2,
-    N_RM = 3 from states inside their intervals, recompute every 2 sweeps,
-    replica exchange after every sweep: accept bits, chain <-> interval
-    labels identical to the oracle, every a_k^(n) within 1e-6 (the angles
-    part at ~1e-9 .. 1e-6 by the ninth sweep)."""
+    """Every driver step inside the divergence horizon: N_TH = 1, N_A = 1,
+    N_RM = 3 (6 sweeps) from states inside their intervals, recompute every 2
+    sweeps, replica exchange after every sweep: accept bits and chain <->
+    interval labels identical to the oracle, every a_k^(n) within 1e-7."""
     import torch
     L, d = 4, 4
     V6 = 6 * L ** 4
@@ -239,7 +238,7 @@ def test_driver_short_run_fp64(llr, replica):
     E_low = 0.55 * V6 + dE * np.arange(8)
     th = _states_in_intervals(L, E_low, dE, seed=5)
     a0 = np.linspace(0.95, 1.1, 8)
-    ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a0], n_th=1, n_a=2, n_rm=3, recompute_every=2,
+    ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a0], n_th=1, n_a=1, n_rm=3, recompute_every=2,
                replica_exchange=replica)
     ctx.enable_bits_log(100)
     ctx.import_state(0, torch.from_numpy(th))
@@ -249,13 +248,13 @@ def test_driver_short_run_fp64(llr, replica):
     E, conf = ctx.get_energy(0)
     bits = ctx.get_bits_log()
     _, _, re_prop, re_acc = ctx.stats()
-    r = oracle.llr_run(d, L, E_low, dE, a0, n_th=1, n_a=2, n_rm=3, seed=SEED, recompute_every=2,
+    r = oracle.llr_run(d, L, E_low, dE, a0, n_th=1, n_a=1, n_rm=3, seed=SEED, recompute_every=2,
                        replica_exchange=replica, theta=th, record_bits=True, approach_cap=0)
     assert r["approach_sweeps"] == 0
     assert np.array_equal(bits.astype(np.int64), r["bits"].astype(np.int64))
     assert np.array_equal(conf, r["conf"])
-    assert np.max(np.abs(hist - r["a_hist"])) < 1e-6
-    assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-8
+    assert np.max(np.abs(hist - r["a_hist"])) < 1e-7
+    assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-9
     assert np.array_equal(it, r["conv_iter"])
     if replica:
         assert (re_prop, re_acc) == (int(r["re"][0]), int(r["re"][1]))
@@ -295,16 +294,16 @@ def test_driver_mixed_lattices_fp64(llr):
         dE = 0.02 * V6
         E_low = 0.58 * V6 + dE * np.arange(n)
         lats.append((L, E_low, dE, _states_in_intervals(L, E_low, dE, seed=L)))
-    ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=1, n_a=2, n_rm=2, recompute_every=3)
+    ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=0, n_a=2, n_rm=2, recompute_every=3)
     for i, x in enumerate(lats):
         ctx.import_state(i, torch.from_numpy(x[3]))
     ctx.run()
     for i, (L, E_low, dE, th) in enumerate(lats):
-        r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=1, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
+        r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=0, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
                            lattice_id=i, theta=th, approach_cap=0)
         a, it, sw = ctx.get_a(i)
-        assert np.max(np.abs(a - r["a"])) < 1e-6
-        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-5
+        assert np.max(np.abs(a - r["a"])) < 1e-7
+        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-7
 
 
 @pytest.mark.slow
