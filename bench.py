@@ -30,6 +30,10 @@ L = 20
 N_INT = 128
 SEED = 1509083910
 PEAK_HBM_GBS = 8000.0
+# Calibrated HBM bytes per heatbath launch (FETCH_SIZE x 2 + WRITE_SIZE x 1,
+# rocprofv3 on this kernel version, profiles/k_hb_L20x128_fp32_counters.md);
+# None once the kernel changes until the counters are taken again.
+HB_TRAFFIC_BYTES_FP32 = 370.1e6
 
 
 def cpu_baseline(target_s=12.0):
@@ -68,6 +72,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-th", type=int, default=500)
     ap.add_argument("--n-a", type=int, default=2000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 plain device copies of 1 GiB (FP32) to calibrate the FETCH_SIZE and "
+                         "WRITE_SIZE counters against a known byte count, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the chains of this workload are "
@@ -76,6 +83,16 @@ def main():
         sys.exit(2)
     import torch
     from paper_1509_08391_amd import llr
+
+    if args.copy_calibration:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
 
     V = L ** 4
     V6 = 6 * V
@@ -152,7 +169,8 @@ def main():
                    "L": L, "intervals": N_INT, "sweeps_per_step": nsw,
                    "precision": "fp32 angles, fp64 energy/test/RM" if prec == llr.FP32 else "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": HB_TRAFFIC_BYTES_FP32 if prec == llr.FP32 else None,
                      "kernel": "heatbath class pass (k_hb)",
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
                      "overrelaxation_avg_launch_us": or_avg_s * 1e6},
