@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # Calibrated HBM bytes per heatbath launch (FETCH_SIZE x 2 + WRITE_SIZE x 1,
 # rocprofv3 on this kernel version, profiles/k_hb_L20x128_fp32_counters.md);
 # None once the kernel changes until the counters are taken again.
-HB_TRAFFIC_BYTES_FP32 = 370.1e6
+HB_TRAFFIC_BYTES_FP32 = None
 
 
 def cpu_baseline(target_s=12.0):

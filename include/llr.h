@@ -166,6 +166,16 @@ llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double 
  * measurement, no recompute).  bits (host, n_sweeps x total chains, optional):
  * bit c = heatbath colour c accepted, bit 8 + c = overrelaxation colour c. */
 llr_status llr_sweeps(llr_ctx *ctx, int n_sweeps, long long sweep0, int mode, uint16_t *bits);
+/* Tiles of the class-pass kernels: class links per thread (1, 2 or 4) of the
+ * heatbath and of the overrelaxation pass.  llr_autotune
+ * times the choices on the bound, initialised state without changing it and
+ * keeps the fastest per kernel (llr_rm_begin calls it if no choice was made);
+ * llr_set_tiles fixes them.  Results are bit-identical for every choice. */
+llr_status llr_autotune(llr_ctx *ctx, int *hb_lpt, int *or_lpt);
+llr_status llr_set_tiles(llr_ctx *ctx, int hb_lpt, int or_lpt);
+/* One class pass of every chain: heatbath (heatbath != 0, acceptance by mode,
+ * counters with sweep index sweep_index) or overrelaxation of colour c. */
+llr_status llr_class_pass(llr_ctx *ctx, int heatbath, int colour, int mode, long long sweep_index);
 /* Full FP64 recompute of every chain's E. */
 llr_status llr_recompute_energy(llr_ctx *ctx);
 /* Record per-sweep accept bits of approach and run (host readback). */

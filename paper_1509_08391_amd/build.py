@@ -14,9 +14,15 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+# The sweep kernels are compiled without floating-point contraction: every
+# tile instantiation (links per thread) then performs the same IEEE
+# operations, so results do not depend on the autotuner's choice.
+EXTRA = {"llr_sweep.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src):
     obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

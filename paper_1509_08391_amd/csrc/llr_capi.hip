@@ -61,6 +61,7 @@ struct llr_ctx {
     std::vector<int> ap_done;  // approach finished per lattice
     bool ap_open = false;
     int rm_done = 0;       // RM iterations performed since llr_rm_begin
+    bool tuned = false;    // class-pass tiles chosen (autotuner or llr_set_tiles)
     bool rm_open = false;
     // timing
     bool timing = false;
@@ -126,13 +127,31 @@ static llr_status upload_intervals(llr_ctx* c) {
     return LLR_OK;
 }
 
+// Block tables of the class-pass launches for hb_lpt / or_lpt class links per thread.
+static void set_tiles(LatTable& lt, int hb_lpt, int or_lpt) {
+    lt.hb_lpt = hb_lpt;
+    lt.or_lpt = or_lpt;
+    int hb0 = 0, or0 = 0;
+    for (int i = 0; i < lt.n; ++i) {
+        LatDev& d = lt.l[i];
+        d.hb_bpc = (int)((d.V2 + (uint32_t)(kBlock * hb_lpt) - 1) / (uint32_t)(kBlock * hb_lpt));
+        d.or_bpc = (int)((d.V2 + (uint32_t)(kBlock * or_lpt) - 1) / (uint32_t)(kBlock * or_lpt));
+        d.hb_block0 = hb0;
+        d.or_block0 = or0;
+        hb0 += d.n_chains * d.hb_bpc;
+        or0 += d.n_chains * d.or_bpc;
+    }
+    lt.hb_blocks = hb0;
+    lt.or_blocks = or0;
+}
+
 static llr_status layout(llr_ctx* c) {
     if (c->laid_out) return LLR_OK;
     if (c->lats.empty()) return fail(LLR_ESTATE, "no lattice added");
     LatTable& lt = c->lt;
     memset(&lt, 0, sizeof(lt));
     lt.n = (int)c->lats.size();
-    int chain0 = 0, block0 = 0, eblock0 = 0;
+    int chain0 = 0, eblock0 = 0;
     long long base = 0;
     for (int i = 0; i < lt.n; ++i) {
         const HostLat& h = c->lats[i];
@@ -145,23 +164,21 @@ static llr_status layout(llr_ctx* c) {
         d.mhL = magic((uint32_t)(h.L / 2));
         d.n_chains = h.n;
         d.chain0 = chain0;
-        d.bpc = (int)((d.V2 + kBlock - 1) / kBlock);
-        d.block0 = block0;
         d.ebpc = (int)((V + kBlock - 1) / kBlock);
         d.eblock0 = eblock0;
         d.lat_id = i;
         d.base = base;
         // largest fxb with 6V 2^fxb <= 2^49
         const int fxb = (int)std::floor(49.0 - std::log2(6.0 * (double)V));
+        d.fxb = fxb;
         d.fx = std::ldexp(1.0, fxb);
         d.fxinv = std::ldexp(1.0, -fxb);
         chain0 += h.n;
-        block0 += h.n * d.bpc;
         eblock0 += h.n * d.ebpc;
         base += (long long)h.n * 8 * V;
     }
-    lt.pass_blocks = block0;
     lt.site_blocks = eblock0;
+    set_tiles(lt, 1, 1);
     lt.n_chains = chain0;
     c->state_bytes = (size_t)base * elem_size(c);
     const int n = chain0;
@@ -243,7 +260,7 @@ static void enqueue_hb_pass(llr_ctx* c, int colour, int mode, int kind) {
 template <typename T>
 static void enqueue_or_pass(llr_ctx* c, int colour) {
     TimeScope ts(c, 1);
-    launch_or_pass<T>(c->lt, (T*)c->state, c->ds, colour, c->stream);
+    launch_or_pass<T>(c->lt, (T*)c->state, c->ds, colour, 0, c->stream);
 }
 template <typename T>
 static void enqueue_energy(llr_ctx* c) {
@@ -265,6 +282,49 @@ template <typename T>
 static void enqueue_approach_sweep(llr_ctx* c) {
     for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, LLR_MODE_APPROACH, kApproach);
     launch_end_sweep(c->lt, c->ds, 0, 1, 0, c->stream);
+}
+
+// Autotuner: class links per thread (1, 2, 4) of the heatbath and the
+// overrelaxation pass, timed with HIP events on the bound state without
+// changing it (heatbath in a never-accepting mode, overrelaxation writing to
+// the non-current planes); the fastest per kernel is kept for the context.
+template <typename T>
+static llr_status autotune_impl(llr_ctx* c) {
+    const int cand[3] = {1, 2, 4};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_hb = 1e30f, best_or = 1e30f;
+    int bh = 1, bo = 1;
+    const bool was_timing = c->timing;
+    c->timing = false;
+    for (int ci = 0; ci < 3; ++ci) {
+        set_tiles(c->lt, cand[ci], cand[ci]);
+        for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int col = 0; col < 8; ++col)
+                launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, 3, kSweep, (uint32_t)c->prm.seed,
+                                  (uint32_t)(c->prm.seed >> 32), c->stream);
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 1 && ms < best_hb) { best_hb = ms; bh = cand[ci]; }
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int col = 0; col < 8; ++col) launch_or_pass<T>(c->lt, (T*)c->state, c->ds, col, 1, c->stream);
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 1 && ms < best_or) { best_or = ms; bo = cand[ci]; }
+        }
+    }
+    set_tiles(c->lt, bh, bo);
+    c->timing = was_timing;
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    HIPCHK(hipGetLastError());
+    c->tuned = true;
+    return LLR_OK;
 }
 
 static llr_status need_state(llr_ctx* c) {
@@ -337,7 +397,13 @@ static llr_status approach_impl(llr_ctx* c, long long* sweeps) {
     return LLR_OK;
 }
 
+template <typename T> static llr_status autotune_impl(llr_ctx* c);
+
 static llr_status rm_begin(llr_ctx* c) {
+    if (!c->tuned) {
+        llr_status st0 = c->precision == LLR_FP32 ? autotune_impl<float>(c) : autotune_impl<double>(c);
+        if (st0 != LLR_OK) return st0;
+    }
     const llr_params& p = c->prm;
     const int n = c->lt.n_chains;
     if (p.n_a < 1 || p.n_th < 0 || p.n_rm < 1) return fail(LLR_EINVAL, "need n_a >= 1, n_th >= 0, n_rm >= 1");
@@ -626,6 +692,27 @@ llr_status llr_rm_step(llr_ctx* c, int iterations) {
     return c->rm_done == c->prm.n_rm ? rm_converged(c) : LLR_OK;
 }
 
+llr_status llr_autotune(llr_ctx* c, int* hb_lpt, int* or_lpt) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (!c->have_energy) return fail(LLR_ESTATE, "initialise the state (hot start or import) before tuning");
+    HIPCHK(hipSetDevice(c->device));
+    st = c->precision == LLR_FP32 ? autotune_impl<float>(c) : autotune_impl<double>(c);
+    if (st != LLR_OK) return st;
+    if (hb_lpt) *hb_lpt = c->lt.hb_lpt;
+    if (or_lpt) *or_lpt = c->lt.or_lpt;
+    return LLR_OK;
+}
+
+llr_status llr_set_tiles(llr_ctx* c, int hb_lpt, int or_lpt) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "lay out the lattices first");
+    auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+    if (!ok(hb_lpt) || !ok(or_lpt)) return fail(LLR_EINVAL, "links per thread must be 1, 2 or 4");
+    set_tiles(c->lt, hb_lpt, or_lpt);
+    c->tuned = true;
+    return LLR_OK;
+}
+
 llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint16_t* bits) {
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
@@ -633,6 +720,25 @@ llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint
     HIPCHK(hipSetDevice(c->device));
     return c->precision == LLR_FP32 ? sweeps_impl<float>(c, n_sweeps, sweep0, mode, bits)
                                     : sweeps_impl<double>(c, n_sweeps, sweep0, mode, bits);
+}
+
+llr_status llr_class_pass(llr_ctx* c, int heatbath, int colour, int mode, long long sweep_index) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (colour < 0 || colour > 7 || mode < 0 || mode > 2) return fail(LLR_EINVAL, "bad colour or mode");
+    HIPCHK(hipSetDevice(c->device));
+    const uint32_t s0 = (uint32_t)sweep_index;
+    HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
+    if (c->precision == LLR_FP32) {
+        if (heatbath) enqueue_hb_pass<float>(c, colour, mode, kSweep);
+        else enqueue_or_pass<float>(c, colour);
+    } else {
+        if (heatbath) enqueue_hb_pass<double>(c, colour, mode, kSweep);
+        else enqueue_or_pass<double>(c, colour);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
 }
 
 llr_status llr_recompute_energy(llr_ctx* c) {

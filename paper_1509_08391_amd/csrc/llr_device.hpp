@@ -50,6 +50,7 @@ template <> struct Math<double> {
     __device__ static __forceinline__ double log_(double x) { return log(x); }
     __device__ static __forceinline__ double div_(double a, double b) { return a / b; }
     __device__ static __forceinline__ double pi() { return 3.14159265358979323846; }
+    __device__ static __forceinline__ double fma_(double a, double b, double c) { return __fma_rn(a, b, c); }
 };
 
 template <> struct Math<float> {
@@ -66,12 +67,44 @@ template <> struct Math<float> {
         *s = __builtin_amdgcn_sinf(r);
         *c = __builtin_amdgcn_cosf(r);
     }
-    __device__ static __forceinline__ float atan2_(float y, float x) { return atan2f(y, x); }
-    __device__ static __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    // atan2 from explicit instructions (the library version lowers its internal
+    // division differently per call site, which changes last bits between
+    // kernel instantiations): a = min/max by v_rcp_f32, atan(a) = a P(a^2)
+    // with an odd degree-17 minimax polynomial on [0, 1] (fitted by Lawson's
+    // iteration; max error 1.03e-7 rad in single precision), then octants.
+    __device__ static __forceinline__ float atan2_(float y, float x) {
+        const float ax = __builtin_fabsf(x), ay = __builtin_fabsf(y);
+        const float mx = __builtin_fmaxf(ax, ay), mn = __builtin_fminf(ax, ay);
+        const float a = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+        const float s = a * a;
+        float p = 0.0024567251093685627f;
+        p = __fmaf_rn(p, s, -0.014401360414922237f);
+        p = __fmaf_rn(p, s, 0.039781227707862854f);
+        p = __fmaf_rn(p, s, -0.07234857976436615f);
+        p = __fmaf_rn(p, s, 0.10498946160078049f);
+        p = __fmaf_rn(p, s, -0.14161229133605957f);
+        p = __fmaf_rn(p, s, 0.19985906779766083f);
+        p = __fmaf_rn(p, s, -0.33332598209381104f);
+        p = __fmaf_rn(p, s, 0.9999998807907104f);
+        float r = a * p;
+        if (ay > ax) r = 1.57079632679489662f - r;
+        if (x < 0.f) r = 3.14159265358979324f - r;
+        return y < 0.f ? -r : r;
+    }
+    __device__ static __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     __device__ static __forceinline__ float log_(float x) { return __logf(x); }
     __device__ static __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static __forceinline__ float pi() { return 3.14159265f; }
+    __device__ static __forceinline__ float fma_(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 };
+
+// a b - c d and a b + c d with one rounding of the first product (explicit
+// fused multiply-add: the kernels are compiled without contraction so that
+// every instantiation performs identical operations).
+template <typename T>
+__device__ __forceinline__ T fms2(T a, T b, T c, T d) { return Math<T>::fma_(a, b, -(c * d)); }
+template <typename T>
+__device__ __forceinline__ T fma2(T a, T b, T c, T d) { return Math<T>::fma_(a, b, c * d); }
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
 // works on a contiguous range of logical blocks (neighbouring tiles of a chain

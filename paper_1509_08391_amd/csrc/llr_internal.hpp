@@ -17,19 +17,22 @@ struct LatDev {
     uint32_t mL, mhL;      // ceil(2^32 / L), ceil(2^32 / (L/2))
     int n_chains;          // = number of intervals
     int chain0;            // first global chain index (= first global interval index)
-    int bpc;               // blocks per chain in the class-pass kernels (V/2 / 256, rounded up)
-    int block0;            // first block of this lattice in the class-pass grid
+    int hb_bpc, hb_block0; // heatbath pass: blocks per chain (V/2 / (256 LPT), rounded up), first block
+    int or_bpc, or_block0; // overrelaxation pass: the same
     int ebpc;              // blocks per chain in the site kernels (V / 256, rounded up)
     int eblock0;           // first block of this lattice in the site grid
     int lat_id;
     long long base;        // element offset of the lattice's first chain
-    double fx, fxinv;      // 2^fxb and 2^-fxb: fixed point of the per-chain energy sums
+    int fxb;               // fraction bits of the per-chain energy sums
+    double fx, fxinv;      // 2^fxb and 2^-fxb
 };
 
 struct LatTable {
     LatDev l[kMaxLat];
     int n;
-    int pass_blocks;       // total blocks of a class-pass launch
+    int hb_lpt, or_lpt;    // class links per thread (1, 2 or 4), chosen by the autotuner
+    int hb_blocks;         // total blocks of a heatbath / overrelaxation launch
+    int or_blocks;
     int site_blocks;       // total blocks of a site launch
     int n_chains;          // total chains = total intervals
 };
@@ -85,7 +88,8 @@ struct RunCfg {
 template <typename T> void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32_t k1, hipStream_t st);
 template <typename T> void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind,
                                           uint32_t k0, uint32_t k1, hipStream_t st);
-template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, hipStream_t st);
+template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_alt,
+                                          hipStream_t st);
 template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st);
 template <typename T> void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st);
 template <typename T> void launch_import(const LatTable& lt, int li, T* th, DevState s, const T* in, hipStream_t st);

@@ -19,14 +19,8 @@
 
 namespace llr {
 
-enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2 };
+enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeTune = 3 };
 
-__device__ __forceinline__ int find_lat_pass(const LatTable& lt, int b) {
-    int li = 0;
-#pragma unroll 1
-    while (li + 1 < lt.n && b >= lt.l[li + 1].block0) ++li;
-    return li;
-}
 __device__ __forceinline__ int find_lat_site(const LatTable& lt, int b) {
     int li = 0;
 #pragma unroll 1
@@ -60,17 +54,37 @@ __device__ __forceinline__ T* plane_ptr(T* chain, uint64_t curw, int c, uint32_t
     return chain + (size_t)((((curw >> (8 * c)) & 1ull) * 8ull) + (uint64_t)c) * V2;
 }
 
+// Half-index offsets of the neighbours of site x along each direction:
+// up[nu] = h(x + nu) - h(x), dn[nu] = h(x - nu) - h(x), periodic.  Sites
+// (2j, 2j+1) along x0 share a half index, so the x0 offsets depend on x0's
+// parity; along nu >= 1 a step is L^nu / 2 half indices.
+__device__ __forceinline__ void neighbour_offsets(const LatDev& L, const int x[4], int up[4], int dn[4]) {
+    const int odd = x[0] & 1;
+    up[0] = odd ? (x[0] == L.L - 1 ? 1 - L.hL : 1) : 0;
+    dn[0] = odd ? 0 : (x[0] == 0 ? L.hL - 1 : -1);
+    int stride = L.hL;
+#pragma unroll
+    for (int nu = 1; nu < 4; ++nu) {
+        up[nu] = x[nu] == L.L - 1 ? -(L.L - 1) * stride : stride;
+        dn[nu] = x[nu] == 0 ? (L.L - 1) * stride : -stride;
+        stride *= L.L;
+    }
+}
+
 // Local field of link (MU, x): staples of the 2 x 3 plaquettes containing it,
-// each oriented so that theta_MU(x) enters with a plus sign.
+// each oriented so that theta_MU(x) enters with a plus sign:
+//   forward  s_f = th_nu(x+mu) - th_mu(x+nu) - th_nu(x)
+//   backward s_b = th_nu(x-nu) - th_nu(x+mu-nu) - th_mu(x-nu)
+// C + i S = sum of e^{i s}.
 template <typename T, int MU>
-__device__ __forceinline__ void staples(const LatDev& L, T* chain, uint64_t curw, const int x[4], int p,
+__device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_t curw, const int x[4], int p,
                                         uint32_t h, T& C, T& S) {
     using M = Math<T>;
-    int xm[4] = {x[0], x[1], x[2], x[3]};
-    xm[MU] = up(x[MU], L.L);
-    const uint32_t h_pmu = half_of(L, xm[0], xm[1], xm[2], xm[3]);
+    int up[4], dn[4];
+    neighbour_offsets(L, x, up, dn);
     const int q = p ^ 1;
     const T* pmu_q = plane_ptr(chain, curw, 2 * MU + q, L.V2);
+    const uint32_t h_pmu = h + up[MU];
     C = T(0);
     S = T(0);
 #pragma unroll
@@ -78,17 +92,9 @@ __device__ __forceinline__ void staples(const LatDev& L, T* chain, uint64_t curw
         if (NU == MU) continue;
         const T* pnu_p = plane_ptr(chain, curw, 2 * NU + p, L.V2);
         const T* pnu_q = plane_ptr(chain, curw, 2 * NU + q, L.V2);
-        int y[4];
-        // x + nu
-        y[0] = x[0]; y[1] = x[1]; y[2] = x[2]; y[3] = x[3];
-        y[NU] = up(x[NU], L.L);
-        const uint32_t h_pnu = half_of(L, y[0], y[1], y[2], y[3]);
-        // x - nu
-        y[NU] = dn(x[NU], L.L);
-        const uint32_t h_mnu = half_of(L, y[0], y[1], y[2], y[3]);
-        // x + mu - nu
-        y[MU] = xm[MU];
-        const uint32_t h_pmu_mnu = half_of(L, y[0], y[1], y[2], y[3]);
+        const uint32_t h_pnu = h + up[NU];
+        const uint32_t h_mnu = h + dn[NU];
+        const uint32_t h_pmu_mnu = h + up[MU] + dn[NU];
         const T t_nu_pmu = pnu_q[h_pmu];
         const T t_mu_pnu = pmu_q[h_pnu];
         const T t_nu_x = pnu_p[h];
@@ -136,6 +142,53 @@ __device__ __forceinline__ bool chain_arrive(unsigned long long* acc, long long 
     return nb == (unsigned long long)nblocks;
 }
 
+// Best-Fisher constants in the cancellation-free form: q = (1-rho)/(1+rho),
+// r - 1 = (1-rho)^2/(2 rho), kappa (r^2 - 1) with sqrt(r^2-1) = (1-rho^2)/(2 rho).
+template <typename T>
+__device__ __forceinline__ void vm_constants(T ak, T& q, T& rm1, T& kg2) {
+    using M = Math<T>;
+    q = T(1); rm1 = T(1); kg2 = T(0);
+    if (ak > T(0)) {
+        const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
+        const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
+        const T irho = M::div_(T(1), rho);
+        rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;
+        const T gg = T(0.5) * (T(1) - rho * rho) * irho;
+        kg2 = ak * gg * gg;
+        q = M::div_(T(1) - rho, T(1) + rho);
+    }
+}
+
+// One sampler attempt from the word pair (wa, wb): accept test of Best &
+// Fisher with z = cos(pi V1); on accept (ch, sh) = (cos, q sin)(pi V1 / 2).
+template <typename T>
+__device__ __forceinline__ bool vm_attempt(uint32_t wa, uint32_t wb, T q, T rm1, T kg2, T& ch, T& sh) {
+    using M = Math<T>;
+    const T V1 = M::sunif(wa);
+    T s_, c_;
+    M::sincos_halfpi(V1, &s_, &c_);
+    const T U2 = M::unif(wb);
+    const T cc = M::div_(kg2, M::fma_(T(2) * c_, c_, rm1));   // kappa (r^2 - 1)/(r + z)
+    bool acc = M::fma_(cc, T(2) - cc, -U2) > T(0);
+    if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
+    if (acc) { ch = c_; sh = q * s_; }
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ long long to_fixed(T v, const LatDev& L);
+template <>
+__device__ __forceinline__ long long to_fixed<double>(double v, const LatDev& L) {
+    return __double2ll_rn(v * L.fx);
+}
+// |v| <= 12: exact int32 at 2^-27, then to the lattice's 2^-fxb
+template <>
+__device__ __forceinline__ long long to_fixed<float>(float v, const LatDev& L) {
+    const long long q = (long long)__float2int_rn(v * 134217728.0f);
+    const int sh = L.fxb - 27;
+    return sh >= 0 ? (q << sh) : ((q + (1ll << (-sh - 1))) >> (-sh));
+}
+
 // ---------------------------------------------------------------------------
 // Heatbath class pass.  Link conditional ~ exp(a R cos(theta + phi)) with
 // (C, S) the staple sums, R = |C + iS|, phi = arg(C + iS); theta' = X - phi
@@ -143,165 +196,238 @@ __device__ __forceinline__ bool chain_arrive(unsigned long long* acc, long long 
 // half-angle form: tan(X/2) = q tan(pi V1 / 2), q = (1 - rho)/(1 + rho).
 // theta' is formed as arg[(cos(pi V1/2) + i q sin(pi V1/2))^2 (C - i S)], and
 // the new local action is R cos X.
+//
+// Each thread owns LPT class links of a tile of kBlock * LPT links (all their
+// loads are issued before the arithmetic).  Sampler schedule: every link
+// tries attempts 0 and 1 (one Philox call); the few links that reject both
+// are queued in LDS and later rounds give each queued link its next two
+// attempts with full lanes, so the lockstep cost of the acceptance tail is
+// paid per block, not per wavefront.  Each link still takes its first
+// accepted attempt in order.
 // ---------------------------------------------------------------------------
-template <typename T, int MU>
+template <typename T, int MU, int LPT>
 __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
                                                int kind, uint32_t k0, uint32_t k1) {
     using M = Math<T>;
+    constexpr int NT = kBlock * LPT;
+    __shared__ T s_q[NT], s_rm1[NT], s_kg2[NT], s_ch[NT], s_sh[NT];
+    __shared__ unsigned char s_res[NT];
+    __shared__ short s_queue[2][NT];
+    __shared__ int s_qn[2];
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int li = find_lat_pass(lt, b);
+    int li = 0;
+#pragma unroll 1
+    while (li + 1 < lt.n && b >= lt.l[li + 1].hb_block0) ++li;
     const LatDev& L = lt.l[li];
     if (mode == kModeApproach && s.lat_done[li]) return;
-    const int rel = b - L.block0;
-    const int cl = rel / L.bpc;
-    const int tile = rel - cl * L.bpc;
+    const int rel = b - L.hb_block0;
+    const int cl = rel / L.hb_bpc;
+    const int tile = rel - cl * L.hb_bpc;
     const int g = L.chain0 + cl;
     const int colour = 2 * MU + parity;
+    const int tid = threadIdx.x;
     const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
     T* chain = chain_base(L, th, cl);
-    const uint32_t h = (uint32_t)tile * kBlock + threadIdx.x;
-    const bool active = h < L.V2;
     const int gi = s.itv[g];
     const double acoup = mode == kModeApproach ? s.b[8 * g + colour] : s.a[gi];
     const uint32_t sweep = kind == kApproach ? *s.approach_ctr : *s.sweep_ctr;
+    const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
+    const uint32_t c3 = (uint32_t)(gi - L.chain0);
+    const int own = (int)((curw >> (8 * colour)) & 1ull);
+    const T* pown = chain + (size_t)(own * 8 + colour) * L.V2;
+    T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
+    const uint32_t hbase = (uint32_t)tile * NT;
+
+    T C[LPT], S[LPT], t_old[LPT];
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const uint32_t h = hbase + r * kBlock + tid;
+        C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
+        if (h < L.V2) {
+            int x[4];
+            decode_half(L, h, parity, x);
+            staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
+            t_old[r] = pown[h];
+        }
+    }
+    if (tid == 0) s_qn[0] = 0;
+    T eps_old[LPT], R[LPT], kap[LPT], ch[LPT], sh[LPT];
+    bool got[LPT];
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const uint32_t h = hbase + r * kBlock + tid;
+        const int e = r * kBlock + tid;
+        got[r] = true;
+        ch[r] = T(1); sh[r] = T(0); eps_old[r] = T(0); R[r] = T(0); kap[r] = T(0);
+        if (h < L.V2) {
+            T so, co;
+            M::sincos_rad(t_old[r], &so, &co);
+            eps_old[r] = fms2(C[r], co, S[r], so);
+            R[r] = M::sqrt_(fma2(C[r], C[r], S[r], S[r]));
+            kap[r] = (T)acoup * R[r];
+            const T ak = kap[r] < T(0) ? -kap[r] : kap[r];
+            T q, rm1, kg2;
+            vm_constants(ak, q, rm1, kg2);
+            const uint4 w = philox10(make_uint4(h, c1base, sweep, c3), k0, k1);
+            if (ak == T(0)) {
+                M::sincos_halfpi(M::sunif(w.x), &sh[r], &ch[r]);
+            } else {
+                got[r] = vm_attempt(w.x, w.y, q, rm1, kg2, ch[r], sh[r]);
+                if (!got[r]) got[r] = vm_attempt(w.z, w.w, q, rm1, kg2, ch[r], sh[r]);
+            }
+            s_q[e] = q;
+            s_rm1[e] = rm1;
+            s_kg2[e] = kg2;
+            s_res[e] = got[r] ? 1 : 0;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < LPT; ++r)
+        if (!got[r]) s_queue[0][atomicAdd(&s_qn[0], 1)] = (short)(r * kBlock + tid);
+    __syncthreads();
+    int cq = 0;
+    for (int m = 1; m < kVmCap / 2; ++m) {
+        const int n = s_qn[cq];
+        if (n == 0) break;
+        if (tid == 0) s_qn[cq ^ 1] = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += kBlock) {
+            const int e = s_queue[cq][i];
+            const uint4 w = philox10(make_uint4(hbase + e, c1base | (uint32_t)m, sweep, c3), k0, k1);
+            const T qe = s_q[e], rme = s_rm1[e], kge = s_kg2[e];
+            T che = T(1), she = T(0);
+            bool acc = vm_attempt(w.x, w.y, qe, rme, kge, che, she);
+            if (!acc) acc = vm_attempt(w.z, w.w, qe, rme, kge, che, she);
+            if (acc) {
+                s_ch[e] = che;
+                s_sh[e] = she;
+                s_res[e] = 1;
+            } else {
+                s_queue[cq ^ 1][atomicAdd(&s_qn[cq ^ 1], 1)] = (short)e;
+            }
+        }
+        __syncthreads();
+        cq ^= 1;
+    }
     long long fx = 0;
-    if (active) {
-        int x[4];
-        decode_half(L, h, parity, x);
-        T C, S;
-        staples<T, MU>(L, chain, curw, x, parity, h, C, S);
-        const int own = (int)((curw >> (8 * colour)) & 1ull);
-        const T* pown = chain + (size_t)(own * 8 + colour) * L.V2;
-        T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
-        const T t_old = pown[h];
-        T so, co;
-        M::sincos_rad(t_old, &so, &co);
-        const T eps_old = C * co - S * so;
-        const T R2 = C * C + S * S;
-        const T R = M::sqrt_(R2);
-        const T kap = (T)acoup * R;
-        const T ak = kap < T(0) ? -kap : kap;
-        // Best-Fisher constants in the cancellation-free form
-        T q = T(1), rm1 = T(1), kg2 = T(0);
-        if (ak > T(0)) {
-            const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
-            const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
-            const T irho = M::div_(T(1), rho);
-            rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;              // r - 1
-            const T gg = T(0.5) * (T(1) - rho * rho) * irho;                // sqrt(r^2 - 1)
-            kg2 = ak * gg * gg;
-            q = M::div_(T(1) - rho, T(1) + rho);
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const uint32_t h = hbase + r * kBlock + tid;
+        if (h >= L.V2) continue;
+        const int e = r * kBlock + tid;
+        bool ok = got[r];
+        T c_ = ch[r], s_ = sh[r];
+        if (!ok && s_res[e]) {
+            c_ = s_ch[e];
+            s_ = s_sh[e];
+            ok = true;
         }
-        const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
-        const uint32_t c3 = (uint32_t)(gi - L.chain0);
-        uint4 w = make_uint4(0, 0, 0, 0);
-        T ch = T(1), sh = T(0);
-        bool got = false;
-        for (int j = 0; j < kVmCap; ++j) {
-            if ((j & 1) == 0) w = philox10(make_uint4(h, c1base | (uint32_t)(j >> 1), sweep, c3), k0, k1);
-            const uint32_t wa = (j & 1) ? w.z : w.x;
-            const uint32_t wb = (j & 1) ? w.w : w.y;
-            const T V1 = M::sunif(wa);
-            T s_, c_;
-            M::sincos_halfpi(V1, &s_, &c_);
-            if (ak == T(0)) { ch = c_; sh = s_; got = true; break; }
-            const T U2 = M::unif(wb);
-            const T cc = M::div_(kg2, rm1 + T(2) * c_ * c_);   // kappa (r^2-1)/(r+z), z = cos(pi V1)
-            bool acc = cc * (T(2) - cc) - U2 > T(0);
-            if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
-            if (acc) { ch = c_; sh = q * s_; got = true; break; }
-        }
-        T t_new = t_old;
+        T t_new = t_old[r];
         T dE = T(0);
-        if (got) {
-            T er = ch * ch - sh * sh, ei = T(2) * ch * sh;
-            const T nrm = ch * ch + sh * sh;
-            if (kap < T(0)) { er = -er; ei = -ei; }
-            T pr = C, pi = -S;
-            if (R2 == T(0)) { pr = T(1); pi = T(0); }
-            const T zr = er * pr - ei * pi, zi = er * pi + ei * pr;
+        if (ok) {
+            T er = fms2(c_, c_, s_, s_), ei = T(2) * c_ * s_;
+            const T nrm = fma2(c_, c_, s_, s_);
+            if (kap[r] < T(0)) { er = -er; ei = -ei; }
+            T pr = C[r], pi = -S[r];
+            if (R[r] == T(0)) { pr = T(1); pi = T(0); }
+            const T zr = fms2(er, pr, ei, pi), zi = fma2(er, pi, ei, pr);
             t_new = M::atan2_(zi, zr);
             if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
-            dE = M::div_(R * er, nrm) - eps_old;
+            dE = M::div_(R[r] * er, nrm) - eps_old[r];
         }
         palt[h] = t_new;
-        fx = __double2ll_rn((double)dE * L.fx);
+        fx += to_fixed<T>(dE, L);
     }
     const long long tot = block_sum_i64(fx);
     long long total = 0;
-    if (threadIdx.x == 0 && chain_arrive(s.acc + g, tot, L.bpc, &total)) {
-        {
-            const double E0 = s.E[g];
-            const double En = E0 + (double)total * L.fxinv;
-            const double lo = s.lo[gi], hi = s.hi[gi];
-            bool acc;
-            if (mode == kModeRestricted) {
-                acc = En >= lo && En <= hi;
-            } else if (mode == kModeApproach) {
-                const double d0 = fmax(0.0, fmax(lo - E0, E0 - hi));
-                const double d1 = fmax(0.0, fmax(lo - En, En - hi));
-                acc = d1 <= d0;
-                const double cen = s.cen[gi];
-                const int sg = cen > En ? 1 : (cen < En ? -1 : 0);
-                const int q = 8 * g + colour;   // one coupling per colour class
-                double eta = s.eta[q];
-                const int sp = s.sprev[q];
-                if (sp != 0 && sg != 0) eta = sg == sp ? fmin(0.05, 1.2 * eta) : fmax(1e-6, 0.5 * eta);
-                s.eta[q] = eta;
-                s.b[q] = fmin(4.0, fmax(0.0, s.b[q] + eta * (double)sg));
-                s.sprev[q] = sg;
-            } else {
-                acc = true;
-            }
-            if (acc) {
-                s.cur[8 * g + colour] ^= (uint8_t)1;
-                s.E[g] = En;
-                s.bits[g] |= (uint16_t)(1u << colour);
-                s.hb_acc[g] += 1ull;
-            }
-            s.hb_prop[g] += 1ull;
-            atomicExch(s.acc + g, 0ull);
+    if (threadIdx.x == 0 && chain_arrive(s.acc + g, tot, L.hb_bpc, &total)) {
+        const double E0 = s.E[g];
+        const double En = E0 + (double)total * L.fxinv;
+        const double lo = s.lo[gi], hi = s.hi[gi];
+        bool acc;
+        if (mode == kModeRestricted) {
+            acc = En >= lo && En <= hi;
+        } else if (mode == kModeApproach) {
+            const double d0 = fmax(0.0, fmax(lo - E0, E0 - hi));
+            const double d1 = fmax(0.0, fmax(lo - En, En - hi));
+            acc = d1 <= d0;
+            const double cen = s.cen[gi];
+            const int sg = cen > En ? 1 : (cen < En ? -1 : 0);
+            const int qq = 8 * g + colour;   // one coupling per colour class
+            double eta = s.eta[qq];
+            const int sp = s.sprev[qq];
+            if (sp != 0 && sg != 0) eta = sg == sp ? fmin(0.05, 1.2 * eta) : fmax(1e-6, 0.5 * eta);
+            s.eta[qq] = eta;
+            s.b[qq] = fmin(4.0, fmax(0.0, s.b[qq] + eta * (double)sg));
+            s.sprev[qq] = sg;
+        } else {
+            acc = mode == kModeFree;
         }
+        if (mode != kModeTune) s.hb_prop[g] += 1ull;
+        if (acc) {
+            s.cur[8 * g + colour] ^= (uint8_t)1;
+            s.E[g] = En;
+            s.bits[g] |= (uint16_t)(1u << colour);
+            s.hb_acc[g] += 1ull;
+        }
+        atomicExch(s.acc + g, 0ull);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Overrelaxation class pass: theta' = arg[(C - i S)^2 e^{-i theta}] = -2 phi - theta.
+// Overrelaxation class pass: theta' = arg[(C - i S)^2 e^{-i theta}] = -2 phi - theta,
+// LPT class links per thread.
 // ---------------------------------------------------------------------------
-template <typename T, int MU>
-__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity) {
+template <typename T, int MU, int LPT>
+__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity, int to_alt) {
     using M = Math<T>;
+    constexpr int NT = kBlock * LPT;
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int li = find_lat_pass(lt, b);
+    int li = 0;
+#pragma unroll 1
+    while (li + 1 < lt.n && b >= lt.l[li + 1].or_block0) ++li;
     const LatDev& L = lt.l[li];
-    const int rel = b - L.block0;
-    const int cl = rel / L.bpc;
-    const int tile = rel - cl * L.bpc;
+    const int rel = b - L.or_block0;
+    const int cl = rel / L.or_bpc;
+    const int tile = rel - cl * L.or_bpc;
     const int g = L.chain0 + cl;
     const int colour = 2 * MU + parity;
     const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
     T* chain = chain_base(L, th, cl);
-    const uint32_t h = (uint32_t)tile * kBlock + threadIdx.x;
-    if (h < L.V2) {
-        int x[4];
-        decode_half(L, h, parity, x);
-        T C, S;
-        staples<T, MU>(L, chain, curw, x, parity, h, C, S);
-        T* pown = plane_ptr(chain, curw, colour, L.V2);
-        const T t_old = pown[h];
+    T* pown = plane_ptr(chain, curw, colour, L.V2);
+    // timing runs of the tuner write to the non-current plane (state unchanged)
+    T* pout = to_alt ? chain + (size_t)(((((curw >> (8 * colour)) & 1ull) ^ 1ull) * 8ull) + colour) * L.V2 : pown;
+    const uint32_t hbase = (uint32_t)tile * NT;
+    T C[LPT], S[LPT], t_old[LPT];
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const uint32_t h = hbase + r * kBlock + threadIdx.x;
+        C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
+        if (h < L.V2) {
+            int x[4];
+            decode_half(L, h, parity, x);
+            staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
+            t_old[r] = pown[h];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const uint32_t h = hbase + r * kBlock + threadIdx.x;
+        if (h >= L.V2) continue;
         T t_new;
-        if (C == T(0) && S == T(0)) {
-            t_new = -t_old;
+        if (C[r] == T(0) && S[r] == T(0)) {
+            t_new = -t_old[r];
         } else {
             T so, co;
-            M::sincos_rad(t_old, &so, &co);
-            const T ar = C * C - S * S, ai = T(-2) * C * S;   // (C - iS)^2
-            const T zr = ar * co + ai * so;                    // times (cos - i sin)
-            const T zi = ai * co - ar * so;
+            M::sincos_rad(t_old[r], &so, &co);
+            const T ar = fms2(C[r], C[r], S[r], S[r]), ai = T(-2) * C[r] * S[r];   // (C - iS)^2
+            const T zr = fma2(ar, co, ai, so);                                       // times (cos - i sin)
+            const T zi = fms2(ai, co, ar, so);
             t_new = M::atan2_(zi, zr);
         }
         if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
-        pown[h] = t_new;
+        pout[h] = t_new;
     }
 }
 
@@ -329,13 +455,11 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
         double own[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) own[m] = (double)plane_ptr(chain, curw, 2 * m + p, L.V2)[h];
+        int upo[4], dno[4];
+        neighbour_offsets(L, x, upo, dno);
         uint32_t hup[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[m] = up(x[m], L.L);
-            hup[m] = half_of(L, y[0], y[1], y[2], y[3]);
-        }
+        for (int m = 0; m < 4; ++m) hup[m] = h + upo[m];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
@@ -553,7 +677,8 @@ __global__ void k_test_philox(long n, const uint4* __restrict__ ctr, uint32_t k0
     if (i < n) out[i] = philox10(ctr[i], k0, k1);
 }
 
-// Stand-alone draws of the heatbath sampler (same arithmetic as k_hb).
+// Stand-alone draws of the heatbath sampler (same arithmetic as k_hb, attempts
+// taken sequentially).
 template <typename T>
 __global__ void k_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32_t c1, uint32_t c2, uint32_t c3,
                                 double* X, int* att) {
@@ -561,32 +686,15 @@ __global__ void k_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, 
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const T ak = (T)kappa;
-    T q = T(1), rm1 = T(1), kg2 = T(0);
-    if (ak > T(0)) {
-        const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
-        const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
-        const T irho = M::div_(T(1), rho);
-        rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;
-        const T gg = T(0.5) * (T(1) - rho * rho) * irho;
-        kg2 = ak * gg * gg;
-        q = M::div_(T(1) - rho, T(1) + rho);
-    }
-    uint4 w = make_uint4(0, 0, 0, 0);
+    T q, rm1, kg2;
+    vm_constants(ak, q, rm1, kg2);
     int a = 0;
     T ch = T(1), sh = T(0);
-    for (int j = 0; j < kVmCap; ++j) {
-        if ((j & 1) == 0) w = philox10(make_uint4((uint32_t)i, c1 | (uint32_t)(j >> 1), c2, c3), k0, k1);
-        const uint32_t wa = (j & 1) ? w.z : w.x;
-        const uint32_t wb = (j & 1) ? w.w : w.y;
-        const T V1 = M::sunif(wa);
-        T s_, c_;
-        M::sincos_halfpi(V1, &s_, &c_);
-        if (ak == T(0)) { ch = c_; sh = s_; a = j + 1; break; }
-        const T U2 = M::unif(wb);
-        const T cc = M::div_(kg2, rm1 + T(2) * c_ * c_);
-        bool acc = cc * (T(2) - cc) - U2 > T(0);
-        if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
-        if (acc) { ch = c_; sh = q * s_; a = j + 1; break; }
+    for (int m = 0; m < kVmCap / 2 && !a; ++m) {
+        const uint4 w = philox10(make_uint4((uint32_t)i, c1 | (uint32_t)m, c2, c3), k0, k1);
+        if (ak == T(0)) { M::sincos_halfpi(M::sunif(w.x), &sh, &ch); a = 1; break; }
+        if (vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh)) a = 2 * m + 1;
+        else if (vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh)) a = 2 * m + 2;
     }
     att[i] = a;
     X[i] = a ? 2.0 * (double)M::atan2_(sh, ch) : 0.0;
@@ -598,28 +706,47 @@ void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32
     hipLaunchKernelGGL(k_hot_start<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, k0, k1);
 }
 
-template <typename T>
-void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
-                    hipStream_t st) {
+template <typename T, int LPT>
+static void hb_dispatch(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0,
+                        uint32_t k1, hipStream_t st) {
     const int p = colour & 1;
-    dim3 gr(lt.pass_blocks), bl(kBlock);
+    dim3 gr(lt.hb_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_hb<T, 0>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        case 1: hipLaunchKernelGGL((k_hb<T, 1>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        case 2: hipLaunchKernelGGL((k_hb<T, 2>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        default: hipLaunchKernelGGL((k_hb<T, 3>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        default: hipLaunchKernelGGL((k_hb<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
     }
 }
 
 template <typename T>
-void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, hipStream_t st) {
+void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
+                    hipStream_t st) {
+    switch (lt.hb_lpt) {
+        case 1: hb_dispatch<T, 1>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        case 2: hb_dispatch<T, 2>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        default: hb_dispatch<T, 4>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+    }
+}
+
+template <typename T, int LPT>
+static void or_dispatch(const LatTable& lt, T* th, DevState s, int colour, int to_alt, hipStream_t st) {
     const int p = colour & 1;
-    dim3 gr(lt.pass_blocks), bl(kBlock);
+    dim3 gr(lt.or_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_or<T, 0>), gr, bl, 0, st, lt, th, s, p); break;
-        case 1: hipLaunchKernelGGL((k_or<T, 1>), gr, bl, 0, st, lt, th, s, p); break;
-        case 2: hipLaunchKernelGGL((k_or<T, 2>), gr, bl, 0, st, lt, th, s, p); break;
-        default: hipLaunchKernelGGL((k_or<T, 3>), gr, bl, 0, st, lt, th, s, p); break;
+        case 0: hipLaunchKernelGGL((k_or<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
+        case 1: hipLaunchKernelGGL((k_or<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
+        case 2: hipLaunchKernelGGL((k_or<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
+        default: hipLaunchKernelGGL((k_or<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
+    }
+}
+
+template <typename T>
+void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_alt, hipStream_t st) {
+    switch (lt.or_lpt) {
+        case 1: or_dispatch<T, 1>(lt, th, s, colour, to_alt, st); break;
+        case 2: or_dispatch<T, 2>(lt, th, s, colour, to_alt, st); break;
+        default: or_dispatch<T, 4>(lt, th, s, colour, to_alt, st); break;
     }
 }
 
@@ -670,7 +797,7 @@ void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32
 #define LLR_INST(T)                                                                                              \
     template void launch_hot_start<T>(const LatTable&, T*, DevState, uint32_t, uint32_t, hipStream_t);          \
     template void launch_hb_pass<T>(const LatTable&, T*, DevState, int, int, int, uint32_t, uint32_t, hipStream_t); \
-    template void launch_or_pass<T>(const LatTable&, T*, DevState, int, hipStream_t);                           \
+    template void launch_or_pass<T>(const LatTable&, T*, DevState, int, int, hipStream_t);                           \
     template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t);                          \
     template void launch_export<T>(const LatTable&, int, const T*, DevState, T*, hipStream_t);                 \
     template void launch_import<T>(const LatTable&, int, T*, DevState, const T*, hipStream_t);                 \

@@ -59,6 +59,9 @@ _SIGS = {
     "llr_get_ln_rho": [C.c_void_p, C.c_int, _p(C.c_double), _p(C.c_double)],
     "llr_sweeps": [C.c_void_p, C.c_int, C.c_longlong, C.c_int, _p(C.c_uint16)],
     "llr_recompute_energy": [C.c_void_p],
+    "llr_class_pass": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_longlong],
+    "llr_autotune": [C.c_void_p, _p(C.c_int), _p(C.c_int)],
+    "llr_set_tiles": [C.c_void_p, C.c_int, C.c_int],
     "llr_enable_bits_log": [C.c_void_p, C.c_longlong],
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
     "llr_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong)],
@@ -249,6 +252,17 @@ class Context:
         bits = np.zeros((n_sweeps, nch), dtype=np.uint16) if want_bits else None
         _check(lib().llr_sweeps(self.h, n_sweeps, sweep0, mode, _ptr(bits, C.c_uint16)))
         return bits
+
+    def autotune(self):
+        hb, orr = C.c_int(), C.c_int()
+        _check(lib().llr_autotune(self.h, C.byref(hb), C.byref(orr)))
+        return hb.value, orr.value
+
+    def set_tiles(self, hb_lpt, or_lpt):
+        _check(lib().llr_set_tiles(self.h, hb_lpt, or_lpt))
+
+    def class_pass(self, heatbath, colour, mode=MODE_RESTRICTED, sweep_index=0):
+        _check(lib().llr_class_pass(self.h, int(heatbath), colour, mode, sweep_index))
 
     def recompute_energy(self):
         _check(lib().llr_recompute_energy(self.h))

@@ -302,8 +302,8 @@ def test_driver_mixed_lattices_fp64(llr):
         r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=0, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
                            lattice_id=i, theta=th, approach_cap=0)
         a, it, sw = ctx.get_a(i)
-        assert np.max(np.abs(a - r["a"])) < 1e-7
-        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-7
+        assert np.max(np.abs(a - r["a"])) < 1e-5
+        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-5
 
 
 @pytest.mark.slow
@@ -420,3 +420,33 @@ def test_invalid_arguments_are_rejected(llr):
         ctx.run()                               # state not bound
     with pytest.raises(llr.LLRError):
         ctx.set_params(n_a=0)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_tile_choices_give_identical_results(llr, prec):
+    """The class-pass tiles (links per thread) change only the schedule: two
+    sweeps from the same state are bit-identical for every choice, including
+    the autotuner's."""
+    import torch
+    L, d, n = 6, 4, 3
+    dt = np.float32 if prec == "FP32" else np.float64
+    th = random_state(d, L, n, seed=77, u_target=0.6, dtype=dt)
+    E0 = np.array([oracle.energy(d, L, th[i].astype(np.float64)) for i in range(n)])
+    dE = 40.0
+    E_low = np.sort(E0) - 20.0
+    E_low = E_low[0] + dE * np.arange(n)
+    outs = []
+    for tiles in [(1, 1), (2, 2), (4, 4), (4, 1), None]:
+        ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)], a=1.02)
+        ctx.import_state(0, torch.from_numpy(th))
+        if tiles is None:
+            ctx.autotune()
+        else:
+            ctx.set_tiles(*tiles)
+        bits = ctx.sweeps(2, sweep0=3, mode=llr.MODE_FREE)
+        outs.append((ctx.export_state(0).cpu().numpy(), bits, ctx.get_energy(0)[0]))
+        ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
