@@ -173,6 +173,14 @@ llr_status llr_sweeps(llr_ctx *ctx, int n_sweeps, long long sweep0, int mode, ui
  * llr_set_tiles fixes them.  Results are bit-identical for every choice. */
 llr_status llr_autotune(llr_ctx *ctx, int *hb_lpt, int *or_lpt);
 llr_status llr_set_tiles(llr_ctx *ctx, int hb_lpt, int or_lpt);
+/* Block order of the class passes: serpentine != 0 (default) walks the chains
+ * in reverse order on odd-parity colours, so a pass starts on the data the
+ * previous pass touched last (Infinity Cache reuse); 0 keeps one order.
+ * Results do not depend on it. */
+llr_status llr_set_order(llr_ctx *ctx, int serpentine);
+/* on != 0 (default): the sweeps of llr_run / llr_rm_step are captured once per
+ * variant into HIP graphs and replayed (not while per-kernel timing is on). */
+llr_status llr_set_graphs(llr_ctx *ctx, int on);
 /* One class pass of every chain: heatbath (heatbath != 0, acceptance by mode,
  * counters with sweep index sweep_index) or overrelaxation of colour c. */
 llr_status llr_class_pass(llr_ctx *ctx, int heatbath, int colour, int mode, long long sweep_index);
@@ -185,9 +193,11 @@ llr_status llr_get_bits_log(llr_ctx *ctx, uint16_t *bits, long long *rows);
  * heatbath proposals/accepts; replica-exchange proposals/accepts (scalars). */
 llr_status llr_stats(llr_ctx *ctx, long long *hb_prop, long long *hb_acc, long long *re_prop,
                      long long *re_acc);
-/* Per-kernel timing with HIP events on the context stream: on/off, and the
+/* Kernel timing with HIP events on the context stream: on/off, and the
  * summed duration (ms) and count of heatbath-pass, overrelaxation-pass and
- * energy launches since enabling. */
+ * energy launches since enabling.  The 8 heatbath (and the 8
+ * overrelaxation) launches of a sweep share one event pair, so the average
+ * per launch includes the short gaps between consecutive launches. */
 llr_status llr_set_timing(llr_ctx *ctx, int on);
 llr_status llr_get_timing(llr_ctx *ctx, double *hb_ms, long long *hb_n, double *or_ms,
                           long long *or_n, double *en_ms, long long *en_n);

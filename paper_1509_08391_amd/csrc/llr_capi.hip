@@ -41,7 +41,8 @@ struct HostLat {
 
 struct TimingPair {
     hipEvent_t a, b;
-    int kind;  // 0 hb, 1 or, 2 energy
+    int kind;   // 0 hb, 1 or, 2 energy
+    int count;  // launches between the two events
 };
 
 struct llr_ctx {
@@ -62,6 +63,10 @@ struct llr_ctx {
     bool ap_open = false;
     int rm_done = 0;       // RM iterations performed since llr_rm_begin
     bool tuned = false;    // class-pass tiles chosen (autotuner or llr_set_tiles)
+    // captured sweeps (kernel nodes only), keyed by recompute | replica << 1 | measure << 2
+    bool use_graphs = true;
+    hipGraphExec_t sweep_graph[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;  // default priority
     bool rm_open = false;
     // timing
     bool timing = false;
@@ -127,6 +132,11 @@ static llr_status upload_intervals(llr_ctx* c) {
     return LLR_OK;
 }
 
+static void drop_graphs(llr_ctx* c) {
+    for (auto& g : c->sweep_graph)
+        if (g) { hipGraphExecDestroy(g); g = nullptr; }
+}
+
 // Block tables of the class-pass launches for hb_lpt / or_lpt class links per thread.
 static void set_tiles(LatTable& lt, int hb_lpt, int or_lpt) {
     lt.hb_lpt = hb_lpt;
@@ -178,6 +188,7 @@ static llr_status layout(llr_ctx* c) {
         base += (long long)h.n * 8 * V;
     }
     lt.site_blocks = eblock0;
+    lt.serpentine = 1;
     set_tiles(lt, 1, 1);
     lt.n_chains = chain0;
     c->state_bytes = (size_t)base * elem_size(c);
@@ -220,18 +231,20 @@ static void harvest(llr_ctx* c) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->t_ms[p.kind] += ms;
-            c->t_n[p.kind] += 1;
+            c->t_n[p.kind] += p.count;
         }
         c->pool.push_back(p.a);
         c->pool.push_back(p.b);
     }
     c->pending.clear();
 }
+// Event pair around `count` consecutive launches of one kernel kind.
 struct TimeScope {
     llr_ctx* c;
     int kind;
+    int count;
     hipEvent_t a{}, b{};
-    TimeScope(llr_ctx* cc, int k) : c(cc), kind(k) {
+    TimeScope(llr_ctx* cc, int k, int n = 1) : c(cc), kind(k), count(n) {
         if (c->timing) {
             a = ev_get(c);
             b = ev_get(c);
@@ -241,7 +254,7 @@ struct TimeScope {
     ~TimeScope() {
         if (c->timing) {
             hipEventRecord(b, c->stream);
-            c->pending.push_back({a, b, kind});
+            c->pending.push_back({a, b, kind, count});
             if (c->pending.size() >= 2048) {
                 hipEventSynchronize(b);
                 harvest(c);
@@ -253,13 +266,11 @@ struct TimeScope {
 // ---------------------------------------------------------------- sweep drivers
 template <typename T>
 static void enqueue_hb_pass(llr_ctx* c, int colour, int mode, int kind) {
-    TimeScope ts(c, 0);
     launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, colour, mode, kind, (uint32_t)c->prm.seed,
                       (uint32_t)(c->prm.seed >> 32), c->stream);
 }
 template <typename T>
 static void enqueue_or_pass(llr_ctx* c, int colour) {
-    TimeScope ts(c, 1);
     launch_or_pass<T>(c->lt, (T*)c->state, c->ds, colour, 0, c->stream);
 }
 template <typename T>
@@ -271,11 +282,52 @@ static void enqueue_energy(llr_ctx* c) {
 // one restricted sweep of all chains, then recompute / replica exchange / measurement
 template <typename T>
 static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bool measure) {
-    for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, mode, kSweep);
-    for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
+    {
+        TimeScope ts(c, 0, 8);
+        for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, mode, kSweep);
+    }
+    {
+        TimeScope ts(c, 1, 8);
+        for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
+    }
     if (recompute) enqueue_energy<T>(c);
     if (replica) launch_replica(c->lt, c->ds, (uint32_t)c->prm.seed, (uint32_t)(c->prm.seed >> 32), c->stream);
     launch_end_sweep(c->lt, c->ds, measure ? 1 : 0, 0, 1, c->stream);
+}
+
+// One restricted sweep of the Robbins-Monro loop.  Without per-kernel timing
+// the 18-20 launches of a sweep are captured once per variant into a HIP graph
+// (kernel nodes only) and replayed; the sweep index lives in device memory, so
+// every replay advances it.
+template <typename T>
+static llr_status launch_sweep(llr_ctx* c, bool recompute, bool replica, bool measure) {
+    if (!c->use_graphs || c->timing) {
+        enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, recompute, replica, measure);
+        return LLR_OK;
+    }
+    const int key = (recompute ? 1 : 0) | (replica ? 2 : 0) | (measure ? 4 : 0);
+    if (!c->sweep_graph[key]) {
+        // capture on a library-owned stream (the caller's may be the null
+        // stream, which cannot be captured); the graph runs on the caller's
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e0 = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e0 == hipSuccess) {
+            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, recompute, replica, measure);
+            e0 = hipStreamEndCapture(c->stream, &g);
+        }
+        c->stream = user;
+        if (e0 != hipSuccess) return fail(LLR_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e0));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LLR_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        c->sweep_graph[key] = ex;
+    }
+    HIPCHK(hipGraphLaunch(c->sweep_graph[key], c->stream));
+    return LLR_OK;
 }
 
 template <typename T>
@@ -300,7 +352,7 @@ static llr_status autotune_impl(llr_ctx* c) {
     c->timing = false;
     for (int ci = 0; ci < 3; ++ci) {
         set_tiles(c->lt, cand[ci], cand[ci]);
-        for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+        for (int rep = 0; rep < 4; ++rep) {   // first repetition warms up; minimum of the others
             HIPCHK(hipEventRecord(e0, c->stream));
             for (int col = 0; col < 8; ++col)
                 launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, 3, kSweep, (uint32_t)c->prm.seed,
@@ -309,16 +361,17 @@ static llr_status autotune_impl(llr_ctx* c) {
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (rep == 1 && ms < best_hb) { best_hb = ms; bh = cand[ci]; }
+            if (rep > 0 && ms < best_hb) { best_hb = ms; bh = cand[ci]; }
             HIPCHK(hipEventRecord(e0, c->stream));
             for (int col = 0; col < 8; ++col) launch_or_pass<T>(c->lt, (T*)c->state, c->ds, col, 1, c->stream);
             HIPCHK(hipEventRecord(e1, c->stream));
             HIPCHK(hipEventSynchronize(e1));
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (rep == 1 && ms < best_or) { best_or = ms; bo = cand[ci]; }
+            if (rep > 0 && ms < best_or) { best_or = ms; bo = cand[ci]; }
         }
     }
     set_tiles(c->lt, bh, bo);
+    drop_graphs(c);
     c->timing = was_timing;
     HIPCHK(hipEventDestroy(e0));
     HIPCHK(hipEventDestroy(e1));
@@ -434,10 +487,12 @@ static llr_status rm_step_impl(llr_ctx* c, int iters) {
     const int K = std::max(1, p.recompute_every);
     const int nsw = p.n_th + p.n_a;
     RunCfg cfg{(uint32_t)p.seed, (uint32_t)(p.seed >> 32), p.n_a, nsw, p.eps};
+    llr_status st = LLR_OK;
     for (int it = 0; it < iters; ++it) {
         for (int j = 0; j < nsw; ++j) {
             const bool rec = ((j + 1) % K == 0) || (j == nsw - 1);
-            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, rec, p.replica_exchange != 0, j >= p.n_th);
+            st = launch_sweep<T>(c, rec, p.replica_exchange != 0, j >= p.n_th);
+            if (st != LLR_OK) return st;
             if ((j & 255) == 255) HIPCHK(hipStreamSynchronize(c->stream));   // bound the queue depth
         }
         launch_rm_update(c->lt, c->ds, cfg, c->stream);
@@ -517,6 +572,8 @@ void llr_destroy(llr_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
     for (void* p : c->allocs) hipFree(p);
@@ -531,6 +588,7 @@ llr_status llr_set_params(llr_ctx* c, const llr_params* p) {
         return fail(LLR_EINVAL, "invalid parameters");
     const bool width_changed = c->laid_out && (p->replica_exchange != c->prm.replica_exchange || p->overlap != c->prm.overlap);
     c->prm = *p;
+    drop_graphs(c);
     if (width_changed) return upload_intervals(c);
     return LLR_OK;
 }
@@ -575,6 +633,7 @@ llr_status llr_bind_state(llr_ctx* c, void* dev_state, size_t bytes) {
     if (st != LLR_OK) return st;
     if (bytes != c->state_bytes) return fail(LLR_EINVAL, "state buffer size differs from llr_state_bytes");
     if (((uintptr_t)dev_state) & 255) return fail(LLR_EINVAL, "state buffer must be 256-byte aligned");
+    drop_graphs(c);
     c->state = dev_state;
     c->have_energy = false;
     return LLR_OK;
@@ -704,11 +763,26 @@ llr_status llr_autotune(llr_ctx* c, int* hb_lpt, int* or_lpt) {
     return LLR_OK;
 }
 
+llr_status llr_set_graphs(llr_ctx* c, int on) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    c->use_graphs = on != 0;
+    drop_graphs(c);
+    return LLR_OK;
+}
+
+llr_status llr_set_order(llr_ctx* c, int serpentine) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "lay out the lattices first");
+    c->lt.serpentine = serpentine ? 1 : 0;
+    drop_graphs(c);
+    return LLR_OK;
+}
+
 llr_status llr_set_tiles(llr_ctx* c, int hb_lpt, int or_lpt) {
     if (!c || !c->laid_out) return fail(LLR_ESTATE, "lay out the lattices first");
     auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
     if (!ok(hb_lpt) || !ok(or_lpt)) return fail(LLR_EINVAL, "links per thread must be 1, 2 or 4");
     set_tiles(c->lt, hb_lpt, or_lpt);
+    drop_graphs(c);
     c->tuned = true;
     return LLR_OK;
 }
@@ -822,6 +896,7 @@ llr_status llr_enable_bits_log(llr_ctx* c, long long max_rows) {
         c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->ds.bits_log), c->allocs.end());
         c->ds.bits_log = nullptr;
     }
+    drop_graphs(c);
     c->ds.bits_rows_max = max_rows;
     if (max_rows > 0) {
         llr_status st = dalloc(c, &c->ds.bits_log, (size_t)max_rows * c->lt.n_chains);

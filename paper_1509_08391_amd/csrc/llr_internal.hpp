@@ -31,6 +31,7 @@ struct LatTable {
     LatDev l[kMaxLat];
     int n;
     int hb_lpt, or_lpt;    // class links per thread (1, 2 or 4), chosen by the autotuner
+    int serpentine;        // odd-parity colours walk the blocks in reverse order (cache reuse)
     int hb_blocks;         // total blocks of a heatbath / overrelaxation launch
     int or_blocks;
     int site_blocks;       // total blocks of a site launch

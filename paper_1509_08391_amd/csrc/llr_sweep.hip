@@ -207,14 +207,15 @@ __device__ __forceinline__ long long to_fixed<float>(float v, const LatDev& L) {
 // ---------------------------------------------------------------------------
 template <typename T, int MU, int LPT>
 __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
-                                               int kind, uint32_t k0, uint32_t k1) {
+                                               int kind, uint32_t k0, uint32_t k1, int reverse) {
     using M = Math<T>;
     constexpr int NT = kBlock * LPT;
     __shared__ T s_q[NT], s_rm1[NT], s_kg2[NT], s_ch[NT], s_sh[NT];
     __shared__ unsigned char s_res[NT];
     __shared__ short s_queue[2][NT];
     __shared__ int s_qn[2];
-    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int b = reverse ? (int)gridDim.x - 1 - b0 : b0;
     int li = 0;
 #pragma unroll 1
     while (li + 1 < lt.n && b >= lt.l[li + 1].hb_block0) ++li;
@@ -380,10 +381,12 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
 // LPT class links per thread.
 // ---------------------------------------------------------------------------
 template <typename T, int MU, int LPT>
-__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity, int to_alt) {
+__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity, int to_alt,
+                                               int reverse) {
     using M = Math<T>;
     constexpr int NT = kBlock * LPT;
-    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int b = reverse ? (int)gridDim.x - 1 - b0 : b0;
     int li = 0;
 #pragma unroll 1
     while (li + 1 < lt.n && b >= lt.l[li + 1].or_block0) ++li;
@@ -710,12 +713,13 @@ template <typename T, int LPT>
 static void hb_dispatch(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0,
                         uint32_t k1, hipStream_t st) {
     const int p = colour & 1;
+    const int rv = lt.serpentine ? p : 0;
     dim3 gr(lt.hb_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
-        default: hipLaunchKernelGGL((k_hb<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1); break;
+        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        default: hipLaunchKernelGGL((k_hb<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
     }
 }
 
@@ -732,12 +736,13 @@ void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode,
 template <typename T, int LPT>
 static void or_dispatch(const LatTable& lt, T* th, DevState s, int colour, int to_alt, hipStream_t st) {
     const int p = colour & 1;
+    const int rv = lt.serpentine ? p : 0;
     dim3 gr(lt.or_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_or<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
-        case 1: hipLaunchKernelGGL((k_or<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
-        case 2: hipLaunchKernelGGL((k_or<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
-        default: hipLaunchKernelGGL((k_or<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt); break;
+        case 0: hipLaunchKernelGGL((k_or<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt, rv); break;
+        case 1: hipLaunchKernelGGL((k_or<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt, rv); break;
+        case 2: hipLaunchKernelGGL((k_or<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt, rv); break;
+        default: hipLaunchKernelGGL((k_or<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, to_alt, rv); break;
     }
 }
 

@@ -62,6 +62,8 @@ _SIGS = {
     "llr_class_pass": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_longlong],
     "llr_autotune": [C.c_void_p, _p(C.c_int), _p(C.c_int)],
     "llr_set_tiles": [C.c_void_p, C.c_int, C.c_int],
+    "llr_set_order": [C.c_void_p, C.c_int],
+    "llr_set_graphs": [C.c_void_p, C.c_int],
     "llr_enable_bits_log": [C.c_void_p, C.c_longlong],
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
     "llr_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong)],
@@ -257,6 +259,12 @@ class Context:
         hb, orr = C.c_int(), C.c_int()
         _check(lib().llr_autotune(self.h, C.byref(hb), C.byref(orr)))
         return hb.value, orr.value
+
+    def set_graphs(self, on):
+        _check(lib().llr_set_graphs(self.h, int(on)))
+
+    def set_order(self, serpentine):
+        _check(lib().llr_set_order(self.h, int(serpentine)))
 
     def set_tiles(self, hb_lpt, or_lpt):
         _check(lib().llr_set_tiles(self.h, hb_lpt, or_lpt))

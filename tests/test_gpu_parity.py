@@ -450,3 +450,34 @@ def test_tile_choices_give_identical_results(llr, prec):
         assert np.array_equal(o[0], outs[0][0])
         assert np.array_equal(o[1], outs[0][1])
         assert np.array_equal(o[2], outs[0][2])
+
+
+@pytest.mark.parametrize("replica", [False, True])
+def test_graph_replays_match_eager_launches(llr, replica):
+    """The captured sweep graphs replayed over several RM iterations (with the
+    host's own synchronising reads between iterations) give results
+    bit-identical to direct launches."""
+    import torch
+    L = 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.55 * V6 + dE * np.arange(8)
+    th = _states_in_intervals(L, E_low, dE, seed=9)
+    out = []
+    for graphs in (False, True):
+        ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], n_th=3, n_a=7, n_rm=4, recompute_every=4,
+                   replica_exchange=replica)
+        ctx.set_graphs(graphs)
+        ctx.enable_bits_log(200)
+        ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
+        ctx.set_tiles(4, 2)
+        ctx.rm_begin()
+        hist = []
+        for it in range(4):
+            ctx.rm_step(1)
+            hist.append(ctx.get_energy(0)[0].copy())
+        a, _, _ = ctx.get_a(0)
+        out.append((a, np.array(hist), ctx.get_bits_log(), ctx.export_state(0).cpu().numpy()))
+        ctx.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
