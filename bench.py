@@ -31,9 +31,10 @@ N_INT = 128
 SEED = 1509083910
 PEAK_HBM_GBS = 8000.0
 # Calibrated HBM bytes per heatbath launch (FETCH_SIZE x 2 + WRITE_SIZE x 1,
-# rocprofv3 on this kernel version, profiles/k_hb_L20x128_fp32_counters.md);
-# None once the kernel changes until the counters are taken again.
-HB_TRAFFIC_BYTES_FP32 = None
+# rocprofv3 on this kernel version with 4 class links per thread,
+# profiles/k_hb_L20x128_fp32_counters.md); None once the kernel changes until
+# the counters are taken again.
+HB_TRAFFIC = {("fp32", 4): 375.5e6}
 
 
 def cpu_baseline(target_s=12.0):
@@ -171,11 +172,11 @@ def main():
         "config": {"workload": "LLR 4D compact U(1), L=20, 128 intervals u in [0.60,0.664], dE=480, "
                                "replica exchange (w=2dE), N_TH=500, N_A=2000; step = one Robbins-Monro "
                                "iteration (2500 sweeps) + beta_c reconstruction",
-                   "L": L, "intervals": N_INT, "sweeps_per_step": nsw,
+                   "L": L, "intervals": N_INT, "sweeps_per_step": nsw, "tiles": list(tiles),
                    "precision": "fp32 angles, fp64 energy/test/RM" if prec == llr.FP32 else "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": HB_TRAFFIC_BYTES_FP32 if prec == llr.FP32 else None,
+                     "traffic": HB_TRAFFIC.get((args.precision, tiles[0])),
                      "kernel": "heatbath class pass (k_hb)",
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
                      "overrelaxation_avg_launch_us": or_avg_s * 1e6},
