@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 on this kernel version with 4 class links per thread,
 # profiles/k_hb_L20x128_fp32_counters.md); None once the kernel changes until
 # the counters are taken again.
-HB_TRAFFIC = {("fp32", 4): 375.5e6}
+HB_TRAFFIC = {("fp32", 4): 374.0e6}
 
 
 def cpu_baseline(target_s=12.0):
@@ -79,7 +79,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the chains of this workload are "
-              f"independent and one MI355X holds all of them; see DESIGN.md for how it would shard.",
+              f"independent between replica exchanges and one MI355X holds all 128 of them.",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -125,6 +125,9 @@ def main():
         if ap_sweeps[0] >= 20000:
             raise SystemExit("approach did not finish within 20000 sweeps")
     t_setup = time.perf_counter() - t_setup
+    tiles = ctx.autotune()
+    print(f"# autotuned class links per thread: heatbath {tiles[0]}, overrelaxation {tiles[1]}",
+          file=sys.stderr, flush=True)
     ctx.rm_begin()
     centres = E_low + 0.5 * dE
     for w in range(args.warmup):

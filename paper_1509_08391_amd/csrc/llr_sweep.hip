@@ -54,6 +54,19 @@ __device__ __forceinline__ T* plane_ptr(T* chain, uint64_t curw, int c, uint32_t
     return chain + (size_t)((((curw >> (8 * c)) & 1ull) * 8ull) + (uint64_t)c) * V2;
 }
 
+// Element i of a plane through a 32-bit byte offset: the plane base is uniform
+// (scalar registers) and every plane is < 4 GiB, so the access compiles to a
+// global load/store with a scalar base and one 32-bit vector offset instead
+// of a 64-bit vector address per access.
+template <typename T>
+__device__ __forceinline__ T ld_plane(const T* plane, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_plane(T* plane, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + i * (uint32_t)sizeof(T)) = v;
+}
+
 // Half-index offsets of the neighbours of site x along each direction:
 // up[nu] = h(x + nu) - h(x), dn[nu] = h(x - nu) - h(x), periodic.  Sites
 // (2j, 2j+1) along x0 share a half index, so the x0 offsets depend on x0's
@@ -95,12 +108,12 @@ __device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_
         const uint32_t h_pnu = h + up[NU];
         const uint32_t h_mnu = h + dn[NU];
         const uint32_t h_pmu_mnu = h + up[MU] + dn[NU];
-        const T t_nu_pmu = pnu_q[h_pmu];
-        const T t_mu_pnu = pmu_q[h_pnu];
-        const T t_nu_x = pnu_p[h];
-        const T t_nu_pmu_mnu = pnu_p[h_pmu_mnu];
-        const T t_mu_mnu = pmu_q[h_mnu];
-        const T t_nu_mnu = pnu_q[h_mnu];
+        const T t_nu_pmu = ld_plane(pnu_q, h_pmu);
+        const T t_mu_pnu = ld_plane(pmu_q, h_pnu);
+        const T t_nu_x = ld_plane(pnu_p, h);
+        const T t_nu_pmu_mnu = ld_plane(pnu_p, h_pmu_mnu);
+        const T t_mu_mnu = ld_plane(pmu_q, h_mnu);
+        const T t_nu_mnu = ld_plane(pnu_q, h_mnu);
         const T sf = t_nu_pmu - t_mu_pnu - t_nu_x;
         const T sb = t_nu_mnu - t_nu_pmu_mnu - t_mu_mnu;
         T s1, c1, s2, c2;
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             int x[4];
             decode_half(L, h, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
-            t_old[r] = pown[h];
+            t_old[r] = ld_plane(pown, h);
         }
     }
     if (tid == 0) s_qn[0] = 0;
@@ -337,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
             dE = M::div_(R[r] * er, nrm) - eps_old[r];
         }
-        palt[h] = t_new;
+        st_plane(palt, h, t_new);
         fx += to_fixed<T>(dE, L);
     }
     const long long tot = block_sum_i64(fx);
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
             int x[4];
             decode_half(L, h, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
-            t_old[r] = pown[h];
+            t_old[r] = ld_plane(pown, h);
         }
     }
 #pragma unroll
@@ -430,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
             t_new = M::atan2_(zi, zr);
         }
         if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
-        pout[h] = t_new;
+        st_plane(pout, h, t_new);
     }
 }
 
@@ -457,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
         decode_half(L, h, p, x);
         double own[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) own[m] = (double)plane_ptr(chain, curw, 2 * m + p, L.V2)[h];
+        for (int m = 0; m < 4; ++m) own[m] = (double)ld_plane(plane_ptr(chain, curw, 2 * m + p, L.V2), h);
         int upo[4], dno[4];
         neighbour_offsets(L, x, upo, dno);
         uint32_t hup[4];
@@ -467,8 +480,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
         for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
             for (int nu = mu + 1; nu < 4; ++nu) {
-                const double t_nu_pmu = (double)plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2)[hup[mu]];
-                const double t_mu_pnu = (double)plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2)[hup[nu]];
+                const double t_nu_pmu = (double)ld_plane(plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2), hup[mu]);
+                const double t_mu_pnu = (double)ld_plane(plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2), hup[nu]);
                 const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
                 fx += __double2ll_rn(cos(ang) * L.fx);
             }

@@ -1,0 +1,220 @@
+"""Runs of Algorithm 1 on the configurations the method is measured on.
+
+  config1  L=8, 32 intervals from u = 0.55, dE = 0.005 6V, N_TH = 200,
+           N_A = 500, N_RM = 50, a^(0) = 1; once in FP64 and once with FP32
+           angles; <u>(beta), C_V(beta) on beta in [0.98, 1.04].
+  config2  L = 12, 16, 20 batched in one launch, 64 intervals each over
+           u in [0.58, 0.68], replica exchange after every sweep, FP32,
+           N_TH = 200, N_A = 1000, N_RM = 100.
+  config3  warm start: the network a(u, 1/L) trained on the converged a_k of
+           config1 (L=8) and config2 (L=12, 16), predicting the L=20 interval
+           set of config4; Robbins-Monro from the prediction and from
+           a^(0) = 1, compared by the sweeps until |a^(n+1) - a^(n)| < 1e-4.
+  config4  L = 20, 128 intervals from u = 0.60, dE = 0.0005 6V, warm start,
+           replica exchange, FP32, N_TH = 500, N_A = 2000, N_RM = 100;
+           ln rho, C_V(beta) on beta in [1.008, 1.012], beta_c and peak.
+
+Each writes a JSON record.  Usage:
+    python -m paper_1509_08391_amd.experiments config1 [--out DIR]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import llr
+
+SEED = 1509083910
+
+
+def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None, eps=1e-4):
+    """lattices: list of (L, E_low, dE).  a0: list of per-lattice arrays or None."""
+    ctx = llr.Context(precision=prec, device=0)
+    ctx.set_params(n_th=n_th, n_a=n_a, n_rm=n_rm, seed=seed, replica_exchange=replica, overlap=1.0,
+                   recompute_every=10, eps=eps, approach_cap=20000)
+    for (L, E_low, dE) in lattices:
+        ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    for i, (L, E_low, dE) in enumerate(lattices):
+        ctx.set_a(i, 1.0 if a0 is None else a0[i])
+    t0 = time.perf_counter()
+    ctx.hot_start()
+    ctx.approach_begin()
+    done = False
+    while not done:
+        ap, done = ctx.approach_continue(100)
+        if ap.max() >= 20000:
+            raise RuntimeError("approach did not finish")
+    t_ap = time.perf_counter() - t0
+    tiles = ctx.autotune()
+    ctx.rm_begin()
+    t1 = time.perf_counter()
+    for it in range(n_rm):
+        ctx.rm_step(1)
+        if log and (it % 10 == 9 or it == n_rm - 1):
+            log(f"RM iteration {it + 1}/{n_rm}, {time.perf_counter() - t1:.1f} s")
+    t_rm = time.perf_counter() - t1
+    out = []
+    for i, (L, E_low, dE) in enumerate(lattices):
+        a, conv, sw = ctx.get_a(i)
+        hist = ctx.get_history(i)
+        E, conf = ctx.get_energy(i)
+        out.append(dict(L=L, E_low=np.asarray(E_low).tolist(), dE=dE, a=a.tolist(), conv_iter=conv.tolist(),
+                        conv_sweeps=sw.tolist(), a_hist=hist.tolist(), approach_sweeps=int(ap[i]),
+                        E=E.tolist()))
+    hp, ha, rp, ra = ctx.stats()
+    nsw = n_th + n_a
+    upd = sum(2 * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lattices) * nsw * n_rm
+    meta = dict(precision="fp32" if prec == llr.FP32 else "fp64", n_th=n_th, n_a=n_a, n_rm=n_rm, replica=replica,
+                seed=seed, seconds_approach=t_ap, seconds_rm=t_rm, updates_per_s=upd / t_rm, tiles=list(tiles),
+                hb_acceptance=float(ha.sum() / max(hp.sum(), 1)),
+                re_acceptance=float(ra / max(rp, 1)) if replica else None)
+    ctx.close()
+    return out, meta
+
+
+def _reconstruct(L, E_low, dE, a, blo, bhi, nb=61):
+    ctx = llr.Context(precision=llr.FP64, device=0)
+    V6 = 6 * L ** 4
+    cen = np.asarray(E_low) + 0.5 * dE
+    beta = np.linspace(blo, bhi, nb)
+    lr, u, cv = ctx.reconstruct(cen, a, dE, V6, beta)
+    bc, pk = ctx.beta_c(cen, a, dE, V6, blo, bhi, h=1e-5, tol=1e-9)
+    ctx.close()
+    return dict(beta=beta.tolist(), u_mean=u.tolist(), cv=cv.tolist(), ln_rho=lr.tolist(), beta_c=bc,
+                cv_peak=pk, cv_peak_over_6v=pk / V6)
+
+
+def config1(log, replicas=8):
+    """The L=8 interval set as `replicas` independent lattices of one context
+    (the lattice index enters every random counter), in FP64 and in FP32."""
+    L = 8
+    V6 = 6 * L ** 4
+    dE = 0.005 * V6
+    E_low = 0.55 * V6 + dE * np.arange(32)
+    rec = {}
+    for prec in (llr.FP64, llr.FP32):
+        res, meta = _run([(L, E_low, dE)] * replicas, prec, 200, 500, 50, False, log=log)
+        for r in res:
+            r.update(_reconstruct(L, E_low, dE, np.array(r["a"]), 0.98, 1.04))
+        rec[meta["precision"]] = dict(results=res, meta=meta)
+        a = np.array([r["a"] for r in res])
+        bc = np.array([r["beta_c"] for r in res])
+        pk = np.array([r["cv_peak_over_6v"] for r in res])
+        log(f"{meta['precision']}: a_k spread (std over replicas) max {a.std(0, ddof=1).max():.2e}; "
+            f"beta_c {bc.mean():.6f} +- {bc.std(ddof=1) / np.sqrt(len(bc)):.6f}; "
+            f"C_V/(6V) peak {pk.mean():.3e} +- {pk.std(ddof=1) / np.sqrt(len(pk)):.1e}; "
+            f"{meta['updates_per_s']:.3e} updates/s")
+    return rec
+
+
+def config2(log):
+    lats = []
+    for L in (12, 16, 20):
+        V6 = 6 * L ** 4
+        dE = 0.1 / 64 * V6
+        lats.append((L, 0.58 * V6 + dE * np.arange(64), dE))
+    res, meta = _run(lats, llr.FP32, 200, 1000, 100, True, log=log)
+    for r in res:
+        r.update(_reconstruct(r["L"], r["E_low"], r["dE"], np.array(r["a"]), 0.98, 1.04))
+    return dict(results=res, meta=meta)
+
+
+def config4_intervals():
+    L = 20
+    V6 = 6 * L ** 4
+    dE = 0.0005 * V6
+    return L, 0.60 * V6 + dE * np.arange(128), dE
+
+
+def train_network(points, epochs=4000, lr=3e-3, seed=SEED):
+    """points: list of (u, 1/L, a).  Trained on the GPU with the library's
+    kernels (BF16 MFMA forward, FP32 backward, Adam)."""
+    ctx = llr.Context(precision=llr.FP32, device=0)
+    u = np.array([p[0] for p in points])
+    il = np.array([p[1] for p in points])
+    a = np.array([p[2] for p in points])
+    w0 = ctx.mlp_init(seed)
+    w, hist = ctx.mlp_train(w0, u, il, a, epochs=epochs, lr=lr, bf16=True)
+    pred = ctx.mlp_predict(w, u, il, bf16=True)
+    ctx.close()
+    return w, hist, float(np.sqrt(np.mean((pred - a) ** 2)))
+
+
+def config3(log, c1, c2, n_rm=20):
+    pts = []
+    r1 = c1["fp64"]["results"]
+    a8 = np.mean([r["a"] for r in r1], axis=0)
+    V6 = 6 * 8 ** 4
+    for e, a in zip(r1[0]["E_low"], a8):
+        pts.append(((e + 0.5 * r1[0]["dE"]) / V6, 1.0 / 8, a))
+    for r in c2["results"]:
+        if r["L"] in (12, 16):
+            V6 = 6 * r["L"] ** 4
+            for e, a in zip(r["E_low"], r["a"]):
+                pts.append(((e + 0.5 * r["dE"]) / V6, 1.0 / r["L"], a))
+    w, hist, rms = train_network(pts)
+    L, E_low, dE = config4_intervals()
+    V6 = 6 * L ** 4
+    u20 = (E_low + 0.5 * dE) / V6
+    ctx = llr.Context(precision=llr.FP32, device=0)
+    a_mlp = ctx.mlp_predict(w, u20, np.full(u20.size, 1.0 / L), bf16=True)
+    ctx.close()
+    log(f"network trained on {len(pts)} points, fit rms {rms:.2e}; prediction range "
+        f"{a_mlp.min():.4f}..{a_mlp.max():.4f}")
+    runs = {}
+    for name, a0 in (("cold", np.full(128, 1.0)), ("mlp", a_mlp)):
+        res, meta = _run([(L, E_low, dE)], llr.FP32, 500, 2000, n_rm, True, a0=[a0], log=log)
+        runs[name] = dict(result=res[0], meta=meta)
+    return dict(training_points=len(pts), fit_rms=rms, loss_hist=hist[::100].tolist(), weights=w.tolist(),
+                a_mlp=a_mlp.tolist(), runs=runs, n_rm=n_rm)
+
+
+def config4(log, c3, n_rm=100):
+    L, E_low, dE = config4_intervals()
+    a0 = np.array(c3["a_mlp"])
+    res, meta = _run([(L, E_low, dE)], llr.FP32, 500, 2000, n_rm, True, a0=[a0], log=log)
+    r = res[0]
+    r.update(_reconstruct(L, E_low, dE, np.array(r["a"]), 1.008, 1.012, nb=41))
+    return dict(result=r, meta=meta)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["config1", "config2", "config3", "config4"])
+    ap.add_argument("--out", default="gpurun_out")
+    ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
+                    "(config3 reads config1 and config2, config4 reads config3); default --out")
+    ap.add_argument("--n-rm", type=int, default=None)
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+
+    def log(msg):
+        print(f"# {args.which}: {msg}", flush=True)
+
+    def load(name):
+        with open(os.path.join(args.inputs or args.out, f"{name}.json")) as f:
+            return json.load(f)
+
+    t0 = time.perf_counter()
+    if args.which == "config1":
+        rec = config1(log)
+    elif args.which == "config2":
+        rec = config2(log)
+    elif args.which == "config3":
+        rec = config3(log, load("config1"), load("config2"), n_rm=args.n_rm or 20)
+    else:
+        rec = config4(log, load("config3"), n_rm=args.n_rm or 100)
+    rec["wall_seconds"] = time.perf_counter() - t0
+    with open(os.path.join(args.out, f"{args.which}.json"), "w") as f:
+        json.dump(rec, f)
+    log(f"done in {rec['wall_seconds']:.1f} s")
+
+
+if __name__ == "__main__":
+    sys.exit(main())

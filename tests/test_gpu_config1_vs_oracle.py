@@ -1,0 +1,85 @@
+"""Full L = 8 runs of Algorithm 1 on the GPU against the FP64 oracle's full run
+of the same case (stored by tests/golden/make_config1_oracle.py, which calls
+only the oracle): 32 intervals from u = 0.55 with dE = 0.005 6V, N_TH = 200,
+N_A = 500, N_RM = 50, a^(0) = 1, hot start.
+
+Two implementations of the same Markov chain follow different trajectories
+after ~15 sweeps (last-bit differences of the transcendentals grow ~5x per
+sweep), so a full run is compared as a sample: eight GPU replicas (eight
+lattices of one context; the lattice index enters every counter) give the
+spread of a_k, <u>(beta) and C_V(beta) from one run, and the oracle's run must
+lie within it, interval by interval and beta by beta.  Done in FP64 and with
+FP32 angles (the FP32-vs-FP64-oracle error is this comparison)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config1_oracle_fp64.json")
+REPLICAS = 8
+
+
+@pytest.fixture(scope="module")
+def llr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1509_08391_amd import llr as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_config1_replicas_bracket_the_oracle_run(llr, golden, prec):
+    g = golden
+    L, dE = g["L"], g["dE"]
+    V6 = 6 * L ** 4
+    E_low = np.array(g["E_low"])
+    ctx = llr.Context(precision=getattr(llr, prec), device=0)
+    ctx.set_params(n_th=g["n_th"], n_a=g["n_a"], n_rm=g["n_rm"], seed=g["seed"], replica_exchange=False,
+                   recompute_every=10, eps=1e-4, approach_cap=20000)
+    for _ in range(REPLICAS):
+        ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    for i in range(REPLICAS):
+        ctx.set_a(i, 1.0)
+    ctx.hot_start()
+    ctx.approach()
+    ctx.run()
+    A = np.array([ctx.get_a(i)[0] for i in range(REPLICAS)])
+    cen = E_low + 0.5 * dE
+    beta = np.array(g["beta"])
+    U, CV, BC = [], [], []
+    for i in range(REPLICAS):
+        _, u, cv = ctx.reconstruct(cen, A[i], dE, V6, beta)
+        bc, _ = ctx.beta_c(cen, A[i], dE, V6, beta[0], beta[-1])
+        U.append(u)
+        CV.append(cv)
+        BC.append(bc)
+    ctx.close()
+    U, CV, BC = np.array(U), np.array(CV), np.array(BC)
+
+    def z(sample, ref):
+        # the oracle's run is one more draw of the same distribution
+        return (np.asarray(ref) - sample.mean(0)) / (sample.std(0, ddof=1) * np.sqrt(1 + 1 / REPLICAS))
+
+    za, zu, zc, zb = z(A, g["a"]), z(U, g["u_mean"]), z(CV, g["cv"]), z(BC, g["beta_c"])
+    print(f"\n{prec}: a_k chi2/n {np.mean(za ** 2):.2f} max|z| {np.abs(za).max():.2f}; <u> max|z| "
+          f"{np.abs(zu).max():.2f}; C_V max|z| {np.abs(zc).max():.2f}; beta_c {BC.mean():.6f} vs oracle "
+          f"{g['beta_c']:.6f} (z {float(zb):.2f}); max |a_gpu - a_oracle| {np.abs(A.mean(0) - g['a']).max():.2e}")
+    # each z is Student t with 7 degrees of freedom (E z^2 = 1.4, P(|z| > 6)
+    # = 5e-4); 32 intervals, 61 correlated couplings
+    assert np.mean(za ** 2) < 3.0
+    assert np.abs(za).max() < 6.0
+    assert np.abs(zu).max() < 6.0
+    assert np.abs(zc).max() < 6.0
+    assert abs(float(zb)) < 4.0

@@ -481,3 +481,128 @@ def test_graph_replays_match_eager_launches(llr, replica):
         ctx.close()
     for x, y in zip(out[0], out[1]):
         assert np.array_equal(x, y)
+
+
+def _full_size_states(dtype):
+    """128 synthetic L = 20 states (four plaquette densities 0.58-0.64), sorted by
+    their oracle energy, each the centre of its own interval of width 16000
+    (the states are far from equilibrium: class Delta E of 1e3-1e4 at the
+    couplings below, so this width gives both outcomes of the interval test)."""
+    d, L, n = 4, 20, 128
+    groups = [random_state(d, L, n // 4, seed=2000 + g, u_target=0.58 + 0.02 * g, dtype=dtype) for g in range(4)]
+    th = np.concatenate(groups).astype(np.float64)
+    del groups
+    E = np.array([oracle.energy(d, L, th[k]) for k in range(n)])
+    order = np.argsort(E)
+    th, E = np.ascontiguousarray(th[order]), E[order]
+    assert np.all(np.diff(E) > 0)
+    dE = 16000.0
+    return th, E, E - 0.5 * dE, dE, np.linspace(0.7, 0.9, n)
+
+
+# chains at the first and last blocks of both serpentine directions
+_SAMPLE = np.array([0, 1, 63, 64, 126, 127])
+
+
+def test_full_size_one_sweep_sampled_chains_fp64(llr):
+    """The benchmark's shape and launch configuration (128 chains of L = 20 in
+    one lattice, 640 000 links each; heatbath tiles of 4 and overrelaxation
+    tiles of 2 class links per thread; serpentine block order), in FP64: one
+    restricted sweep of every chain; six chains spread over the grid are swept
+    by the oracle from the same state with the same counters.  Accept bits
+    identical, energies within 1e-9 relative, 99.999 % of the 3.84 M angles
+    within 1e-12 and all within 1e-10.  (Every angle is within 1e-12 at
+    L <= 10.  A link whose staple modulus R is small amplifies the ulp-level
+    differences of the two sides' sin, cos and atan2 by ~1/R in
+    phi = arg(C + iS); with P(R < r) ~ r^2 the largest amplification over N
+    links grows like sqrt(N), about 1e3 here, and measured maxima are ~2e-12.)"""
+    import torch
+    d, L = 4, 20
+    th, E, E_low, dE, a = _full_size_states(np.float64)
+    ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a])
+    ctx.set_tiles(4, 2)
+    ctx.set_order(True)
+    ctx.import_state(0, torch.from_numpy(th))
+    bits = ctx.sweeps(1, sweep0=7)
+    got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy()
+    Eg, _ = ctx.get_energy(0)
+    ctx.close()
+    tr = np.ascontiguousarray(th[_SAMPLE])
+    Er, br = oracle.sweeps(d, L, tr, a[_SAMPLE], E_low[_SAMPLE], E_low[_SAMPLE] + dE, _SAMPLE, E[_SAMPLE], 1, 7,
+                           seed=SEED)
+    n_acc = int(sum(bin(int(b) & 0xff).count("1") for b in br[0]))
+    assert 0 < n_acc < 8 * _SAMPLE.size          # both outcomes of the interval test occur
+    dist = circ_dist(got, tr)
+    print(f"\nL=20 x 128 FP64 sweep, 6 sampled chains: max angle difference {dist.max():.2e}, "
+          f"links above 1e-12: {int(np.sum(dist > 1e-12))} of {dist.size}")
+    assert np.mean(dist <= 1e-12) >= 0.99999
+    assert dist.max() < 1e-10
+    for j, k in enumerate(_SAMPLE):
+        assert int(bits[0, k]) == int(br[0, j]), (k, bits[0, k], br[0, j])
+        assert abs(Eg[k] - Er[j]) < 1e-9 * abs(Er[j])
+
+
+def test_full_size_class_passes_sampled_chains_fp32(llr):
+    """The same shape and launch configuration with FP32 angles, one class at
+    a time (links of one class share no plaquette, so a link that differs
+    cannot move another): a restricted heatbath pass of colour 5, then an
+    overrelaxation pass of colour 2, against the oracle's FP32-state mode
+    (FP64 arithmetic on FP32-rounded angles, 23-bit uniforms).  Heatbath links
+    whose sampler accept test has a margin below 1e-5 can fall the other way
+    in FP32; the oracle flags them.  All other class links within 1e-5, all
+    other links untouched, the class Delta E within its rounding bound plus
+    2R per flagged link, the interval decision identical wherever the new
+    energy is farther from an edge than that bound; after the
+    overrelaxation pass 99.9 % of its class within 1e-5 (the rest are
+    neighbours of flagged links)."""
+    import torch
+    d, L = 4, 20
+    V = L ** d
+    th, E, E_low, dE, a = _full_size_states(np.float32)
+    ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], a=[a])
+    ctx.set_tiles(4, 2)
+    ctx.set_order(True)
+    ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
+    par = np.zeros(V, dtype=np.int64)
+    for m in range(d):
+        par += (np.arange(V) // L ** m) % L
+    par &= 1
+    sel = torch.from_numpy(_SAMPLE).cuda()
+    ctx.class_pass(1, 5, mode=llr.MODE_RESTRICTED, sweep_index=7)
+    got_hb = ctx.export_state(0)[sel].cpu().numpy().astype(np.float64)
+    E_hb, _ = ctx.get_energy(0)
+    ctx.class_pass(0, 2)
+    got_or = ctx.export_state(0)[sel].cpu().numpy().astype(np.float64)
+    ctx.close()
+    cls5 = (2, np.nonzero(par == 1)[0])
+    cls2 = (1, np.nonzero(par == 0)[0])
+    for j, k in enumerate(_SAMPLE):
+        tr = th[k].copy()
+        before = tr.copy()
+        acc, E1, dE1, mg = oracle.class_pass(d, L, tr, 1, 5, oracle.MODE_RESTRICTED, a[k], E_low[k], E_low[k] + dE,
+                                             E[k], SEED, sweep=7, interval=k, f32=True, want_margin=True)
+        flag = mg < 1e-5
+        assert flag.mean() < 1e-3
+        bound = 0.05 + 12.0 * flag.sum()
+        # the class: GPU proposal vs oracle proposal (both stored only on accept)
+        mu, idx = cls5
+        dist = circ_dist(got_hb[j], tr)
+        others = np.ones((d, V), dtype=bool)
+        others[mu, idx] = False
+        assert np.array_equal(got_hb[j][others], before[others])
+        edge = min(abs(E[k] + dE1 - E_low[k]), abs(E[k] + dE1 - E_low[k] - dE))
+        if edge > bound:
+            gpu_acc = not np.array_equal(got_hb[j][mu, idx], before[mu, idx])
+            assert gpu_acc == bool(acc), (k, gpu_acc, acc)
+            if acc:
+                assert dist[mu, idx][~flag].max() < 1e-5
+                assert abs(E_hb[k] - E1) < bound
+            else:
+                assert abs(E_hb[k] - E[k]) < 1e-9 * abs(E[k])
+        # overrelaxation of colour 2 from the oracle's state after the heatbath pass
+        oracle.class_pass(d, L, tr, 0, 2, oracle.MODE_RESTRICTED, a[k], E_low[k], E_low[k] + dE, E1, SEED, sweep=7,
+                          interval=k, f32=True)
+        if edge > bound:
+            mu, idx = cls2
+            d2 = circ_dist(got_or[j][mu, idx], tr[mu, idx])
+            assert np.mean(d2 < 1e-5) > 0.999, (k, np.mean(d2 < 1e-5))
