@@ -25,7 +25,9 @@
  * Sign convention (beta-convention): the restricted weight in interval k is
  * exp(+a E) 1[E in I_k], so that a_k = -d ln rho/dE ~ beta > 0 for E > 0.
  * With this reading Algorithm 1's update a <- a - 12 dE/((n+1) w^2) is the
- * correct sign (the paper mixes e^{-aS} and e^{+beta S}).
+ * correct sign (the paper's general LLR section and its U(1) application
+ * attach opposite signs to a; in this convention a_k approaches beta where
+ * <E>(beta) is the interval centre, which the 4D oracle pin checks).
  *
  * Parity pins (tests/test_oracle_*.py) check this file against brute-force
  * enumeration, closed forms (2D U(1) character expansion, von Mises moments,
