@@ -68,7 +68,8 @@ enum {
 
 enum { LLR_FP64 = 0, LLR_FP32 = 1 }; /* precision of link angles and local arithmetic;
                                         energies, interval tests, a_k, RM always FP64 */
-enum { LLR_MODE_RESTRICTED = 0, LLR_MODE_APPROACH = 1, LLR_MODE_FREE = 2 };
+enum { LLR_MODE_RESTRICTED = 0, LLR_MODE_APPROACH = 1, LLR_MODE_FREE = 2,
+       LLR_MODE_MUCA = 3 /* multicanonical; only through llr_muca_sweeps */ };
 
 typedef struct {
     int n_th;             /* thermalisation sweeps per RM iteration (Algorithm 1 N_TH) */
@@ -221,6 +222,78 @@ llr_status llr_reconstruct(llr_ctx *ctx, const double *centres, const double *a,
 llr_status llr_beta_c(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
                       double six_v, double blo, double bhi, double h, double tol,
                       double *beta_c, double *cv_peak);
+
+/* --- analysis of repeated runs (Sec. 2.4 N_B repetitions, Sec. 3.4) ------ */
+
+/* ln P_beta(E) at m energies E (host), P_beta(E) = rho~(E) e^{beta E} / Z with
+ * the piecewise-exponential rho~ of eq. (rhoguess) built from a_k on intervals
+ * of width s centred at centres (host, n, spaced by s; else LLR_EINVAL):
+ * ln rho~ is continuous, with slope -a_k in interval k, and Z is its exact
+ * integral over [c_0 - s/2, c_{n-1} + s/2].  log_p (host, m) is -inf outside
+ * that range. */
+llr_status llr_prob_density(llr_ctx *ctx, const double *centres, const double *a, int n,
+                            double s, double beta, const double *E, int m, double *log_p);
+/* Interior local maxima of P_beta(E) (the peaks of the two phases at a
+ * first-order transition, Sec. 3.4): ln P is linear in each interval, so the
+ * edge between intervals k and k+1 is a maximum iff a_k < beta <= a_{k+1}.
+ * Up to max_peaks energies and ln P values (host) in ascending E; n_found
+ * receives the total number, which may exceed max_peaks. */
+llr_status llr_prob_peaks(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
+                          double beta, int max_peaks, double *E_peak, double *log_p_peak,
+                          int *n_found);
+/* Bootstrap of beta_c and the C_V peak over n_runs independent runs of
+ * Algorithm 1 (repeated N_B times for the error analysis, Sec. 2.4 and 3.2).
+ * a_runs (host, n_runs x n, row-major; 1 <= n_runs <= 1024).  Sample b
+ * (0 <= b < n_boot) takes run floor(n_runs w / 2^32) as its j-th draw, w the
+ * first word of Philox4x32-10 at counter (j, kind 5 << 12, b, 0) with key
+ * (seed lo, seed hi), averages the drawn runs' a_k in draw order, and is
+ * reconstructed as llr_beta_c does.  beta_c, cv_peak (host, n_boot): one
+ * value per sample; their mean and standard deviation are the estimate and
+ * its error.  (n_boot (ng + 1) <= 6.5e7 grid points, ng = (bhi - blo)/h.) */
+llr_status llr_bootstrap(llr_ctx *ctx, const double *centres, const double *a_runs, int n_runs,
+                         int n, double s, double six_v, double blo, double bhi, double h,
+                         double tol, int n_boot, uint64_t seed, double *beta_c,
+                         double *cv_peak);
+/* Weighted least squares for the finite-size scaling forms of Sec. 3.4,
+ * y(L) = sum_j p_j L^{powers_j} (e.g. beta_c(L) = beta_c + B_1 L^-4 + B_2 L^-8
+ * with powers {0, -4, -8}; C_V/(6V) at the peak = G^2/4 + C_1 L^-4 + ...):
+ * x (L > 0), y, sigma (> 0): host, m > n_par; powers: host, n_par <= 16.
+ * params (host, n_par); errors (host, n_par, optional): sqrt of the diagonal
+ * of the covariance (A^T A)^-1 of the weighted design matrix, not scaled by
+ * chi2_red; chi2_red (optional): residual sum of squares / (m - n_par).
+ * Host computation (Householder QR); needs no context. */
+llr_status llr_fss_fit(const double *x, const double *y, const double *sigma, int m,
+                       const double *powers, int n_par, double *params, double *errors,
+                       double *chi2_red);
+
+/* --- multicanonical sampling with W = 1/rho~ and reweighting (Sec. 2.6) --- */
+
+/* Builds each lattice's weight W(E) = 1/rho~(E) from its current a_k
+ * (intervals of width dE: ln rho~ continuous, slope -a_k in interval k; below
+ * the first and above the last interval the first and last pieces continue,
+ * i.e. W = e^{a_0 E + c_1} and e^{a_{n-1} E + c_2}, eq. (4.1) with beta_1 =
+ * a_0, beta_2 = a_{n-1} and c_1, c_2 from continuity), stores the heatbath
+ * proposal couplings b (host, one per lattice, >= 0) and recomputes E in
+ * FP64.  Any later change of a_k (llr_set_a, llr_run, llr_rm_*) requires a new
+ * llr_muca_begin. */
+llr_status llr_muca_begin(llr_ctx *ctx, const double *b);
+/* n_sweeps multicanonical sweeps of every chain from sweep index sweep0: per
+ * colour class a heatbath proposal at coupling b, accepted with probability
+ * min(1, W(E') / W(E) e^{-b (E' - E)}) (the Metropolis-Hastings ratio of the
+ * class heatbath, whose normalisation depends only on the other classes;
+ * uniform from Philox counter (interval, colour << 8 | 6 << 12 | lattice <<
+ * 16, sweep, 0), first word), then the overrelaxation classes (E unchanged,
+ * always accepted); FP64 recompute after every K-th sweep of the call.
+ * E_hist (host, n_sweeps x total chains, optional): each chain's E after each
+ * sweep, chains in context order. */
+llr_status llr_muca_sweeps(llr_ctx *ctx, int n_sweeps, long long sweep0, double *E_hist);
+/* Canonical <u> = <E>/(6V) and C_V = Var(E)/(6V) at nb couplings beta (host)
+ * from m multicanonical samples E (host) taken with the weight built from a_k
+ * (host, n, on intervals of width s centred at centres, spaced by s):
+ * <O>_beta = <O e^{beta E} / W(E)>_W / <e^{beta E} / W(E)>_W, eq. (4.7). */
+llr_status llr_muca_reweight(llr_ctx *ctx, const double *E, long m, const double *centres,
+                             const double *a, int n, double s, double six_v, const double *beta,
+                             int nb, double *u_mean, double *cv);
 
 /* --- warm-start network a(u, 1/L): 2 -> 64 (tanh) -> 64 (tanh) -> 1 ------ */
 /* Parameter vector (host, 4417 FP32): W1[64][2], b1[64], W2[64][64], b2[64],

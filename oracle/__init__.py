@@ -27,8 +27,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "llr_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP = 0, 1, 2, 3, 4
-MODE_RESTRICTED, MODE_APPROACH, MODE_FREE = 0, 1, 2
+KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP, KIND_BOOT, KIND_MUCA = 0, 1, 2, 3, 4, 5, 6
+MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA = 0, 1, 2, 3
 N_PARAMS = 4417
 
 
@@ -97,6 +97,9 @@ def _declare(L):
     L.or_rm_step.argtypes = [d, d, d, i, d]
     L.or_rm_step.restype = d
     L.or_ln_rho.argtypes = [_p(d), i, d, _p(d)]
+    L.or_set_muca.argtypes = [_p(d), _p(d), i, d]
+    L.or_muca_lnw.argtypes = [d]
+    L.or_muca_lnw.restype = d
     L.or_reconstruct.argtypes = [_p(d), _p(d), i, d, d, _p(d), i, _p(d), _p(d), _p(d)]
     L.or_beta_c.argtypes = [_p(d), _p(d), i, d, d, d, d, d, d, _p(d), _p(d)]
     L.or_mlp_nparams.restype = i
@@ -274,6 +277,120 @@ def beta_c(centres, a, s, six_v, blo, bhi, h=1e-5, tol=1e-9):
     lib().or_beta_c(_ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, six_v, blo, bhi, h, tol,
                     C.byref(bc), C.byref(pk))
     return bc.value, pk.value
+
+
+# --------------------------------------------- analysis of repeated runs
+def log_rho_tilde(centres, a, s, E):
+    """ln rho~(E) of eq. (rhoguess) relative to the first centre: in interval k
+    ln rho~ = L_k - a_k (E - c_k), with L_k from the trapezium recursion."""
+    c, a, E = _f64(centres), _f64(a), np.atleast_1d(_f64(E))
+    L = ln_rho(a, s)
+    out = np.full(E.size, -np.inf)
+    lo, hi = c[0] - 0.5 * s, c[-1] + 0.5 * s
+    for i, e in enumerate(E):
+        if lo <= e <= hi:
+            k = min(int(np.floor((e - lo) / s)), c.size - 1)
+            out[i] = L[k] - a[k] * (e - c[k])
+    return out
+
+
+def prob_density(centres, a, s, beta, E):
+    """ln P_beta(E) = ln rho~(E) + beta E - ln Z (Sec. 3.4), Z the integral of
+    rho~ e^{beta E} over the covered range, interval by interval:
+    int_{c-s/2}^{c+s/2} e^{L - a (E - c) + beta E} dE = e^{L + beta c} s sinh(x)/x,
+    x = (beta - a) s / 2."""
+    c, a = _f64(centres), _f64(a)
+    L = ln_rho(a, s)
+    x = (beta - a) * 0.5 * s
+    ax = np.abs(x)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lsh = np.where(ax < 1e-6, ax * ax / 6.0, np.log(np.sinh(np.minimum(ax, 700.0)) / np.maximum(ax, 1e-300)))
+    lsh = np.where(ax > 700.0, ax - np.log(2.0 * ax), lsh)
+    t = L + beta * c + lsh
+    m = t.max()
+    lnz = m + np.log(s * np.sum(np.exp(t - m)))
+    lr = log_rho_tilde(c, a, s, E)
+    return lr + beta * np.atleast_1d(_f64(E)) - lnz
+
+
+def prob_peaks(centres, a, s, beta):
+    """Interior local maxima of ln P_beta(E), found by comparing its values at
+    the breakpoints (the interval edges), between which it is linear: edge k
+    (between intervals k and k+1) is a maximum iff its value exceeds the
+    previous edge's and is not below the next one's."""
+    c, a = _f64(centres), _f64(a)
+    edges = np.concatenate([[c[0] - 0.5 * s], c + 0.5 * s])
+    v = prob_density(c, a, s, beta, edges)
+    pk = [k for k in range(1, edges.size - 1) if v[k] > v[k - 1] and v[k] >= v[k + 1]]
+    return edges[pk], v[pk]
+
+
+def bootstrap_indices(n_runs, n_boot, seed):
+    """Draw j of sample b: floor(n_runs w / 2^32), w the first Philox word of
+    counter (j, kind 5 << 12, b, 0)."""
+    j, b = np.meshgrid(np.arange(n_runs), np.arange(n_boot))
+    ctr = np.zeros((n_boot * n_runs, 4), dtype=np.uint32)
+    ctr[:, 0] = j.ravel()
+    ctr[:, 1] = ctr1(kind=KIND_BOOT)
+    ctr[:, 2] = b.ravel()
+    w = philox(ctr, seed)[:, 0].astype(np.uint64)
+    return ((w * np.uint64(n_runs)) >> np.uint64(32)).astype(np.int64).reshape(n_boot, n_runs)
+
+
+def bootstrap(centres, a_runs, s, six_v, blo, bhi, n_boot, seed, h=1e-5, tol=1e-9):
+    """beta_c and the C_V peak of each bootstrap sample: the mean a_k of the
+    drawn runs (summed in draw order), reconstructed by beta_c()."""
+    ar = np.atleast_2d(_f64(a_runs))
+    idx = bootstrap_indices(ar.shape[0], n_boot, seed)
+    bc, pk = np.empty(n_boot), np.empty(n_boot)
+    for b in range(n_boot):
+        acc = np.zeros(ar.shape[1])
+        for j in idx[b]:
+            acc = acc + ar[j]
+        bc[b], pk[b] = beta_c(centres, acc / ar.shape[0], s, six_v, blo, bhi, h, tol)
+    return bc, pk
+
+
+# ------------------------------------ multicanonical sampling (Sec. 2.6)
+def set_muca(centres, a, s):
+    """Weight W = 1/rho~ for MODE_MUCA passes and sweeps (the proposal coupling
+    is the per-chain a passed to those calls)."""
+    c, a = _f64(centres), _f64(a)
+    lib().or_set_muca(_ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s)
+
+
+def muca_lnw(E):
+    return np.array([lib().or_muca_lnw(float(e)) for e in np.atleast_1d(E)])
+
+
+def muca_reweight(E, centres, a, s, six_v, beta):
+    """Eq. (4.7): <O>_beta = <O e^{beta E}/W(E)>_W / <e^{beta E}/W(E)>_W for
+    O = E, (E - <E>)^2; returns <u> = <E>/(6V), C_V = Var(E)/(6V)."""
+    E = np.ravel(_f64(E))
+    set_muca(centres, a, s)
+    lw = muca_lnw(E)
+    u, cv = [], []
+    for b in np.atleast_1d(beta):
+        t = b * E - lw
+        w = np.exp(t - t.max())
+        mu = np.sum(w * E) / np.sum(w)
+        u.append(mu / six_v)
+        cv.append(np.sum(w * (E - mu) ** 2) / np.sum(w) / six_v)
+    return np.array(u), np.array(cv)
+
+
+def fss_fit(L, y, sigma, powers):
+    """Weighted least squares for y(L) = sum_j p_j L^powers_j (the finite-size
+    forms of Sec. 3.4) with numpy's lstsq; errors sqrt(diag((A^T A)^-1)) of the
+    weighted design matrix A, chi2_red = |A p - y/sigma|^2 / (m - n_par)."""
+    L, y, sg, pw = _f64(L), _f64(y), _f64(sigma), _f64(powers)
+    A = L[:, None] ** pw[None, :] / sg[:, None]
+    col = np.sqrt(np.sum(A * A, axis=0))
+    As = A / col
+    p, _, _, _ = np.linalg.lstsq(As, y / sg, rcond=None)
+    r = As @ p - y / sg
+    cov = np.linalg.inv(As.T @ As)
+    return p / col, np.sqrt(np.diag(cov)) / col, float(r @ r) / (L.size - pw.size)
 
 
 def mlp_init(seed):

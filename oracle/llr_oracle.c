@@ -82,7 +82,7 @@ void or_philox_batch(long n, const uint32_t *ctr, const uint32_t key[2], uint32_
 /* Counter word 1 layout (shared convention, documented in include/llr.h):
  * bits 0-7 attempt pair, 8-11 colour/pass, 12-15 kind, 16-23 lattice id,
  * 24-31 replica id (reserved). */
-enum { KIND_SWEEP = 0, KIND_INIT = 1, KIND_APPROACH = 2, KIND_REPLICA = 3, KIND_MLP = 4 };
+enum { KIND_SWEEP = 0, KIND_INIT = 1, KIND_APPROACH = 2, KIND_REPLICA = 3, KIND_MLP = 4, KIND_MUCA = 6 };
 
 static uint32_t ctr1_word(int attempt_pair, int colour, int kind, int lattice_id)
 {
@@ -352,6 +352,11 @@ void or_hot_start(int d, int L, int n_chains, uint64_t seed, int lattice_id, int
 /*   mode 1: approach: accept iff dist(E + dE) <= dist(E), dist = distance    */
 /*           to [lo, hi].                                                    */
 /*   mode 2: unrestricted (canonical heatbath, used by physics pins).         */
+/*   mode 3: multicanonical (Sec. 2.6): target weight W(E) = 1/rho~(E) set by */
+/*           or_set_muca; the heatbath proposal at coupling a has a           */
+/*           normalisation that depends only on the other classes, so the     */
+/*           class is accepted with probability min(1, W(E+dE)/W(E) e^{-a dE}) */
+/*           against the uniform of Philox counter (interval, kind 6, sweep). */
 /* Links are visited in ascending half index h = s >> 1 and Delta E is       */
 /* summed sequentially in that order.                                        */
 /* ------------------------------------------------------------------------ */
@@ -363,6 +368,42 @@ typedef struct {
     uint32_t interval; /* counter word 3 */
     int f32;           /* single-precision state: 24-bit uniforms, stored angles rounded */
 } pass_ctx_t;
+
+/* Multicanonical weight: ln W(E) = -ln rho~(E), ln rho~ continuous with slope
+ * -a_k on [c_k - s/2, c_k + s/2] (ln rho~(c_0) = 0, eq. (kk3a) recursion);
+ * below the first and above the last interval the first and last pieces
+ * continue (eq. (4.1) with beta_1 = a_0, beta_2 = a_{n-1}). */
+static struct {
+    int n;
+    double s;
+    double *c, *a, *lr;
+} g_muca = {0, 0.0, NULL, NULL, NULL};
+
+void or_set_muca(const double *centres, const double *a, int n, double s)
+{
+    free(g_muca.c);
+    free(g_muca.a);
+    free(g_muca.lr);
+    g_muca.n = n;
+    g_muca.s = s;
+    g_muca.c = (double *)malloc(sizeof(double) * n);
+    g_muca.a = (double *)malloc(sizeof(double) * n);
+    g_muca.lr = (double *)malloc(sizeof(double) * n);
+    memcpy(g_muca.c, centres, sizeof(double) * n);
+    memcpy(g_muca.a, a, sizeof(double) * n);
+    g_muca.lr[0] = 0.0;
+    for (int k = 0; k + 1 < n; ++k) g_muca.lr[k + 1] = g_muca.lr[k] - 0.5 * s * (a[k] + a[k + 1]);
+}
+
+double or_muca_lnw(double E)
+{
+    int n = g_muca.n;
+    double lo = g_muca.c[0] - 0.5 * g_muca.s;
+    int k = (int)floor((E - lo) / g_muca.s);
+    if (k < 0) k = 0;
+    if (k > n - 1) k = n - 1;
+    return -(g_muca.lr[k] - g_muca.a[k] * (E - g_muca.c[k]));
+}
 
 static int class_pass(const geo_t *g, double *th, double *scratch, int hb, int colour,
                       int mode, double a, double lo, double hi, double *E,
@@ -408,6 +449,12 @@ static int class_pass(const geo_t *g, double *th, double *scratch, int hb, int c
         double d0 = fmax(0.0, fmax(lo - *E, *E - hi));
         double d1 = fmax(0.0, fmax(lo - En, En - hi));
         accept = (d1 <= d0);
+    } else if (mode == 3) {
+        double lr = or_muca_lnw(En) - or_muca_lnw(*E) - a * dE;
+        uint32_t ctr[4] = {pc->interval, ctr1_word(0, colour, KIND_MUCA, pc->lattice_id), pc->sweep, 0u};
+        uint32_t w[4];
+        or_philox(ctr, pc->key, w);
+        accept = lr >= 0.0 || ((double)w[0] + 0.5) * 0x1p-32 < exp(lr);
     } else accept = 1;
     if (dE_out) *dE_out = dE;
     if (accept) {

@@ -46,6 +46,7 @@ struct TimingPair {
 };
 
 struct llr_ctx {
+    bool muca_ready = false;   // multicanonical weights built (llr_muca_begin)
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = LLR_FP64;
@@ -177,7 +178,23 @@ static llr_status layout(llr_ctx* c) {
         // site kernels: the even and the odd sites of a chain in blocks of their own
         d.ebpc = 2 * (int)((V / 2 + kBlock - 1) / kBlock);
         d.eblock0 = eblock0;
+        {
+            long long r = kBlock;
+            d.st0 = (int)(r % d.hL);
+            r /= d.hL;
+            d.st1 = (int)(r % h.L);
+            r /= h.L;
+            d.st2 = (int)(r % h.L);
+            d.st3 = (int)(r / h.L);
+        }
+        d.hstr[0] = 0;
+        d.hwrap[0] = 0;
+        for (int nu = 1; nu < 4; ++nu) {
+            d.hstr[nu] = nu == 1 ? d.hL : d.hstr[nu - 1] * h.L;
+            d.hwrap[nu] = (h.L - 1) * d.hstr[nu];
+        }
         d.lat_id = i;
+        d.ds = h.dE;
         d.base = base;
         // largest fxb with 6V 2^fxb <= 2^49
         const int fxb = (int)std::floor(49.0 - std::log2(6.0 * (double)V));
@@ -200,7 +217,8 @@ static llr_status layout(llr_ctx* c) {
     if ((st = dalloc(c, &s.field, (cnt))) != LLR_OK) return st;
     AL(E, n) AL(acc, n) AL(eacc, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
     AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
-    AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n)
+    AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n) AL(mu_lnrho, n)
+    AL(mu_b, kMaxLat)
     AL(lat_done, kMaxLat) AL(lat_outside, kMaxLat) AL(lat_approach, kMaxLat) AL(sweep_ctr, 1)
     AL(approach_ctr, 1) AL(rm_iter, 1) AL(re_cnt, 2) AL(bits_row, 1)
 #undef AL
@@ -356,7 +374,7 @@ static llr_status autotune_impl(llr_ctx* c) {
         for (int rep = 0; rep < 4; ++rep) {   // first repetition warms up; minimum of the others
             HIPCHK(hipEventRecord(e0, c->stream));
             for (int col = 0; col < 8; ++col)
-                launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, 3, kSweep, (uint32_t)c->prm.seed,
+                launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, kHbModeTune, kSweep, (uint32_t)c->prm.seed,
                                   (uint32_t)(c->prm.seed >> 32), c->stream);
             HIPCHK(hipEventRecord(e1, c->stream));
             HIPCHK(hipEventSynchronize(e1));
@@ -540,6 +558,23 @@ static llr_status sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, int mo
     return LLR_OK;
 }
 
+template <typename T>
+static llr_status muca_sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, double* E_hist) {
+    const uint32_t s0 = (uint32_t)sweep0;
+    HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
+    const int n = c->lt.n_chains;
+    const int K = c->prm.recompute_every;
+    for (int t = 0; t < n_sweeps; ++t) {
+        enqueue_sweep<T>(c, LLR_MODE_MUCA, K > 0 && (t + 1) % K == 0, false, false);
+        if (E_hist) HIPCHK(hipMemcpyAsync(E_hist + (size_t)t * n, c->ds.E, 8 * (size_t)n, hipMemcpyDeviceToHost,
+                                          c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    if (c->timing) harvest(c);
+    return LLR_OK;
+}
+
 // ================================================================= C ABI
 extern "C" {
 
@@ -641,6 +676,7 @@ llr_status llr_bind_state(llr_ctx* c, void* dev_state, size_t bytes) {
 }
 
 llr_status llr_set_a(llr_ctx* c, int lat, const double* a) {
+    if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     if (!c || !a) return fail(LLR_EINVAL, "null argument");
     if (lat < 0 || lat >= (int)c->lats.size()) return fail(LLR_EINVAL, "no such lattice");
     for (int k = 0; k < c->lats[lat].n; ++k)
@@ -730,6 +766,7 @@ llr_status llr_approach_continue(llr_ctx* c, long long max_sweeps, long long* sw
 }
 
 llr_status llr_run(llr_ctx* c) {
+    if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     HIPCHK(hipSetDevice(c->device));
@@ -737,6 +774,7 @@ llr_status llr_run(llr_ctx* c) {
 }
 
 llr_status llr_rm_begin(llr_ctx* c) {
+    if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     HIPCHK(hipSetDevice(c->device));
@@ -744,6 +782,7 @@ llr_status llr_rm_begin(llr_ctx* c) {
 }
 
 llr_status llr_rm_step(llr_ctx* c, int iterations) {
+    if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     HIPCHK(hipSetDevice(c->device));
@@ -1044,6 +1083,238 @@ llr_status llr_beta_c(llr_ctx* c, const double* centres, const double* a, int n,
     HIPCHK(hipGetLastError());
     *beta_c = r[0];
     *cv_peak = r[1];
+    return LLR_OK;
+}
+
+static bool uniform_centres(const double* c, int n, double s) {
+    for (int k = 0; k + 1 < n; ++k)
+        if (!(std::fabs(c[k + 1] - c[k] - s) <= 1e-9 * std::max(1.0, std::fabs(s)))) return false;
+    return true;
+}
+
+llr_status llr_muca_begin(llr_ctx* c, const double* b) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (!b) return fail(LLR_EINVAL, "null coupling array");
+    for (int i = 0; i < c->lt.n; ++i)
+        if (!std::isfinite(b[i]) || b[i] < 0) return fail(LLR_EINVAL, "proposal couplings must be finite and >= 0");
+    HIPCHK(hipSetDevice(c->device));
+    for (int i = 0; i < c->lt.n; ++i) {
+        const LatDev& L = c->lt.l[i];
+        launch_recon(nullptr, c->ds.a + L.chain0, L.n_chains, L.ds, 1.0, nullptr, 0, c->ds.mu_lnrho + L.chain0,
+                     nullptr, nullptr, c->stream);
+    }
+    HIPCHK(hipMemcpyAsync(c->ds.mu_b, b, 8 * (size_t)c->lt.n, hipMemcpyHostToDevice, c->stream));
+    if (c->precision == LLR_FP32) enqueue_energy<float>(c);
+    else enqueue_energy<double>(c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    c->muca_ready = true;
+    return LLR_OK;
+}
+
+llr_status llr_muca_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, double* E_hist) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (!c->muca_ready) return fail(LLR_ESTATE, "call llr_muca_begin first");
+    if (n_sweeps < 0) return fail(LLR_EINVAL, "bad n_sweeps");
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? muca_sweeps_impl<float>(c, n_sweeps, sweep0, E_hist)
+                                    : muca_sweeps_impl<double>(c, n_sweeps, sweep0, E_hist);
+}
+
+llr_status llr_muca_reweight(llr_ctx* c, const double* E, long m, const double* centres, const double* a, int n,
+                             double s, double six_v, const double* beta, int nb, double* u_mean, double* cv) {
+    if (!c || !E || m < 1 || !centres || !a || n < 1 || !(s > 0) || !(six_v > 0) || nb < 1 || !beta || !u_mean ||
+        !cv)
+        return fail(LLR_EINVAL, "bad argument");
+    if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 8 * ((size_t)m + 3 * (size_t)n + 3 * (size_t)nb) + 64);
+    if (st != LLR_OK) return st;
+    double* dE = (double*)c->scratch;
+    double* dc = dE + m;
+    double* da = dc + n;
+    double* dL = da + n;
+    double* db = dL + n;
+    double* du = db + nb;
+    double* dv = du + nb;
+    HIPCHK(hipMemcpyAsync(dE, E, 8 * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(db, beta, 8 * (size_t)nb, hipMemcpyHostToDevice, c->stream));
+    launch_reweight(dE, m, dc, da, n, s, db, nb, six_v, du, dv, dL, c->stream);
+    HIPCHK(hipMemcpyAsync(u_mean, du, 8 * (size_t)nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(cv, dv, 8 * (size_t)nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+
+llr_status llr_prob_density(llr_ctx* c, const double* centres, const double* a, int n, double s, double beta,
+                            const double* E, int m, double* log_p) {
+    if (!c || !centres || !a || n < 1 || !(s > 0) || !std::isfinite(beta) || m < 0 || (m > 0 && (!E || !log_p)))
+        return fail(LLR_EINVAL, "bad argument");
+    if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 2 * m + 4) + 64);
+    if (st != LLR_OK) return st;
+    double* dc = (double*)c->scratch;
+    double* da = dc + n;
+    double* dE = da + n;
+    double* dp = dE + m;
+    double* scr = dp + m;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    if (m) HIPCHK(hipMemcpyAsync(dE, E, 8 * (size_t)m, hipMemcpyHostToDevice, c->stream));
+    launch_prob(dc, da, n, s, beta, dE, m, dp, 0, nullptr, nullptr, nullptr, scr, c->stream);
+    if (m) HIPCHK(hipMemcpyAsync(log_p, dp, 8 * (size_t)m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+llr_status llr_prob_peaks(llr_ctx* c, const double* centres, const double* a, int n, double s, double beta,
+                          int max_peaks, double* E_peak, double* log_p_peak, int* n_found) {
+    if (!c || !centres || !a || n < 1 || !(s > 0) || !std::isfinite(beta) || max_peaks < 0 || !n_found ||
+        (max_peaks > 0 && (!E_peak || !log_p_peak)))
+        return fail(LLR_EINVAL, "bad argument");
+    if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
+    HIPCHK(hipSetDevice(c->device));
+    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 2 * max_peaks + 8) + 64);
+    if (st != LLR_OK) return st;
+    double* dc = (double*)c->scratch;
+    double* da = dc + n;
+    double* dEp = da + n;
+    double* dlp = dEp + max_peaks;
+    int* dn = (int*)(dlp + max_peaks);
+    double* scr = dlp + max_peaks + 2;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    launch_prob(dc, da, n, s, beta, nullptr, 0, nullptr, max_peaks, dEp, dlp, dn, scr, c->stream);
+    int nf = 0;
+    HIPCHK(hipMemcpyAsync(&nf, dn, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int keep = std::min(nf, max_peaks);
+    if (keep > 0) {
+        HIPCHK(hipMemcpy(E_peak, dEp, 8 * (size_t)keep, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(log_p_peak, dlp, 8 * (size_t)keep, hipMemcpyDeviceToHost));
+    }
+    HIPCHK(hipGetLastError());
+    *n_found = nf;
+    return LLR_OK;
+}
+
+llr_status llr_bootstrap(llr_ctx* c, const double* centres, const double* a_runs, int n_runs, int n, double s,
+                         double six_v, double blo, double bhi, double h, double tol, int n_boot, uint64_t seed,
+                         double* beta_c, double* cv_peak) {
+    if (!c || !centres || !a_runs || n < 1 || n_runs < 1 || n_runs > 1024 || n_boot < 1 || !(s > 0) ||
+        !(six_v > 0) || !(bhi > blo) || !(h > 0) || !(tol > 0) || !beta_c || !cv_peak)
+        return fail(LLR_EINVAL, "bad argument");
+    const long ng = (long)std::floor((bhi - blo) / h + 0.5);
+    if (ng > 1000000 || (double)n_boot * (double)(ng + 1) > 6.5e7) return fail(LLR_EINVAL, "beta grid too fine");
+    HIPCHK(hipSetDevice(c->device));
+    const size_t nd = (size_t)n * (1 + (size_t)n_runs + 2 * (size_t)n_boot) + (size_t)n_boot * (ng + 1 + 2) + 8;
+    llr_status st = ensure_scratch(c, 8 * nd + 64);
+    if (st != LLR_OK) return st;
+    double* dc = (double*)c->scratch;
+    double* druns = dc + n;
+    double* dbar = druns + (size_t)n_runs * n;
+    double* dout = dbar + (size_t)n_boot * n;
+    double* scr = dout + 2 * (size_t)n_boot;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(druns, a_runs, 8 * (size_t)n * n_runs, hipMemcpyHostToDevice, c->stream));
+    launch_boot_mean(druns, n_runs, n, n_boot, seed, dbar, c->stream);
+    launch_beta_c_rows(dc, dbar, n, n_boot, s, six_v, blo, bhi, h, tol, scr, dout, c->stream);
+    std::vector<double> r(2 * (size_t)n_boot);
+    HIPCHK(hipMemcpyAsync(r.data(), dout, 16 * (size_t)n_boot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    for (int b = 0; b < n_boot; ++b) {
+        beta_c[b] = r[2 * b];
+        cv_peak[b] = r[2 * b + 1];
+    }
+    return LLR_OK;
+}
+
+// Weighted linear least squares y ~ sum_j p_j x^{e_j} by Householder QR of the
+// column-equilibrated design matrix (the columns x^0, x^-4, x^-8 of a
+// finite-size fit differ by many orders of magnitude, which the normal
+// equations would square).
+llr_status llr_fss_fit(const double* x, const double* y, const double* sigma, int m, const double* powers, int n_par,
+                       double* params, double* errors, double* chi2_red) {
+    if (!x || !y || !sigma || !powers || !params || m < 1 || n_par < 1 || n_par > 16 || m <= n_par)
+        return fail(LLR_EINVAL, "bad argument (need m > n_par, n_par <= 16)");
+    for (int i = 0; i < m; ++i)
+        if (!(sigma[i] > 0) || !(x[i] > 0) || !std::isfinite(y[i])) return fail(LLR_EINVAL, "bad data point");
+    std::vector<double> A((size_t)m * n_par), b(m), scale(n_par);
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < n_par; ++j) A[(size_t)i * n_par + j] = std::pow(x[i], powers[j]) / sigma[i];
+        b[i] = y[i] / sigma[i];
+    }
+    for (int j = 0; j < n_par; ++j) {
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += A[(size_t)i * n_par + j] * A[(size_t)i * n_par + j];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0)) return fail(LLR_ENUMERIC, "zero column in the design matrix");
+        scale[j] = nrm;
+        for (int i = 0; i < m; ++i) A[(size_t)i * n_par + j] /= nrm;
+    }
+    // Householder: A = Q R, b <- Q^T b
+    for (int j = 0; j < n_par; ++j) {
+        double nrm = 0.0;
+        for (int i = j; i < m; ++i) nrm += A[(size_t)i * n_par + j] * A[(size_t)i * n_par + j];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0)) return fail(LLR_ENUMERIC, "rank-deficient design matrix");
+        const double ajj = A[(size_t)j * n_par + j];
+        const double alpha = ajj > 0 ? -nrm : nrm;
+        std::vector<double> v(m, 0.0);
+        v[j] = ajj - alpha;
+        for (int i = j + 1; i < m; ++i) v[i] = A[(size_t)i * n_par + j];
+        double vv = 0.0;
+        for (int i = j; i < m; ++i) vv += v[i] * v[i];
+        if (vv > 0) {
+            for (int k = j; k < n_par; ++k) {
+                double d = 0.0;
+                for (int i = j; i < m; ++i) d += v[i] * A[(size_t)i * n_par + k];
+                d = 2.0 * d / vv;
+                for (int i = j; i < m; ++i) A[(size_t)i * n_par + k] -= d * v[i];
+            }
+            double d = 0.0;
+            for (int i = j; i < m; ++i) d += v[i] * b[i];
+            d = 2.0 * d / vv;
+            for (int i = j; i < m; ++i) b[i] -= d * v[i];
+        }
+    }
+    // back substitution R z = (Q^T b)[0:n]; residual norm from the rest
+    std::vector<double> z(n_par);
+    for (int j = n_par - 1; j >= 0; --j) {
+        double t = b[j];
+        for (int k = j + 1; k < n_par; ++k) t -= A[(size_t)j * n_par + k] * z[k];
+        z[j] = t / A[(size_t)j * n_par + j];
+    }
+    double rss = 0.0;
+    for (int i = n_par; i < m; ++i) rss += b[i] * b[i];
+    // covariance (R^T R)^{-1} = R^{-1} R^{-T}: invert the upper triangle
+    std::vector<double> Ri((size_t)n_par * n_par, 0.0);
+    for (int j = 0; j < n_par; ++j) {
+        Ri[(size_t)j * n_par + j] = 1.0 / A[(size_t)j * n_par + j];
+        for (int i = j - 1; i >= 0; --i) {
+            double t = 0.0;
+            for (int k = i + 1; k <= j; ++k) t += A[(size_t)i * n_par + k] * Ri[(size_t)k * n_par + j];
+            Ri[(size_t)i * n_par + j] = -t / A[(size_t)i * n_par + i];
+        }
+    }
+    for (int j = 0; j < n_par; ++j) {
+        params[j] = z[j] / scale[j];
+        if (errors) {
+            double v = 0.0;
+            for (int k = j; k < n_par; ++k) v += Ri[(size_t)j * n_par + k] * Ri[(size_t)j * n_par + k];
+            errors[j] = std::sqrt(v) / scale[j];
+        }
+    }
+    if (chi2_red) *chi2_red = rss / (double)(m - n_par);
     return LLR_OK;
 }
 

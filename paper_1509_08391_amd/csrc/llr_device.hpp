@@ -11,7 +11,11 @@ constexpr int kBlock = 256;           // threads per block of the lattice kernel
 constexpr int kMaxLat = 8;            // lattices per context
 constexpr int kVmCap = 64;            // heatbath sampler attempt cap
 
-enum Kind : uint32_t { kSweep = 0, kInit = 1, kApproach = 2, kReplica = 3, kMlp = 4 };
+enum Kind : uint32_t { kSweep = 0, kInit = 1, kApproach = 2, kReplica = 3, kMlp = 4, kBoot = 5, kMuca = 6 };
+
+// heatbath pass modes: the public LLR_MODE_* values 0-3 and the tuner's
+// timing mode (proposals written, nothing accepted, no counters touched)
+constexpr int kHbModeTune = 5;
 
 __host__ __device__ inline uint32_t ctr1_word(uint32_t attempt_pair, uint32_t colour, uint32_t kind,
                                               uint32_t lat) {

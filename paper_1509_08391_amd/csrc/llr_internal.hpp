@@ -19,7 +19,11 @@ struct LatDev {
     int chain0;            // first global chain index (= first global interval index)
     int hb_bpc, hb_block0; // heatbath pass: blocks per chain (V/2 / (256 LPT), rounded up), first block
     int or_bpc, or_block0; // overrelaxation pass: the same
-    int ebpc;              // blocks per chain in the site kernels (V / 256, rounded up)
+    int ebpc;              // blocks per chain in the site kernels (2 x V/2 / 256, rounded up)
+    int st0, st1, st2, st3; // digits of kBlock in the radices (L/2, L, L, L) of a half index
+    int hstr[4];           // half-index stride of a step along nu = 1..3: (L/2) L^(nu-1); [0] unused
+    int hwrap[4];          // (L - 1) hstr[nu]: the periodic jump across the boundary
+    double ds;             // interval spacing delta E
     int eblock0;           // first block of this lattice in the site grid
     int lat_id;
     long long base;        // element offset of the lattice's first chain
@@ -42,7 +46,7 @@ struct LatTable {
 struct DevState {
     // per chain
     double* E;             // current energy (incremental, FP64)
-    unsigned long long* acc;   // arrivals << 48 | fixed-point Delta E of the running pass
+    unsigned long long* acc;   // arrivals << 51 | fixed-point Delta E of the running pass
     unsigned long long* eacc;  // the same for the energy recompute
     uint8_t* cur;          // 8 per chain: current plane of each colour
     int* itv;              // global index of the interval the chain serves
@@ -64,10 +68,12 @@ struct DevState {
     int* conv_iter;
     long long* conv_sweeps;
     double* a_hist;        // (n_rm + 1) x n_chains
+    double* mu_lnrho;      // ln rho~ at the centre, for the multicanonical weight W = 1/rho~
     // per lattice
     int* lat_done;         // approach finished
     int* lat_outside;      // chains outside their interval (approach check)
     long long* lat_approach;   // approach sweeps performed
+    double* mu_b;          // multicanonical heatbath proposal coupling
     // scalars
     uint32_t* sweep_ctr;   // RM sweep index (counter word 2)
     uint32_t* approach_ctr;
@@ -108,6 +114,15 @@ void launch_recon(const double* c, const double* a, int n, double s, double six_
                   double* lnrho, double* u, double* cv, hipStream_t st);
 void launch_beta_c(const double* c, const double* a, int n, double s, double six_v, double blo, double bhi,
                    double h, double tol, double* lnrho_scratch, double* out2, hipStream_t st);
+void launch_beta_c_rows(const double* c, const double* a, int n, int rows, double s, double six_v, double blo,
+                        double bhi, double h, double tol, double* scratch, double* out2, hipStream_t st);
+void launch_boot_mean(const double* a_runs, int n_runs, int n, int n_boot, uint64_t seed, double* abar,
+                      hipStream_t st);
+void launch_prob(const double* c, const double* a, int n, double s, double beta, const double* E, int m,
+                 double* logp, int max_peaks, double* E_pk, double* lp_pk, int* n_pk, double* scratch,
+                 hipStream_t st);
+void launch_reweight(const double* E, long m, const double* c, const double* a, int n, double s, const double* beta,
+                     int nb, double six_v, double* u, double* cv, double* scratch, hipStream_t st);
 
 // network (llr_mlp.hip)
 constexpr int kMlpH = 64;

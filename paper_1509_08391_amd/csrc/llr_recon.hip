@@ -12,14 +12,18 @@ namespace llr {
 
 constexpr int kRB = 256;
 
-// the recursion is sequential by definition: one thread
-__global__ void k_lnrho(const double* __restrict__ a, int n, double s, double* __restrict__ L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The recursion is sequential by definition: one thread per set of a_k
+// (row r of a and of L at offset r n).
+__global__ void k_lnrho(const double* __restrict__ a, int n, int rows, double s, double* __restrict__ L) {
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= rows) return;
+    const double* ar = a + (size_t)r * n;
+    double* Lr = L + (size_t)r * n;
     double v = 0.0;
-    L[0] = 0.0;
+    Lr[0] = 0.0;
     for (int k = 0; k + 1 < n; ++k) {
-        v = v - 0.5 * s * (a[k] + a[k + 1]);
-        L[k + 1] = v;
+        v = v - 0.5 * s * (ar[k] + ar[k + 1]);
+        Lr[k + 1] = v;
     }
 }
 
@@ -80,19 +84,24 @@ __global__ __launch_bounds__(kRB) void k_moments(const double* __restrict__ c, c
     }
 }
 
-// Var(E) on the grid blo + i h, i = 0..ng (one block per point)
+// Var(E) on the grid blo + i h, i = 0..ng (one block per point; blockIdx.y
+// selects the set of a_k: L row y, var row y of ng + 1)
 __global__ __launch_bounds__(kRB) void k_var_grid(const double* __restrict__ c, const double* __restrict__ L, int n,
-                                                   double blo, double h, double* __restrict__ var) {
+                                                   double blo, double h, long ng, double* __restrict__ var) {
     __shared__ double sh[kRB / 64];
     double mu, v;
-    moments(c, L, n, blo + (double)blockIdx.x * h, sh, &mu, &v);
-    if (threadIdx.x == 0) var[blockIdx.x] = v;
+    moments(c, L + (size_t)blockIdx.y * n, n, blo + (double)blockIdx.x * h, sh, &mu, &v);
+    if (threadIdx.x == 0) var[(size_t)blockIdx.y * (size_t)(ng + 1) + blockIdx.x] = v;
 }
 
-// argmax of the grid, then golden section on [b* - h, b* + h] to tol (one block)
-__global__ __launch_bounds__(kRB) void k_golden(const double* __restrict__ c, const double* __restrict__ L, int n,
-                                                 const double* __restrict__ var, long ng, double blo, double bhi,
-                                                 double h, double tol, double six_v, double* __restrict__ out) {
+// argmax of the grid, then golden section on [b* - h, b* + h] to tol (one
+// block per set of a_k: L row, var row and out pair selected by blockIdx.x)
+__global__ __launch_bounds__(kRB) void k_golden(const double* __restrict__ c, const double* __restrict__ Lrows, int n,
+                                                 const double* __restrict__ var_rows, long ng, double blo, double bhi,
+                                                 double h, double tol, double six_v, double* __restrict__ out_rows) {
+    const double* L = Lrows + (size_t)blockIdx.x * n;
+    const double* var = var_rows + (size_t)blockIdx.x * (size_t)(ng + 1);
+    double* out = out_rows + 2 * (size_t)blockIdx.x;
     __shared__ double sh[kRB / 64];
     __shared__ double sbest;
     __shared__ long sidx;
@@ -133,18 +142,190 @@ __global__ __launch_bounds__(kRB) void k_golden(const double* __restrict__ c, co
 
 void launch_recon(const double* c, const double* a, int n, double s, double six_v, const double* beta, int nb,
                   double* lnrho, double* u, double* cv, hipStream_t st) {
-    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, s, lnrho);
+    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, 1, s, lnrho);
     if (nb > 0) hipLaunchKernelGGL(k_moments, dim3(nb), dim3(kRB), 0, st, c, lnrho, n, beta, six_v, u, cv);
 }
 
-// lnrho_scratch holds n + ng + 1 doubles
+// beta_c and the C_V peak for `rows` sets of a_k (a row r at a + r n);
+// scratch holds rows (n + ng + 1) doubles, out2 rows pairs
+void launch_beta_c_rows(const double* c, const double* a, int n, int rows, double s, double six_v, double blo,
+                        double bhi, double h, double tol, double* scratch, double* out2, hipStream_t st) {
+    const long ng = (long)floor((bhi - blo) / h + 0.5);
+    double* L = scratch;
+    double* var = scratch + (size_t)rows * n;
+    hipLaunchKernelGGL(k_lnrho, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, st, a, n, rows, s, L);
+    hipLaunchKernelGGL(k_var_grid, dim3((unsigned)(ng + 1), (unsigned)rows), dim3(kRB), 0, st, c, L, n, blo, h, ng,
+                       var);
+    hipLaunchKernelGGL(k_golden, dim3((unsigned)rows), dim3(kRB), 0, st, c, L, n, var, ng, blo, bhi, h, tol, six_v,
+                       out2);
+}
+
 void launch_beta_c(const double* c, const double* a, int n, double s, double six_v, double blo, double bhi, double h,
                    double tol, double* lnrho_scratch, double* out2, hipStream_t st) {
-    const long ng = (long)floor((bhi - blo) / h + 0.5);
-    double* var = lnrho_scratch + n;
-    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, s, lnrho_scratch);
-    hipLaunchKernelGGL(k_var_grid, dim3((unsigned)(ng + 1)), dim3(kRB), 0, st, c, lnrho_scratch, n, blo, h, var);
-    hipLaunchKernelGGL(k_golden, dim3(1), dim3(kRB), 0, st, c, lnrho_scratch, n, var, ng, blo, bhi, h, tol, six_v, out2);
+    launch_beta_c_rows(c, a, n, 1, s, six_v, blo, bhi, h, tol, lnrho_scratch, out2, st);
+}
+
+// ---------------------------------------------------------------------------
+// Bootstrap over N_B independent runs (Algorithm 1 repeated N_B times, Sec. 2.4
+// and Sec. 3.2): sample b draws n_runs runs with replacement, run j of sample
+// b being floor(n_runs w / 2^32) for the first word w of Philox counter
+// (j, kind 5, b, 0), and averages their a_k (runs summed in draw order).
+// ---------------------------------------------------------------------------
+constexpr int kMaxRuns = 1024;
+
+__global__ __launch_bounds__(kRB) void k_boot_mean(const double* __restrict__ a_runs, int n_runs, int n, uint32_t k0,
+                                                    uint32_t k1, double* __restrict__ abar) {
+    __shared__ int idx[kMaxRuns];
+    const uint32_t b = blockIdx.x;
+    for (int j = threadIdx.x; j < n_runs; j += kRB) {
+        const uint4 w = philox10(make_uint4((uint32_t)j, ctr1_word(0, 0, kBoot, 0), b, 0u), k0, k1);
+        idx[j] = (int)(((uint64_t)w.x * (uint64_t)n_runs) >> 32);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += kRB) {
+        double sum = 0.0;
+        for (int j = 0; j < n_runs; ++j) sum += a_runs[(size_t)idx[j] * n + k];
+        abar[(size_t)b * n + k] = sum / (double)n_runs;
+    }
+}
+
+void launch_boot_mean(const double* a_runs, int n_runs, int n, int n_boot, uint64_t seed, double* abar,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_boot_mean, dim3((unsigned)n_boot), dim3(kRB), 0, st, a_runs, n_runs, n, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), abar);
+}
+
+// ---------------------------------------------------------------------------
+// Probability density P_beta(E) = rho~(E) e^{beta E} / Z (Sec. 3.4) of the
+// piecewise-exponential rho~ of eq. (rhoguess): in interval k (centre c_k,
+// width s) ln rho~(E) = L_k - a_k (E - c_k), continuous at the edges by the
+// trapezium recursion.  Z is the exact integral over the covered range:
+// Z = sum_k s e^{L_k + beta c_k} sinh(x_k)/x_k, x_k = (beta - a_k) s / 2.
+// ---------------------------------------------------------------------------
+__device__ double log_sinhc(double x) {
+    const double ax = fabs(x);
+    if (ax < 1e-3) return ax * ax * (1.0 / 6.0) - ax * ax * ax * ax * (1.0 / 180.0);
+    if (ax < 20.0) return log(sinh(ax) / ax);
+    return ax - log(2.0 * ax) + log1p(-exp(-2.0 * ax));
+}
+
+// one block: ln Z, with the row maximum subtracted before the sum
+__global__ __launch_bounds__(kRB) void k_logz(const double* __restrict__ c, const double* __restrict__ L,
+                                               const double* __restrict__ a, int n, double s, double beta,
+                                               double* __restrict__ lnz) {
+    __shared__ double sh[kRB / 64];
+    double m = -INFINITY;
+    for (int k = threadIdx.x; k < n; k += kRB)
+        m = fmax(m, L[k] + beta * c[k] + log_sinhc((beta - a[k]) * 0.5 * s));
+    m = block_max(m, sh);
+    double z = 0.0;
+    for (int k = threadIdx.x; k < n; k += kRB)
+        z += exp(L[k] + beta * c[k] + log_sinhc((beta - a[k]) * 0.5 * s) - m);
+    z = block_sum(z, sh);
+    if (threadIdx.x == 0) lnz[0] = m + log(s * z);
+}
+
+// ln P at m points E (one thread each; -inf outside the covered range)
+__global__ void k_logp(const double* __restrict__ c, const double* __restrict__ L, const double* __restrict__ a,
+                       int n, double s, double beta, const double* __restrict__ E, int m,
+                       const double* __restrict__ lnz, double* __restrict__ logp) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= m) return;
+    const double lo = c[0] - 0.5 * s, hi = c[n - 1] + 0.5 * s, e = E[i];
+    if (!(e >= lo && e <= hi)) {
+        logp[i] = -INFINITY;
+        return;
+    }
+    int k = (int)floor((e - lo) / s);
+    k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+    logp[i] = (L[k] + beta * c[k] - lnz[0]) + (beta - a[k]) * (e - c[k]);
+}
+
+// Interior local maxima of ln P: ln P is linear with slope beta - a_k in
+// interval k, so the edge between k and k+1 is a maximum iff beta - a_k > 0
+// and beta - a_{k+1} <= 0 (one thread; every maximum counted, at most
+// max_peaks stored in order of E).
+__global__ void k_peaks(const double* __restrict__ c, const double* __restrict__ L, const double* __restrict__ a,
+                        int n, double s, double beta, const double* __restrict__ lnz, int max_peaks,
+                        double* __restrict__ E_out, double* __restrict__ lp_out, int* __restrict__ n_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int np = 0;
+    for (int k = 0; k + 1 < n; ++k) {
+        if (beta - a[k] > 0.0 && beta - a[k + 1] <= 0.0) {
+            if (np < max_peaks) {
+                E_out[np] = c[k] + 0.5 * s;
+                lp_out[np] = (L[k] + beta * c[k] - lnz[0]) + (beta - a[k]) * (0.5 * s);
+            }
+            ++np;
+        }
+    }
+    *n_out = np;
+}
+
+// scratch: n (ln rho) + 1 (ln Z) doubles
+void launch_prob(const double* c, const double* a, int n, double s, double beta, const double* E, int m,
+                 double* logp, int max_peaks, double* E_pk, double* lp_pk, int* n_pk, double* scratch,
+                 hipStream_t st) {
+    double* L = scratch;
+    double* lnz = scratch + n;
+    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, 1, s, L);
+    hipLaunchKernelGGL(k_logz, dim3(1), dim3(kRB), 0, st, c, L, a, n, s, beta, lnz);
+    if (m > 0) hipLaunchKernelGGL(k_logp, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, c, L, a, n, s, beta,
+                                  E, m, lnz, logp);
+    if (n_pk) hipLaunchKernelGGL(k_peaks, dim3(1), dim3(64), 0, st, c, L, a, n, s, beta, lnz, max_peaks, E_pk, lp_pk,
+                                 n_pk);
+}
+
+// ---------------------------------------------------------------------------
+// Reweighting of multicanonical samples (Sec. 2.6, eq. (4.7)): with the
+// sampling weight W(E) = 1/rho~(E) (first and last pieces continued outside
+// the intervals), <O>_beta = <O e^{beta E} / W(E)>_W / <e^{beta E} / W(E)>_W.
+// One block per beta: <E>, Var(E) -> <u> = <E>/(6V), C_V = Var(E)/(6V).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rw_lnw(const double* c, const double* L, const double* a, int n, double s,
+                                         double e) {
+    int k = (int)floor((e - (c[0] - 0.5 * s)) / s);
+    k = k < 0 ? 0 : (k > n - 1 ? n - 1 : k);
+    return -L[k] + a[k] * (e - c[k]);
+}
+
+__global__ __launch_bounds__(kRB) void k_rw_moments(const double* __restrict__ E, long m,
+                                                     const double* __restrict__ c, const double* __restrict__ L,
+                                                     const double* __restrict__ a, int n, double s,
+                                                     const double* __restrict__ beta, double six_v,
+                                                     double* __restrict__ u, double* __restrict__ cv) {
+    __shared__ double sh[kRB / 64];
+    const double b = beta[blockIdx.x];
+    double mx = -INFINITY;
+    for (long i = threadIdx.x; i < m; i += kRB) mx = fmax(mx, b * E[i] - rw_lnw(c, L, a, n, s, E[i]));
+    mx = block_max(mx, sh);
+    double z = 0.0, s1 = 0.0;
+    for (long i = threadIdx.x; i < m; i += kRB) {
+        const double w = exp(b * E[i] - rw_lnw(c, L, a, n, s, E[i]) - mx);
+        z += w;
+        s1 += w * E[i];
+    }
+    z = block_sum(z, sh);
+    s1 = block_sum(s1, sh);
+    const double mu = s1 / z;
+    double s2 = 0.0;
+    for (long i = threadIdx.x; i < m; i += kRB) {
+        const double w = exp(b * E[i] - rw_lnw(c, L, a, n, s, E[i]) - mx);
+        s2 += w * (E[i] - mu) * (E[i] - mu);
+    }
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        u[blockIdx.x] = mu / six_v;
+        cv[blockIdx.x] = s2 / z / six_v;
+    }
+}
+
+// scratch: n doubles (ln rho)
+void launch_reweight(const double* E, long m, const double* c, const double* a, int n, double s, const double* beta,
+                     int nb, double six_v, double* u, double* cv, double* scratch, hipStream_t st) {
+    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, 1, s, scratch);
+    hipLaunchKernelGGL(k_rw_moments, dim3((unsigned)nb), dim3(kRB), 0, st, E, m, c, scratch, a, n, s, beta, six_v, u,
+                       cv);
 }
 
 }  // namespace llr

@@ -19,7 +19,7 @@
 
 namespace llr {
 
-enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeTune = 3 };
+enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeMuca = 3, kModeTune = kHbModeTune };
 
 __device__ __forceinline__ int find_lat_site(const LatTable& lt, int b) {
     int li = 0;
@@ -38,6 +38,43 @@ __device__ __forceinline__ void decode_half(const LatDev& L, uint32_t h, int p, 
     x[2] = (int)(r2 - r3 * (uint32_t)L.L);
     x[3] = (int)r3;
     x[0] = 2 * x0h + ((p + x[1] + x[2] + x[3]) & 1);
+}
+// A half index in mixed radix: h = x0h + (L/2)(x1 + L(x2 + L x3)).  The
+// class links of one thread lie kBlock half indices apart, so the next one's
+// digits follow from adding kBlock's digits (st0..st3) with carries, without
+// the divisions of decode_half.  Digits beyond the lattice only arise for
+// h >= V/2, which the kernels skip.
+struct HalfPos {
+    int x0h, x1, x2, x3;
+};
+__device__ __forceinline__ HalfPos half_pos(const LatDev& L, uint32_t h) {
+    HalfPos q;
+    const uint32_t r1 = L.hL == 1 ? h : fdiv(h, L.mhL);
+    q.x0h = (int)(h - r1 * (uint32_t)L.hL);
+    const uint32_t r2 = fdiv(r1, L.mL);
+    q.x1 = (int)(r1 - r2 * (uint32_t)L.L);
+    const uint32_t r3 = fdiv(r2, L.mL);
+    q.x2 = (int)(r2 - r3 * (uint32_t)L.L);
+    q.x3 = (int)r3;
+    return q;
+}
+__device__ __forceinline__ void advance_pos(const LatDev& L, HalfPos& q) {
+    q.x0h += L.st0;
+    int c = q.x0h >= L.hL ? 1 : 0;
+    q.x0h -= c * L.hL;
+    q.x1 += L.st1 + c;
+    c = q.x1 >= L.L ? 1 : 0;
+    q.x1 -= c * L.L;
+    q.x2 += L.st2 + c;
+    c = q.x2 >= L.L ? 1 : 0;
+    q.x2 -= c * L.L;
+    q.x3 += L.st3 + c;
+}
+__device__ __forceinline__ void pos_coords(const HalfPos& q, int p, int x[4]) {
+    x[1] = q.x1;
+    x[2] = q.x2;
+    x[3] = q.x3;
+    x[0] = 2 * q.x0h + ((p + q.x1 + q.x2 + q.x3) & 1);
 }
 __device__ __forceinline__ uint32_t half_of(const LatDev& L, int y0, int y1, int y2, int y3) {
     return (uint32_t)((y0 >> 1) + L.hL * (y1 + L.L * (y2 + L.L * y3)));
@@ -75,12 +112,11 @@ __device__ __forceinline__ void neighbour_offsets(const LatDev& L, const int x[4
     const int odd = x[0] & 1;
     up[0] = odd ? (x[0] == L.L - 1 ? 1 - L.hL : 1) : 0;
     dn[0] = odd ? 0 : (x[0] == 0 ? L.hL - 1 : -1);
-    int stride = L.hL;
 #pragma unroll
     for (int nu = 1; nu < 4; ++nu) {
-        up[nu] = x[nu] == L.L - 1 ? -(L.L - 1) * stride : stride;
-        dn[nu] = x[nu] == 0 ? (L.L - 1) * stride : -stride;
-        stride *= L.L;
+        // selects between per-lattice constants (no per-link multiply)
+        up[nu] = x[nu] == L.L - 1 ? -L.hwrap[nu] : L.hstr[nu];
+        dn[nu] = x[nu] == 0 ? L.hwrap[nu] : -L.hstr[nu];
     }
 }
 
@@ -202,6 +238,18 @@ __device__ __forceinline__ long long to_fixed<float>(float v, const LatDev& L) {
     return sh >= 0 ? (q << sh) : ((q + (1ll << (-sh - 1))) >> (-sh));
 }
 
+// ln W(E) = -ln rho~(E) of the multicanonical weight (Sec. 2.6): in interval
+// k, -ln rho~(c_k) + a_k (E - c_k); below the first and above the last
+// interval the first and last pieces continue, i.e. W = e^{a_0 E + c_1} and
+// e^{a_{n-1} E + c_2} with the constants fixed by continuity.
+__device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, double E) {
+    const double* c = s.cen + L.chain0;
+    const double lo = c[0] - 0.5 * L.ds;
+    int k = (int)floor((E - lo) / L.ds);
+    k = k < 0 ? 0 : (k > L.n_chains - 1 ? L.n_chains - 1 : k);
+    return -s.mu_lnrho[L.chain0 + k] + s.a[L.chain0 + k] * (E - c[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Heatbath class pass.  Link conditional ~ exp(a R cos(theta + phi)) with
 // (C, S) the staple sums, R = |C + iS|, phi = arg(C + iS); theta' = X - phi
@@ -243,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
     T* chain = chain_base(L, th, cl);
     const int gi = s.itv[g];
-    const double acoup = mode == kModeApproach ? s.b[8 * g + colour] : s.a[gi];
+    const double acoup = mode == kModeApproach ? s.b[8 * g + colour] : (mode == kModeMuca ? s.mu_b[li] : s.a[gi]);
     const uint32_t sweep = kind == kApproach ? *s.approach_ctr : *s.sweep_ctr;
     const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
     const uint32_t c3 = (uint32_t)(gi - L.chain0);
@@ -253,13 +301,15 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const uint32_t hbase = (uint32_t)tile * NT;
 
     T C[LPT], S[LPT], t_old[LPT];
+    HalfPos pos = half_pos(L, hbase + tid);
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + tid;
+        if (r) advance_pos(L, pos);
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
         if (h < L.V2) {
             int x[4];
-            decode_half(L, h, parity, x);
+            pos_coords(pos, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
             t_old[r] = ld_plane(pown, h);
         }
@@ -375,6 +425,15 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             s.eta[qq] = eta;
             s.b[qq] = fmin(4.0, fmax(0.0, s.b[qq] + eta * (double)sg));
             s.sprev[qq] = sg;
+        } else if (mode == kModeMuca) {
+            // target W(E) = 1/rho~(E), proposal the class heatbath at coupling
+            // b: the proposal's normalisation depends only on the other
+            // classes, so the Metropolis-Hastings ratio is
+            // W(E')/W(E) e^{-b (E' - E)}
+            const double lr = muca_lnw(L, s, En) - muca_lnw(L, s, E0) - acoup * (En - E0);
+            const uint4 w = philox10(make_uint4(c3, ctr1_word(0, (uint32_t)colour, kMuca, (uint32_t)L.lat_id), sweep, 0u),
+                                     k0, k1);
+            acc = lr >= 0.0 || ((double)w.x + 0.5) * 0x1p-32 < exp(lr);
         } else {
             acc = mode == kModeFree;
         }
@@ -416,13 +475,15 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
     T* pout = to_alt ? chain + (size_t)(((((curw >> (8 * colour)) & 1ull) ^ 1ull) * 8ull) + colour) * L.V2 : pown;
     const uint32_t hbase = (uint32_t)tile * NT;
     T C[LPT], S[LPT], t_old[LPT];
+    HalfPos pos = half_pos(L, hbase + threadIdx.x);
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + threadIdx.x;
+        if (r) advance_pos(L, pos);
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
         if (h < L.V2) {
             int x[4];
-            decode_half(L, h, parity, x);
+            pos_coords(pos, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
             t_old[r] = ld_plane(pown, h);
         }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libllr.so")
 
 OK, WARN_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
-MODE_RESTRICTED, MODE_APPROACH, MODE_FREE = 0, 1, 2
+MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA = 0, 1, 2, 3
 N_PARAMS = 4417
 
 _lib = None
@@ -77,6 +77,19 @@ _SIGS = {
                         _p(C.c_double), C.c_int, _p(C.c_double), _p(C.c_double), _p(C.c_double)],
     "llr_beta_c": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double, C.c_double,
                    C.c_double, C.c_double, C.c_double, _p(C.c_double), _p(C.c_double)],
+    "llr_prob_density": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double,
+                         _p(C.c_double), C.c_int, _p(C.c_double)],
+    "llr_prob_peaks": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double, C.c_int,
+                       _p(C.c_double), _p(C.c_double), _p(C.c_int)],
+    "llr_bootstrap": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_int, C.c_double, C.c_double,
+                      C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_uint64, _p(C.c_double),
+                      _p(C.c_double)],
+    "llr_fss_fit": [_p(C.c_double), _p(C.c_double), _p(C.c_double), C.c_int, _p(C.c_double), C.c_int,
+                    _p(C.c_double), _p(C.c_double), _p(C.c_double)],
+    "llr_muca_begin": [C.c_void_p, _p(C.c_double)],
+    "llr_muca_sweeps": [C.c_void_p, C.c_int, C.c_longlong, _p(C.c_double)],
+    "llr_muca_reweight": [C.c_void_p, _p(C.c_double), C.c_long, _p(C.c_double), _p(C.c_double), C.c_int,
+                          C.c_double, C.c_double, _p(C.c_double), C.c_int, _p(C.c_double), _p(C.c_double)],
     "llr_mlp_init": [C.c_void_p, C.c_uint64, _p(C.c_float)],
     "llr_mlp_predict": [C.c_void_p, _p(C.c_float), _p(C.c_float), _p(C.c_float), C.c_int, C.c_int,
                         _p(C.c_double)],
@@ -331,6 +344,54 @@ class Context:
                                 tol, C.byref(bc), C.byref(pk)))
         return bc.value, pk.value
 
+    def prob_density(self, centres, a, s, beta, E):
+        """ln P_beta(E) of the piecewise-exponential density of states."""
+        c, a, E = _arr(centres, np.float64), _arr(a, np.float64), _arr(np.atleast_1d(E), np.float64)
+        out = np.empty(E.size)
+        _check(lib().llr_prob_density(self.h, _ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, beta,
+                                      _ptr(E, C.c_double), E.size, _ptr(out, C.c_double)))
+        return out
+
+    def prob_peaks(self, centres, a, s, beta, max_peaks=64):
+        """Interior maxima of P_beta(E): (energies, ln P) in ascending E."""
+        c, a = _arr(centres, np.float64), _arr(a, np.float64)
+        Ep, lp, nf = np.empty(max_peaks), np.empty(max_peaks), C.c_int()
+        _check(lib().llr_prob_peaks(self.h, _ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, beta, max_peaks,
+                                    _ptr(Ep, C.c_double), _ptr(lp, C.c_double), C.byref(nf)))
+        k = min(nf.value, max_peaks)
+        return Ep[:k], lp[:k]
+
+    def bootstrap(self, centres, a_runs, s, six_v, blo, bhi, n_boot, seed, h=1e-5, tol=1e-9):
+        """beta_c and C_V peak of n_boot bootstrap samples over the runs (rows of a_runs)."""
+        c, ar = _arr(centres, np.float64), _arr(np.atleast_2d(a_runs), np.float64)
+        bc, pk = np.empty(n_boot), np.empty(n_boot)
+        _check(lib().llr_bootstrap(self.h, _ptr(c, C.c_double), _ptr(ar, C.c_double), ar.shape[0], ar.shape[1], s,
+                                   six_v, blo, bhi, h, tol, n_boot, seed, _ptr(bc, C.c_double),
+                                   _ptr(pk, C.c_double)))
+        return bc, pk
+
+    # ---- multicanonical sampling and reweighting
+    def muca_begin(self, b):
+        """Weights W = 1/rho~ from the current a_k; b: proposal coupling per lattice."""
+        b = _arr(np.broadcast_to(np.asarray(b, dtype=np.float64), (len(self.lattices),)), np.float64)
+        _check(lib().llr_muca_begin(self.h, _ptr(b, C.c_double)))
+
+    def muca_sweeps(self, n_sweeps, sweep0=0, want_E=True):
+        """n_sweeps multicanonical sweeps; returns E after every sweep (n_sweeps, chains)."""
+        nch = sum(x[1] for x in self.lattices)
+        E = np.empty((n_sweeps, nch)) if want_E else None
+        _check(lib().llr_muca_sweeps(self.h, n_sweeps, sweep0, _ptr(E, C.c_double)))
+        return E
+
+    def muca_reweight(self, E, centres, a, s, six_v, beta):
+        E, c, a = _arr(np.ravel(E), np.float64), _arr(centres, np.float64), _arr(a, np.float64)
+        b = _arr(np.atleast_1d(beta), np.float64)
+        u, cv = np.empty(b.size), np.empty(b.size)
+        _check(lib().llr_muca_reweight(self.h, _ptr(E, C.c_double), E.size, _ptr(c, C.c_double),
+                                       _ptr(a, C.c_double), a.size, s, six_v, _ptr(b, C.c_double), b.size,
+                                       _ptr(u, C.c_double), _ptr(cv, C.c_double)))
+        return u, cv
+
     # ---- network
     def mlp_init(self, seed):
         w = np.empty(N_PARAMS, dtype=np.float32)
@@ -359,3 +420,13 @@ class Context:
         _check(lib().llr_mlp_train(self.h, _ptr(w, C.c_float), _ptr(u, C.c_float), _ptr(invL, C.c_float),
                                    _ptr(a, C.c_double), u.size, epochs, lr, int(bf16), _ptr(hist, C.c_double)))
         return w, hist[:epochs]
+
+
+def fss_fit(L, y, sigma, powers):
+    """Weighted least squares y(L) = sum_j p_j L^powers_j: (params, errors, chi2_red)."""
+    L, y, sg, pw = (_arr(v, np.float64) for v in (L, y, sigma, powers))
+    p, e, chi2 = np.empty(pw.size), np.empty(pw.size), C.c_double()
+    _check(lib().llr_fss_fit(_ptr(L, C.c_double), _ptr(y, C.c_double), _ptr(sg, C.c_double), L.size,
+                             _ptr(pw, C.c_double), pw.size, _ptr(p, C.c_double), _ptr(e, C.c_double),
+                             C.byref(chi2)))
+    return p, e, chi2.value

@@ -1,0 +1,124 @@
+"""GPU parity of the multicanonical sampling with W = 1/rho~ and of the
+reweighting of eq. (4.7) (Sec. 2.6), through the C ABI, against the oracle:
+FP64 energies after every sweep within 1e-9 relative and the same number of
+accepted classes (so the decisions agree), angles within 1e-10 after one
+sweep and, after four, a median within 1e-10 and no difference of the size a
+differing decision makes, the b = beta case bit-identical to canonical
+sweeps, reweighted moments within 1e-9."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.inputs import circ_dist, random_state
+
+pytestmark = pytest.mark.gpu
+
+SEED = 1509083910
+
+
+@pytest.fixture(scope="module")
+def llr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1509_08391_amd import llr as m
+    m.lib()
+    return m
+
+
+def _states(L, n, seed):
+    d = 4
+    th = np.concatenate([random_state(d, L, 1, seed=seed + k, u_target=0.45 + 0.3 * k / n) for k in range(n)])
+    E = np.array([oracle.energy(d, L, th[k]) for k in range(n)])
+    return th, E
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_muca_sweeps_match_oracle_fp64(llr, L):
+    import torch
+    d, n = 4, 12
+    V6 = 6 * L ** 4
+    th, E = _states(L, n, 40 + L)
+    dE = 0.05 * V6
+    E_low = 0.35 * V6 + dE * np.arange(n)
+    cen = E_low + 0.5 * dE
+    k = np.arange(n)
+    a = 0.7 + 0.04 * k + 0.05 * np.sin(k)
+    b = 0.85
+    ctx = llr.Context(precision=llr.FP64)
+    ctx.set_params(seed=SEED)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    ctx.set_a(0, a)
+    ctx.import_state(0, torch.from_numpy(th))
+    ctx.muca_begin([b])
+    oracle.set_muca(cen, a, dE)
+    tr = th.copy()
+    Er = E.copy()
+    acc = 0
+    # one sweep: angles within 1e-10.  Three more: with the random numbers
+    # fixed, last-bit differences of the two sides' transcendentals grow from
+    # sweep to sweep (fastest in these low-density states, to ~1e-5); a
+    # differing decision would move E by a class Delta E and the angles by
+    # O(1), so the energies, the accept counts and max < 1e-3 with a median
+    # below 1e-10 are the bar there.
+    for (n_sw, s0, tol) in [(1, 11, 1e-10), (3, 12, 1e-3)]:
+        Eg = ctx.muca_sweeps(n_sw, sweep0=s0)
+        got = ctx.export_state(0).cpu().numpy()
+        for t in range(n_sw):
+            Er, br = oracle.sweeps(d, L, tr, [b] * n, E_low, E_low + dE, np.arange(n), Er, 1, s0 + t,
+                                   mode=oracle.MODE_MUCA, seed=SEED)
+            acc += sum(bin(int(x) & 0xff).count("1") for x in br[0])
+            assert np.max(np.abs(Eg[t] - Er) / np.abs(Er)) < 1e-9, (s0, t)
+        dist = circ_dist(got, tr)
+        assert np.max(dist) < tol and np.median(dist) < 1e-10, (n_sw, np.max(dist), np.median(dist))
+    hp, ha, _, _ = ctx.stats()
+    ctx.close()
+    assert int(ha.sum()) == acc
+    assert 0 < acc < 8 * 4 * n                         # both outcomes occur
+
+
+def test_muca_equal_coupling_is_canonical_heatbath(llr):
+    """Constant a_k = b: W = e^{b E} and every class is accepted; the sweeps are
+    the free heatbath sweeps bit for bit."""
+    import torch
+    L, n = 4, 6
+    V6 = 6 * L ** 4
+    th, E = _states(L, n, 7)
+    dE = 0.05 * V6
+    E_low = 0.35 * V6 + dE * np.arange(n)
+    out = []
+    for muca in (True, False):
+        ctx = llr.Context(precision=llr.FP64)
+        ctx.set_params(seed=SEED)
+        ctx.add_lattice(L, E_low, dE)
+        ctx.bind_state()
+        ctx.set_a(0, np.full(n, 1.0))
+        ctx.import_state(0, torch.from_numpy(th))
+        if muca:
+            ctx.muca_begin([1.0])
+            ctx.muca_sweeps(3, sweep0=5)
+            hp, ha, _, _ = ctx.stats()
+            assert np.array_equal(hp, ha)
+        else:
+            ctx.recompute_energy()
+            ctx.sweeps(3, sweep0=5, mode=llr.MODE_FREE)
+        out.append(ctx.export_state(0).cpu().numpy())
+        ctx.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_muca_reweight_matches_oracle(llr):
+    rng = np.random.default_rng(2)
+    n, s = 64, 194.4
+    c = 0.58 * 124416 + s * (np.arange(n) + 0.5)
+    k = np.arange(n)
+    a = 1.0 + 0.0003 * k - 0.004 * np.exp(-((k - 40) / 8.0) ** 2)
+    E = rng.uniform(c[0] - 3 * s, c[-1] + 3 * s, 50000)
+    beta = np.linspace(1.004, 1.016, 13)
+    ctx = llr.Context(precision=llr.FP64)
+    ug, cg = ctx.muca_reweight(E, c, a, s, 124416.0, beta)
+    ctx.close()
+    uo, co = oracle.muca_reweight(E, c, a, s, 124416.0, beta)
+    assert np.max(np.abs(ug / uo - 1)) < 1e-10
+    assert np.max(np.abs(cg / co - 1)) < 1e-9
