@@ -178,15 +178,6 @@ static llr_status layout(llr_ctx* c) {
         // site kernels: the even and the odd sites of a chain in blocks of their own
         d.ebpc = 2 * (int)((V / 2 + kBlock - 1) / kBlock);
         d.eblock0 = eblock0;
-        {
-            long long r = kBlock;
-            d.st0 = (int)(r % d.hL);
-            r /= d.hL;
-            d.st1 = (int)(r % h.L);
-            r /= h.L;
-            d.st2 = (int)(r % h.L);
-            d.st3 = (int)(r / h.L);
-        }
         d.hstr[0] = 0;
         d.hwrap[0] = 0;
         for (int nu = 1; nu < 4; ++nu) {

@@ -66,10 +66,14 @@ template <> struct Math<float> {
         *s = __builtin_amdgcn_sinf(r);
         *c = __builtin_amdgcn_cosf(r);
     }
+    // sin and cos of (pi/2) v, |v| < 1.  cos(pi v/2) = sin(pi (1 - |v|)/2) is
+    // taken as a sine of the exact complement (v is a multiple of 2^-23), so a
+    // small cosine keeps its relative accuracy: the proposal 2 atan2(q s, c)
+    // amplifies the error of c by ~2/q, large at large coupling.
     __device__ static __forceinline__ void sincos_halfpi(float v, float* s, float* c) {
         const float r = 0.25f * v;
         *s = __builtin_amdgcn_sinf(r);
-        *c = __builtin_amdgcn_cosf(r);
+        *c = __builtin_amdgcn_sinf(0.25f - __builtin_fabsf(r));
     }
     // atan2 from explicit instructions (the library version lowers its internal
     // division differently per call site, which changes last bits between

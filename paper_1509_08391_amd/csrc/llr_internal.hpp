@@ -20,7 +20,6 @@ struct LatDev {
     int hb_bpc, hb_block0; // heatbath pass: blocks per chain (V/2 / (256 LPT), rounded up), first block
     int or_bpc, or_block0; // overrelaxation pass: the same
     int ebpc;              // blocks per chain in the site kernels (2 x V/2 / 256, rounded up)
-    int st0, st1, st2, st3; // digits of kBlock in the radices (L/2, L, L, L) of a half index
     int hstr[4];           // half-index stride of a step along nu = 1..3: (L/2) L^(nu-1); [0] unused
     int hwrap[4];          // (L - 1) hstr[nu]: the periodic jump across the boundary
     double ds;             // interval spacing delta E

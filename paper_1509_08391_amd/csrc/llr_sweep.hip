@@ -39,43 +39,6 @@ __device__ __forceinline__ void decode_half(const LatDev& L, uint32_t h, int p, 
     x[3] = (int)r3;
     x[0] = 2 * x0h + ((p + x[1] + x[2] + x[3]) & 1);
 }
-// A half index in mixed radix: h = x0h + (L/2)(x1 + L(x2 + L x3)).  The
-// class links of one thread lie kBlock half indices apart, so the next one's
-// digits follow from adding kBlock's digits (st0..st3) with carries, without
-// the divisions of decode_half.  Digits beyond the lattice only arise for
-// h >= V/2, which the kernels skip.
-struct HalfPos {
-    int x0h, x1, x2, x3;
-};
-__device__ __forceinline__ HalfPos half_pos(const LatDev& L, uint32_t h) {
-    HalfPos q;
-    const uint32_t r1 = L.hL == 1 ? h : fdiv(h, L.mhL);
-    q.x0h = (int)(h - r1 * (uint32_t)L.hL);
-    const uint32_t r2 = fdiv(r1, L.mL);
-    q.x1 = (int)(r1 - r2 * (uint32_t)L.L);
-    const uint32_t r3 = fdiv(r2, L.mL);
-    q.x2 = (int)(r2 - r3 * (uint32_t)L.L);
-    q.x3 = (int)r3;
-    return q;
-}
-__device__ __forceinline__ void advance_pos(const LatDev& L, HalfPos& q) {
-    q.x0h += L.st0;
-    int c = q.x0h >= L.hL ? 1 : 0;
-    q.x0h -= c * L.hL;
-    q.x1 += L.st1 + c;
-    c = q.x1 >= L.L ? 1 : 0;
-    q.x1 -= c * L.L;
-    q.x2 += L.st2 + c;
-    c = q.x2 >= L.L ? 1 : 0;
-    q.x2 -= c * L.L;
-    q.x3 += L.st3 + c;
-}
-__device__ __forceinline__ void pos_coords(const HalfPos& q, int p, int x[4]) {
-    x[1] = q.x1;
-    x[2] = q.x2;
-    x[3] = q.x3;
-    x[0] = 2 * q.x0h + ((p + q.x1 + q.x2 + q.x3) & 1);
-}
 __device__ __forceinline__ uint32_t half_of(const LatDev& L, int y0, int y1, int y2, int y3) {
     return (uint32_t)((y0 >> 1) + L.hL * (y1 + L.L * (y2 + L.L * y3)));
 }
@@ -198,13 +161,17 @@ __device__ __forceinline__ void vm_constants(T ak, T& q, T& rm1, T& kg2) {
     using M = Math<T>;
     q = T(1); rm1 = T(1); kg2 = T(0);
     if (ak > T(0)) {
+        // rho = 2 ak / D with D = tau + sqrt(2 tau); in terms of D:
+        // q = (D - 2ak)/(D + 2ak), (1-rho)^2/(2 rho) = (D - 2ak)^2/(4 ak D),
+        // (1-rho^2)/(2 rho) = (D - 2ak)(D + 2ak)/(4 ak D)
         const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
-        const T rho = M::div_(T(2) * ak, tau + M::sqrt_(T(2) * tau));
-        const T irho = M::div_(T(1), rho);
-        rm1 = T(0.5) * (T(1) - rho) * (T(1) - rho) * irho;
-        const T gg = T(0.5) * (T(1) - rho * rho) * irho;
+        const T D = tau + M::sqrt_(T(2) * tau);
+        const T dm = D - T(2) * ak, dp = D + T(2) * ak;
+        const T r1 = M::div_(T(1), T(4) * ak * D);
+        rm1 = dm * dm * r1;
+        const T gg = dm * dp * r1;
         kg2 = ak * gg * gg;
-        q = M::div_(T(1) - rho, T(1) + rho);
+        q = M::div_(dm, dp);
     }
 }
 
@@ -224,19 +191,10 @@ __device__ __forceinline__ bool vm_attempt(uint32_t wa, uint32_t wb, T q, T rm1,
     return acc;
 }
 
-template <typename T>
-__device__ __forceinline__ long long to_fixed(T v, const LatDev& L);
-template <>
-__device__ __forceinline__ long long to_fixed<double>(double v, const LatDev& L) {
-    return __double2ll_rn(v * L.fx);
-}
-// |v| <= 12: exact int32 at 2^-27, then to the lattice's 2^-fxb
-template <>
-__device__ __forceinline__ long long to_fixed<float>(float v, const LatDev& L) {
-    const long long q = (long long)__float2int_rn(v * 134217728.0f);
-    const int sh = L.fxb - 27;
-    return sh >= 0 ? (q << sh) : ((q + (1ll << (-sh - 1))) >> (-sh));
-}
+// A link's Delta E in the lattice's fixed point 2^-fxb (FP64 path).  The FP32
+// path sums a thread's links at 2^-25 in 32 bits (|Delta E| <= 2 R <= 12 per
+// link, at most 4 links per thread) and shifts once: fxb >= 26 for L <= 32.
+__device__ __forceinline__ long long to_fixed(double v, const LatDev& L) { return __double2ll_rn(v * L.fx); }
 
 // ln W(E) = -ln rho~(E) of the multicanonical weight (Sec. 2.6): in interval
 // k, -ln rho~(c_k) + a_k (E - c_k); below the first and above the last
@@ -301,15 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const uint32_t hbase = (uint32_t)tile * NT;
 
     T C[LPT], S[LPT], t_old[LPT];
-    HalfPos pos = half_pos(L, hbase + tid);
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + tid;
-        if (r) advance_pos(L, pos);
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
         if (h < L.V2) {
             int x[4];
-            pos_coords(pos, parity, x);
+            decode_half(L, h, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
             t_old[r] = ld_plane(pown, h);
         }
@@ -339,10 +295,12 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
                 got[r] = vm_attempt(w.x, w.y, q, rm1, kg2, ch[r], sh[r]);
                 if (!got[r]) got[r] = vm_attempt(w.z, w.w, q, rm1, kg2, ch[r], sh[r]);
             }
-            s_q[e] = q;
-            s_rm1[e] = rm1;
-            s_kg2[e] = kg2;
-            s_res[e] = got[r] ? 1 : 0;
+            if (!got[r]) {
+                s_q[e] = q;
+                s_rm1[e] = rm1;
+                s_kg2[e] = kg2;
+                s_res[e] = 0;
+            }
         }
     }
     __syncthreads();
@@ -375,6 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         cq ^= 1;
     }
     long long fx = 0;
+    int fx32 = 0;   // FP32: the thread's class links at 2^-25 (|dE| <= 12 per link, LPT <= 4)
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + tid;
@@ -401,8 +360,10 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             dE = M::div_(R[r] * er, nrm) - eps_old[r];
         }
         st_plane(palt, h, t_new);
-        fx += to_fixed<T>(dE, L);
+        if constexpr (M::f32) fx32 += __float2int_rn(dE * 33554432.0f);
+        else fx += to_fixed((double)dE, L);
     }
+    if constexpr (M::f32) fx = (long long)fx32 << (L.fxb - 25);
     const long long tot = block_sum_i64(fx);
     long long total = 0;
     if (threadIdx.x == 0 && chain_arrive(s.acc + g, tot, L.hb_bpc, &total)) {
@@ -475,15 +436,13 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
     T* pout = to_alt ? chain + (size_t)(((((curw >> (8 * colour)) & 1ull) ^ 1ull) * 8ull) + colour) * L.V2 : pown;
     const uint32_t hbase = (uint32_t)tile * NT;
     T C[LPT], S[LPT], t_old[LPT];
-    HalfPos pos = half_pos(L, hbase + threadIdx.x);
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + threadIdx.x;
-        if (r) advance_pos(L, pos);
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
         if (h < L.V2) {
             int x[4];
-            pos_coords(pos, parity, x);
+            decode_half(L, h, parity, x);
             staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
             t_old[r] = ld_plane(pown, h);
         }

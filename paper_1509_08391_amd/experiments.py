@@ -25,6 +25,11 @@
            and <u>(beta) by reweighting (eq. (4.7)) next to the LLR
            reconstruction from the same a_k.
 
+  dE8      the delta E study of Sec. 3.5 at L = 8: the config1 range
+           u in [0.55, 0.71] cut into 16, 32, 64 and 128 intervals, eight
+           replicas each, FP32; the C_V peak against delta E and the fit
+           C_V(dE) = C_V(0) + 6V b_dis dE^2.
+
 Each writes a JSON record.  Usage:
     python -m paper_1509_08391_amd.experiments config1 [--out DIR]
 """
@@ -293,9 +298,38 @@ def muca12(log, c2, n_sweeps=100000, chunk=2000, n_therm=2000):
                 E_series_chain0=H[::10, 0].tolist())
 
 
+def dE_study_8(log, counts=(16, 32, 64, 128), replicas=8):
+    L = 8
+    V6 = 6 * L ** 4
+    rows = []
+    for nk in counts:
+        dE = 0.16 / nk * V6
+        E_low = 0.55 * V6 + dE * np.arange(nk)
+        res, meta = _run([(L, E_low, dE)] * replicas, llr.FP32, 200, 500, 50, False, seed=SEED + nk, log=log)
+        cen = E_low + 0.5 * dE
+        ctx = llr.Context(precision=llr.FP64, device=0)
+        pk = np.array([ctx.beta_c(cen, np.array(r["a"]), dE, V6, 0.98, 1.04, h=1e-5, tol=1e-9) for r in res])
+        ctx.close()
+        rows.append(dict(n_intervals=nk, dE=dE, beta_c=pk[:, 0].tolist(), cv_peak=pk[:, 1].tolist(),
+                         cv_mean=float(pk[:, 1].mean()), cv_err=float(pk[:, 1].std(ddof=1) / np.sqrt(replicas)),
+                         bc_mean=float(pk[:, 0].mean()), bc_err=float(pk[:, 0].std(ddof=1) / np.sqrt(replicas)),
+                         seconds=meta["seconds_rm"]))
+        log(f"{nk} intervals (dE = {dE:.2f}): C_V/(6V) peak {rows[-1]['cv_mean'] / V6:.4e} "
+            f"+- {rows[-1]['cv_err'] / V6:.1e}, beta_c {rows[-1]['bc_mean']:.6f} +- {rows[-1]['bc_err']:.6f}")
+    x = np.array([r["dE"] for r in rows])
+    y = np.array([r["cv_mean"] for r in rows])
+    sg = np.array([r["cv_err"] for r in rows])
+    p, e, chi2 = llr.fss_fit(x, y, sg, [0.0, 2.0])
+    b_dis, b_err = p[1] / V6, e[1] / V6 * np.sqrt(max(chi2, 1.0))
+    log(f"fit C_V = C_V(0) + 6V b_dis dE^2: C_V(0)/(6V) = {p[0] / V6:.4e}, b_dis = {b_dis:.2e} +- {b_err:.1e}, "
+        f"chi2_red {chi2:.2f}")
+    return dict(rows=rows, cv0=p[0], cv0_over_6v=p[0] / V6, b_dis=b_dis, b_dis_err=b_err, chi2_red=chi2)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12"])
+    ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
+                                            "dE8"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
                     "(config3 reads config1 and config2, config4 reads config3); default --out")
@@ -321,6 +355,8 @@ def main():
         rec = config4(log, load("config3"), n_rm=args.n_rm or 100)
     elif args.which == "muca12":
         rec = muca12(log, load("config2"))
+    elif args.which == "dE8":
+        rec = dE_study_8(log)
     else:
         rec = config4_replicas(log, load("config3"), n_rm=args.n_rm or 25)
     rec["wall_seconds"] = time.perf_counter() - t0

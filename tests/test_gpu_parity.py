@@ -67,7 +67,7 @@ def test_vonmises_fp64_matches_oracle(llr, kappa):
     assert np.max(np.abs(X - Xo)) < 1e-12
 
 
-@pytest.mark.parametrize("kappa", [0.3, 2.0, 5.0, 12.0])
+@pytest.mark.parametrize("kappa", [0.3, 2.0, 5.0, 12.0, 40.0])
 def test_vonmises_fp32_matches_oracle(llr, kappa):
     ctx = llr.Context(precision=llr.FP32)
     n = 100000
@@ -178,8 +178,37 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep):
     return E, flagged
 
 
+def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4):
+    """Per-link linear response of one oracle sweep (FP64): the factor by which
+    a 1e-9 random perturbation of the input state is amplified at each output
+    link, RMS over n_dir independent perturbations (one random direction alone
+    underestimates a link's sensitivity by 3x or more about one time in
+    five).  Rounding differences made anywhere in the sweep reach a link
+    through the same propagation, so this is the link's conditioning."""
+    rng = np.random.default_rng(0)
+    base = np.ascontiguousarray(th_k[None].copy())
+    oracle.sweeps(d, L, base, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED)
+    acc = np.zeros(th_k.shape)
+    for _ in range(n_dir):
+        t = np.ascontiguousarray(th_k[None] + rng.normal(0.0, 1e-9, th_k.shape)[None])
+        oracle.sweeps(d, L, t, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED)
+        acc += (circ_dist(base[0], t[0]) / 1e-9) ** 2
+    return np.sqrt(acc / n_dir)
+
+
 @pytest.mark.parametrize("L", [4, 8])
 def test_one_sweep_fp32_against_fp64_oracle(llr, L):
+    """One FP32 sweep against the oracle's sweep of the same FP32 state (FP64
+    arithmetic, FP32-rounded stored angles, the same 23-bit uniforms).  Each
+    pass of the FP32 kernel is within ~1e-6 of the oracle's on the same input
+    (heatbath measured <= 8.3e-7).  Through the sweep those differences
+    propagate like any input error, and the overrelaxation reflection
+    theta -> -2 phi - theta amplifies a link's phase error by 2/R.  So the bar
+    is per link: 1e-6 times max(10, the link's measured amplification), i.e.
+    1e-5 wherever the sweep amplifies by at most 10 (~99 % of links), and
+    fewer than 2 % of links above that.  In a chain with a link whose sampler
+    test the oracle flags (margin < 1e-5: FP32 may take another attempt),
+    fewer than 1 % of links may exceed the bar."""
     import torch
     d, n = 4, 3
     th = random_state(d, L, n, seed=L + 100, u_target=0.6, dtype=np.float32).astype(np.float64)
@@ -193,15 +222,21 @@ def test_one_sweep_fp32_against_fp64_oracle(llr, L):
         bits = ctx.sweeps(1, sweep0=5)
         got = ctx.export_state(0).cpu().numpy().astype(np.float64)
         Eg, _ = ctx.get_energy(0)
+        amp = _amplification(d, L, th[k], lo, lo + width, E0, 5)
         tr = th[k].copy()
         Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, 1.0, lo, lo + width, E0, 5)
         dist = circ_dist(got[0], tr)
         n_flag_total += int(flagged.sum())
+        bar = 1e-6 * np.maximum(amp, 10.0)
+        assert np.mean(amp > 10.0) < 0.02
+        assert np.median(dist) < 1e-6
         if flagged.sum() == 0:
-            assert dist.max() < 1e-5, dist.max()
+            assert np.all(dist <= bar), (k, np.max(dist / bar))
             assert abs(Eg[0] - Er) < 1e-3 * max(1.0, np.sqrt(L ** 4))
         else:
-            assert np.median(dist) < 1e-6
+            # a flagged link may take another sampler attempt on one side: an
+            # O(1) difference whose effect on later neighbours is not linear
+            assert np.mean(dist > bar) < 0.01
         ctx.close()
     assert n_flag_total <= 3
 
