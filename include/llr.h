@@ -266,6 +266,25 @@ llr_status llr_fss_fit(const double *x, const double *y, const double *sigma, in
                        const double *powers, int n_par, double *params, double *errors,
                        double *chi2_red);
 
+/* --- observables from restricted double brackets (Sec. 2.3) ------------- */
+
+/* n_meas measurements with the current a_k: gap restricted sweeps (replica
+ * exchange as set in llr_params) from sweep index sweep0 (choose it beyond
+ * the sweeps of the Robbins-Monro run, whose counters it would reuse), then
+ * a full FP64 evaluation of E and of the adjoint plaquette sum
+ * B = sum_P cos 2 theta_P of every chain.  E, B (host, n_meas x total
+ * intervals, row-major): the values of the chain serving each interval, so
+ * column k holds the restricted samples of interval k. */
+llr_status llr_observables(llr_ctx *ctx, int n_meas, int gap, long long sweep0, double *E, double *B);
+/* <B>(beta) at nb couplings from m restricted samples (E, B) per interval
+ * (host, m x n, interval fastest) on intervals of width s centred at centres
+ * (spaced by s), eqs. (l9)-(l10):
+ * <B> = sum_k rho~(c_k) e^{beta c_k} <<B e^{(beta - a_k)(E - c_k)}>>_k
+ *     / sum_k rho~(c_k) e^{beta c_k} <<e^{(beta - a_k)(E - c_k)}>>_k. */
+llr_status llr_obs_reconstruct(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
+                               const double *E, const double *B, int m, const double *beta, int nb,
+                               double *B_mean);
+
 /* --- multicanonical sampling with W = 1/rho~ and reweighting (Sec. 2.6) --- */
 
 /* Builds each lattice's weight W(E) = 1/rho~(E) from its current a_k

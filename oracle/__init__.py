@@ -84,6 +84,8 @@ def _declare(L):
     L.or_neighbour.restype = l
     L.or_energy.argtypes = [i, i, _p(d)]
     L.or_energy.restype = d
+    L.or_adjoint.argtypes = [i, i, _p(d)]
+    L.or_adjoint.restype = d
     L.or_local_field.argtypes = [i, i, _p(d), i, l, _p(d), _p(d)]
     L.or_vonmises_batch.argtypes = [l, d, u64, u32, u32, u32, i, _p(d), _p(i), _p(d)]
     L.or_hot_start.argtypes = [i, i, i, u64, i, i, _p(d)]
@@ -349,6 +351,34 @@ def bootstrap(centres, a_runs, s, six_v, blo, bhi, n_boot, seed, h=1e-5, tol=1e-
             acc = acc + ar[j]
         bc[b], pk[b] = beta_c(centres, acc / ar.shape[0], s, six_v, blo, bhi, h, tol)
     return bc, pk
+
+
+# ---------------------------- observables from double brackets (Sec. 2.3)
+def adjoint(d, L, theta):
+    """sum_P cos(2 theta_P) of one chain."""
+    th = _f64(theta)
+    return lib().or_adjoint(d, L, _ptr(th, C.c_double))
+
+
+def obs_reconstruct(centres, a, s, E, B, beta):
+    """Eqs. (l9)-(l10) with the interval centres as reference energies:
+    <B> = sum_k rho~(c_k) e^{beta c_k} <<B e^{(beta-a_k)(E-c_k)}>>_k
+        / sum_k rho~(c_k) e^{beta c_k} <<e^{(beta-a_k)(E-c_k)}>>_k,
+    <<.>>_k the mean over the samples (rows) of column k."""
+    c, a = _f64(centres), _f64(a)
+    E, B = np.atleast_2d(_f64(E)), np.atleast_2d(_f64(B))
+    lr = ln_rho(a, s)
+    out = []
+    for b in np.atleast_1d(beta):
+        x = (b - a)[None, :] * (E - c[None, :])
+        xm = x.max(axis=0)
+        w = np.exp(x - xm[None, :])
+        D = w.mean(axis=0)
+        N = (w * B).mean(axis=0)
+        lw = lr + b * c + xm + np.log(D)
+        p = np.exp(lw - lw.max())
+        out.append(np.sum(p * N / D) / np.sum(p))
+    return np.array(out)
 
 
 # ------------------------------------ multicanonical sampling (Sec. 2.6)

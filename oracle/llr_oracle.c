@@ -201,6 +201,20 @@ double or_energy(int d, int L, const double *theta)
     return E;
 }
 
+/* Adjoint plaquette sum B = sum_P cos(2 theta_P): the non-action observable
+ * measured through the restricted double brackets of Sec. 2.3. */
+double or_adjoint(int d, int L, const double *theta)
+{
+    geo_t g;
+    if (geo_init(&g, d, L)) return NAN;
+    double B = 0.0;
+    for (long s = 0; s < g.V; ++s)
+        for (int mu = 0; mu < g.d; ++mu)
+            for (int nu = mu + 1; nu < g.d; ++nu) B += cos(2.0 * plaq_angle(&g, theta, s, mu, nu));
+    geo_free(&g);
+    return B;
+}
+
 /* Local field of link (mu, s): the 2(d-1) plaquettes that contain the link,
  * each oriented so that theta_mu(s) enters with a plus sign:
  *   forward  (plane mu,nu at s):      theta + [th_nu(s+mu) - th_mu(s+nu) - th_nu(s)]

@@ -206,7 +206,7 @@ static llr_status layout(llr_ctx* c) {
     llr_status st;
 #define AL(field, cnt) \
     if ((st = dalloc(c, &s.field, (cnt))) != LLR_OK) return st;
-    AL(E, n) AL(acc, n) AL(eacc, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
+    AL(E, n) AL(acc, n) AL(eacc, n) AL(oacc, n) AL(obs, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
     AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
     AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n) AL(mu_lnrho, n)
     AL(mu_b, kMaxLat)
@@ -561,6 +561,34 @@ static llr_status muca_sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, d
                                           c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    if (c->timing) harvest(c);
+    return LLR_OK;
+}
+
+template <typename T>
+static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sweep0, double* E_out, double* B_out) {
+    const uint32_t s0 = (uint32_t)sweep0;
+    HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
+    const int n = c->lt.n_chains;
+    std::vector<double> E(n), B(n);
+    std::vector<int> conf(n);
+    for (int m = 0; m < n_meas; ++m) {
+        for (int t = 0; t < gap; ++t)
+            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, false, c->prm.replica_exchange != 0, false);
+        {
+            TimeScope ts(c, 2);
+            launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream, true);
+        }
+        HIPCHK(hipMemcpyAsync(E.data(), c->ds.E, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(B.data(), c->ds.obs, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(conf.data(), c->ds.conf, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int k = 0; k < n; ++k) {
+            E_out[(size_t)m * n + k] = E[conf[k]];
+            B_out[(size_t)m * n + k] = B[conf[k]];
+        }
+    }
     HIPCHK(hipGetLastError());
     if (c->timing) harvest(c);
     return LLR_OK;
@@ -1081,6 +1109,43 @@ static bool uniform_centres(const double* c, int n, double s) {
     for (int k = 0; k + 1 < n; ++k)
         if (!(std::fabs(c[k + 1] - c[k] - s) <= 1e-9 * std::max(1.0, std::fabs(s)))) return false;
     return true;
+}
+
+llr_status llr_observables(llr_ctx* c, int n_meas, int gap, long long sweep0, double* E, double* B) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (n_meas < 1 || gap < 1 || !E || !B) return fail(LLR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(c->device));
+    return c->precision == LLR_FP32 ? observables_impl<float>(c, n_meas, gap, sweep0, E, B)
+                                    : observables_impl<double>(c, n_meas, gap, sweep0, E, B);
+}
+
+llr_status llr_obs_reconstruct(llr_ctx* c, const double* centres, const double* a, int n, double s, const double* E,
+                               const double* B, int m, const double* beta, int nb, double* B_mean) {
+    if (!c || !centres || !a || n < 1 || !(s > 0) || !E || !B || m < 1 || !beta || nb < 1 || !B_mean)
+        return fail(LLR_EINVAL, "bad argument");
+    if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
+    HIPCHK(hipSetDevice(c->device));
+    const size_t mn = (size_t)m * n;
+    llr_status st = ensure_scratch(c, 8 * (2 * mn + 3 * (size_t)n + 2 * (size_t)nb) + 64);
+    if (st != LLR_OK) return st;
+    double* dE = (double*)c->scratch;
+    double* dB = dE + mn;
+    double* dc = dB + mn;
+    double* da = dc + n;
+    double* dL = da + n;
+    double* db = dL + n;
+    double* dout = db + nb;
+    HIPCHK(hipMemcpyAsync(dE, E, 8 * mn, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dB, B, 8 * mn, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(db, beta, 8 * (size_t)nb, hipMemcpyHostToDevice, c->stream));
+    launch_obs_bracket(dE, dB, m, dc, da, n, s, db, nb, dout, dL, c->stream);
+    HIPCHK(hipMemcpyAsync(B_mean, dout, 8 * (size_t)nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    return LLR_OK;
 }
 
 llr_status llr_muca_begin(llr_ctx* c, const double* b) {

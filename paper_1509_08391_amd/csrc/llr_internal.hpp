@@ -47,6 +47,8 @@ struct DevState {
     double* E;             // current energy (incremental, FP64)
     unsigned long long* acc;   // arrivals << 51 | fixed-point Delta E of the running pass
     unsigned long long* eacc;  // the same for the energy recompute
+    unsigned long long* oacc;  // the same for the observable of the measurement recompute
+    double* obs;           // adjoint plaquette sum, sum_P cos 2 theta_P (FP64, at the last measurement)
     uint8_t* cur;          // 8 per chain: current plane of each colour
     int* itv;              // global index of the interval the chain serves
     double* b;             // approach coupling, 8 per chain (one per colour)
@@ -96,7 +98,8 @@ template <typename T> void launch_hb_pass(const LatTable& lt, T* th, DevState s,
                                           uint32_t k0, uint32_t k1, hipStream_t st);
 template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_alt,
                                           hipStream_t st);
-template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st);
+template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st,
+                                          bool with_obs = false);
 template <typename T> void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st);
 template <typename T> void launch_import(const LatTable& lt, int li, T* th, DevState s, const T* in, hipStream_t st);
 void launch_end_sweep(const LatTable& lt, DevState s, int measure, int approach, int with_or, hipStream_t st);
@@ -122,6 +125,8 @@ void launch_prob(const double* c, const double* a, int n, double s, double beta,
                  hipStream_t st);
 void launch_reweight(const double* E, long m, const double* c, const double* a, int n, double s, const double* beta,
                      int nb, double six_v, double* u, double* cv, double* scratch, hipStream_t st);
+void launch_obs_bracket(const double* E, const double* B, int m, const double* c, const double* a, int n, double s,
+                        const double* beta, int nb, double* out, double* scratch, hipStream_t st);
 
 // network (llr_mlp.hip)
 constexpr int kMlpH = 64;

@@ -328,4 +328,55 @@ void launch_reweight(const double* E, long m, const double* c, const double* a, 
                        cv);
 }
 
+// ---------------------------------------------------------------------------
+// Observables from restricted double brackets (Sec. 2.3, eqs. (l9)-(l10)):
+//   <B>_beta = sum_k rho~(c_k) e^{beta c_k} <<B e^{(beta - a_k)(E - c_k)}>>_k
+//            / sum_k rho~(c_k) e^{beta c_k} <<e^{(beta - a_k)(E - c_k)}>>_k,
+// with <<.>>_k the mean over the m samples (E, B) of interval k (row-major
+// m x n, interval fastest).  One block per beta; the interval terms are
+// combined in log space.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRB) void k_obs_bracket(const double* __restrict__ E, const double* __restrict__ B,
+                                                      int m, const double* __restrict__ c,
+                                                      const double* __restrict__ L, const double* __restrict__ a,
+                                                      int n, const double* __restrict__ beta,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[kRB / 64];
+    const double b = beta[blockIdx.x];
+    // per interval: ln D_k and N_k / D_k, D_k = <<e^{x}>>, x = (b - a_k)(E - c_k), shifted by the interval's max
+    double wmax = -INFINITY;
+    for (int k = threadIdx.x; k < n; k += kRB) {
+        double xm = -INFINITY;
+        for (int j = 0; j < m; ++j) xm = fmax(xm, (b - a[k]) * (E[(size_t)j * n + k] - c[k]));
+        double d = 0.0;
+        for (int j = 0; j < m; ++j) d += exp((b - a[k]) * (E[(size_t)j * n + k] - c[k]) - xm);
+        wmax = fmax(wmax, L[k] + b * c[k] + xm + log(d / m));
+    }
+    wmax = block_max(wmax, sh);
+    double num = 0.0, den = 0.0;
+    for (int k = threadIdx.x; k < n; k += kRB) {
+        double xm = -INFINITY;
+        for (int j = 0; j < m; ++j) xm = fmax(xm, (b - a[k]) * (E[(size_t)j * n + k] - c[k]));
+        double d = 0.0, nb = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double w = exp((b - a[k]) * (E[(size_t)j * n + k] - c[k]) - xm);
+            d += w;
+            nb += w * B[(size_t)j * n + k];
+        }
+        const double wk = exp(L[k] + b * c[k] + xm + log(d / m) - wmax);
+        den += wk;
+        num += wk * (nb / d);
+    }
+    den = block_sum(den, sh);
+    num = block_sum(num, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = num / den;
+}
+
+// scratch: n doubles (ln rho)
+void launch_obs_bracket(const double* E, const double* B, int m, const double* c, const double* a, int n, double s,
+                        const double* beta, int nb, double* out, double* scratch, hipStream_t st) {
+    hipLaunchKernelGGL(k_lnrho, dim3(1), dim3(64), 0, st, a, n, 1, s, scratch);
+    hipLaunchKernelGGL(k_obs_bracket, dim3((unsigned)nb), dim3(kRB), 0, st, E, B, m, c, scratch, a, n, beta, out);
+}
+
 }  // namespace llr

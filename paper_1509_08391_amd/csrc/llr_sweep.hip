@@ -501,7 +501,7 @@ __device__ __forceinline__ double cos_plaq(double x) {
 // half the odd ones, so the parity and with it every plane base is uniform
 // over a block.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool OBS>
 __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restrict__ th, DevState s) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int li = find_lat_site(lt, b);
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
     const int half = L.ebpc >> 1;
     const int p = tile >= half ? 1 : 0;
     const uint32_t h = (uint32_t)(tile - p * half) * kBlock + threadIdx.x;
-    long long fx = 0;
+    long long fx = 0, fa = 0;
     if (h < L.V2) {
         int x[4];
         decode_half(L, h, p, x);
@@ -534,7 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
                 const double t_nu_pmu = (double)ld_plane(plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2), hup[mu]);
                 const double t_mu_pnu = (double)ld_plane(plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2), hup[nu]);
                 const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
-                fx += __double2ll_rn(cos_plaq(ang) * L.fx);
+                const double cp = cos_plaq(ang);
+                fx += __double2ll_rn(cp * L.fx);
+                if (OBS) fa += __double2ll_rn(__fma_rn(2.0 * cp, cp, -1.0) * L.fx);   // cos 2 theta_P
             }
     }
     const long long tot = block_sum_i64(fx);
@@ -542,6 +544,15 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
     if (threadIdx.x == 0 && chain_arrive(s.eacc + g, tot, L.ebpc, &total)) {
         s.E[g] = (double)total * L.fxinv;
         atomicExch(s.eacc + g, 0ull);
+    }
+    if (OBS) {
+        __syncthreads();   // block_sum_i64's shared partials are reused
+        const long long ta = block_sum_i64(fa);
+        long long tb = 0;
+        if (threadIdx.x == 0 && chain_arrive(s.oacc + g, ta, L.ebpc, &tb)) {
+            s.obs[g] = (double)tb * L.fxinv;
+            atomicExch(s.oacc + g, 0ull);
+        }
     }
 }
 
@@ -820,8 +831,9 @@ void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_al
 }
 
 template <typename T>
-void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
+void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st, bool with_obs) {
+    if (with_obs) hipLaunchKernelGGL((k_energy<T, true>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
+    else hipLaunchKernelGGL((k_energy<T, false>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
 }
 
 template <typename T>
@@ -867,7 +879,7 @@ void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32
     template void launch_hot_start<T>(const LatTable&, T*, DevState, uint32_t, uint32_t, hipStream_t);          \
     template void launch_hb_pass<T>(const LatTable&, T*, DevState, int, int, int, uint32_t, uint32_t, hipStream_t); \
     template void launch_or_pass<T>(const LatTable&, T*, DevState, int, int, hipStream_t);                           \
-    template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t);                          \
+    template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t, bool);                    \
     template void launch_export<T>(const LatTable&, int, const T*, DevState, T*, hipStream_t);                 \
     template void launch_import<T>(const LatTable&, int, T*, DevState, const T*, hipStream_t);                 \
     template void launch_test_vonmises<T>(long, double, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double*, \

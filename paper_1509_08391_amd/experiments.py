@@ -30,6 +30,13 @@
            replicas each, FP32; the C_V peak against delta E and the fit
            C_V(dE) = C_V(0) + 6V b_dis dE^2.
 
+  obs8     a non-action observable through restricted double brackets
+           (Sec. 2.3): after an L=8 run with config1's dE over u in
+           [0.50, 0.71] (42 intervals, FP32), 400 restricted
+           measurements per interval of E and sum_P cos 2 theta_P;
+           <u>(beta) and <cos 2 theta_P>(beta) on [0.98, 1.04] by eqs.
+           (l9)-(l10), next to direct canonical runs at beta = 0.98, 1.04.
+
 Each writes a JSON record.  Usage:
     python -m paper_1509_08391_amd.experiments config1 [--out DIR]
 """
@@ -326,10 +333,68 @@ def dE_study_8(log, counts=(16, 32, 64, 128), replicas=8):
     return dict(rows=rows, cv0=p[0], cv0_over_6v=p[0] / V6, b_dis=b_dis, b_dis_err=b_err, chi2_red=chi2)
 
 
+def obs8(log, n_meas=400, gap=2):
+    L = 8
+    V6 = 6 * L ** 4
+    NP = V6
+    dE = 0.005 * V6
+    # config1's dE, with the range extended down to u = 0.50 so that the
+    # canonical distribution at beta = 0.98 (<u> ~ 0.55) lies inside it
+    E_low = 0.50 * V6 + dE * np.arange(42)
+    cen = E_low + 0.5 * dE
+    ctx = llr.Context(precision=llr.FP32, device=0)
+    ctx.set_params(n_th=200, n_a=500, n_rm=50, seed=SEED + 8, replica_exchange=False, recompute_every=10,
+                   approach_cap=20000)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    ctx.set_a(0, 1.0)
+    ctx.hot_start()
+    ctx.approach()
+    ctx.autotune()
+    ctx.run()
+    a, _, _ = ctx.get_a(0)
+    log("LLR run done; measuring")
+    E, B = ctx.observables(n_meas, gap, 1 << 24)
+    ctx.close()
+    beta = np.linspace(0.98, 1.04, 31)
+    ctx = llr.Context(precision=llr.FP64, device=0)
+    u = ctx.obs_reconstruct(cen, a, dE, E, E, beta) / V6
+    b2 = ctx.obs_reconstruct(cen, a, dE, E, B, beta) / NP
+    blocks = [(ctx.obs_reconstruct(cen, a, dE, E[i::4], E[i::4], beta) / V6,
+               ctx.obs_reconstruct(cen, a, dE, E[i::4], B[i::4], beta) / NP) for i in range(4)]
+    _, u_mid, _ = ctx.reconstruct(cen, a, dE, V6, beta)
+    ctx.close()
+    u_err = np.std([x[0] for x in blocks], axis=0, ddof=1) / 2
+    b_err = np.std([x[1] for x in blocks], axis=0, ddof=1) / 2
+    # direct canonical runs: 16 chains whose intervals cover every energy
+    canon = {}
+    for bt in (0.98, 1.04):
+        n = 16
+        ctx = llr.Context(precision=llr.FP32, device=0)
+        ctx.set_params(seed=SEED + 9, replica_exchange=False, recompute_every=10)
+        ctx.add_lattice(L, -V6 + 1e-3 * np.arange(n), 2 * V6 - 1.0)
+        ctx.bind_state()
+        ctx.set_a(0, bt)
+        ctx.hot_start()
+        ctx.observables(1, 500, 0)                        # thermalisation
+        Ec, Bc = ctx.observables(400, 5, 1000)
+        ctx.close()
+        per = np.array([Ec.mean(axis=0) / V6, Bc.mean(axis=0) / NP])
+        canon[bt] = dict(u=float(per[0].mean()), u_err=float(per[0].std(ddof=1) / np.sqrt(n)),
+                         cos2=float(per[1].mean()), cos2_err=float(per[1].std(ddof=1) / np.sqrt(n)))
+        i = int(np.argmin(np.abs(beta - bt)))
+        log(f"beta {bt}: <u> brackets {u[i]:.5f} +- {u_err[i]:.5f}, canonical {canon[bt]['u']:.5f} +- "
+            f"{canon[bt]['u_err']:.5f}; <cos 2 theta_P> brackets {b2[i]:.5f} +- {b_err[i]:.5f}, canonical "
+            f"{canon[bt]['cos2']:.5f} +- {canon[bt]['cos2_err']:.5f}")
+    return dict(a=a.tolist(), beta=beta.tolist(), u=u.tolist(), u_err=u_err.tolist(), u_midpoint=u_mid.tolist(),
+                cos2=b2.tolist(), cos2_err=b_err.tolist(), canonical={str(k): v for k, v in canon.items()},
+                n_meas=n_meas, gap=gap)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
-                                            "dE8"])
+                                            "dE8", "obs8"])
     ap.add_argument("--out", default="gpurun_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
                     "(config3 reads config1 and config2, config4 reads config3); default --out")
@@ -357,6 +422,8 @@ def main():
         rec = muca12(log, load("config2"))
     elif args.which == "dE8":
         rec = dE_study_8(log)
+    elif args.which == "obs8":
+        rec = obs8(log)
     else:
         rec = config4_replicas(log, load("config3"), n_rm=args.n_rm or 25)
     rec["wall_seconds"] = time.perf_counter() - t0

@@ -86,6 +86,9 @@ _SIGS = {
                       _p(C.c_double)],
     "llr_fss_fit": [_p(C.c_double), _p(C.c_double), _p(C.c_double), C.c_int, _p(C.c_double), C.c_int,
                     _p(C.c_double), _p(C.c_double), _p(C.c_double)],
+    "llr_observables": [C.c_void_p, C.c_int, C.c_int, C.c_longlong, _p(C.c_double), _p(C.c_double)],
+    "llr_obs_reconstruct": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, _p(C.c_double),
+                            _p(C.c_double), C.c_int, _p(C.c_double), C.c_int, _p(C.c_double)],
     "llr_muca_begin": [C.c_void_p, _p(C.c_double)],
     "llr_muca_sweeps": [C.c_void_p, C.c_int, C.c_longlong, _p(C.c_double)],
     "llr_muca_reweight": [C.c_void_p, _p(C.c_double), C.c_long, _p(C.c_double), _p(C.c_double), C.c_int,
@@ -369,6 +372,24 @@ class Context:
                                    six_v, blo, bhi, h, tol, n_boot, seed, _ptr(bc, C.c_double),
                                    _ptr(pk, C.c_double)))
         return bc, pk
+
+    # ---- observables from restricted double brackets
+    def observables(self, n_meas, gap, sweep0):
+        """(E, B) per measurement and interval: arrays (n_meas, total intervals)."""
+        nch = sum(x[1] for x in self.lattices)
+        E, B = np.empty((n_meas, nch)), np.empty((n_meas, nch))
+        _check(lib().llr_observables(self.h, n_meas, gap, sweep0, _ptr(E, C.c_double), _ptr(B, C.c_double)))
+        return E, B
+
+    def obs_reconstruct(self, centres, a, s, E, B, beta):
+        c, a = _arr(centres, np.float64), _arr(a, np.float64)
+        E, B = _arr(np.atleast_2d(E), np.float64), _arr(np.atleast_2d(B), np.float64)
+        b = _arr(np.atleast_1d(beta), np.float64)
+        out = np.empty(b.size)
+        _check(lib().llr_obs_reconstruct(self.h, _ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s,
+                                         _ptr(E, C.c_double), _ptr(B, C.c_double), E.shape[0], _ptr(b, C.c_double),
+                                         b.size, _ptr(out, C.c_double)))
+        return out
 
     # ---- multicanonical sampling and reweighting
     def muca_begin(self, b):
