@@ -28,7 +28,7 @@ _SRC = os.path.join(_HERE, "llr_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP, KIND_BOOT, KIND_MUCA = 0, 1, 2, 3, 4, 5, 6
-MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA = 0, 1, 2, 3
+MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
 N_PARAMS = 4417
 
 
@@ -89,6 +89,8 @@ def _declare(L):
     L.or_local_field.argtypes = [i, i, _p(d), i, l, _p(d), _p(d)]
     L.or_vonmises_batch.argtypes = [l, d, u64, u32, u32, u32, i, _p(d), _p(i), _p(d)]
     L.or_hot_start.argtypes = [i, i, i, u64, i, i, _p(d)]
+    L.or_link_draw_batch.argtypes = [l, d, d, d, u64, u32, u32, i, _p(d), _p(i)]
+    L.or_link_pass.argtypes = [i, i, _p(d), i, d, d, d, _p(d), u64, i, i, u32, u32, i, _p(d), _p(i)]
     L.or_class_pass.argtypes = [i, i, _p(d), i, i, i, d, d, d, _p(d), u64, i, i, u32, u32, i,
                                 _p(d), _p(d)]
     L.or_class_pass.restype = i
@@ -174,6 +176,31 @@ def vonmises(n, kappa, seed, c1=0, c2=0, c3=0, u24=False):
     lib().or_vonmises_batch(n, kappa, seed, c1, c2, c3, int(u24), _ptr(X, C.c_double),
                             _ptr(att, C.c_int), _ptr(mg, C.c_double))
     return X, att, mg
+
+
+def link_draw(n, kappa, u_lo, u_hi, seed, c2=0, c3=0, u24=False):
+    """n draws of the per-link restricted sampler, X ~ exp(kappa cos X) on
+    cos X in [u_lo, u_hi], counters (i, colour 0, kind 0, lattice 0, c2, c3).
+    Returns X and the stage that produced each draw (1, 2; 0 = none)."""
+    X = np.empty(n)
+    how = np.empty(n, dtype=np.int32)
+    lib().or_link_draw_batch(n, kappa, u_lo, u_hi, seed, c2, c3, int(u24), _ptr(X, C.c_double),
+                             _ptr(how, C.c_int))
+    return X, how
+
+
+def link_pass(d, L, theta, colour, a, lo, hi, E, seed, kind=KIND_SWEEP, lattice_id=0, sweep=0, interval=0,
+              f32=False):
+    """One heatbath pass of one colour under the per-link constraint (theta in
+    place).  Returns (E, margin per class link, stage per class link)."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    e = C.c_double(E)
+    V = L ** d
+    mg = np.empty(V // 2)
+    how = np.empty(V // 2, dtype=np.int32)
+    lib().or_link_pass(d, L, _ptr(theta, C.c_double), colour, a, lo, hi, C.byref(e), seed, kind, lattice_id,
+                       sweep, interval, int(f32), _ptr(mg, C.c_double), _ptr(how, C.c_int))
+    return e.value, mg, how
 
 
 def hot_start(d, L, n_chains, seed, lattice_id=0, f32=False):

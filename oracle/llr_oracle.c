@@ -272,6 +272,41 @@ static double wrap(double x)
 /* ------------------------------------------------------------------------ */
 #define VM_CAP 64
 
+typedef struct {
+    double k, r, gg, q; /* kappa; r, sqrt(r^2 - 1) and q of the wrapped-Cauchy envelope */
+} bf_t;
+
+static void bf_setup(double k, bf_t *b)
+{
+    double tau = 1.0 + sqrt(1.0 + 4.0 * k * k);
+    double rho = 2.0 * k / (tau + sqrt(2.0 * tau));
+    b->k = k;
+    b->r = (1.0 + rho * rho) / (2.0 * rho);
+    b->gg = (1.0 - rho * rho) / (2.0 * rho); /* r^2 - 1 = gg^2 */
+    b->q = (1.0 - rho) / (1.0 + rho);
+}
+
+/* One attempt from the words (wv, wu); on acceptance X is set and 1 returned.
+ * *mg is lowered to the smallest |test statistic| seen (decision margin). */
+static int bf_attempt(const bf_t *b, uint32_t wv, uint32_t wu, int u24, double *X, double *mg)
+{
+    double V1 = uni_signed(wv, u24);
+    double U2 = uni01(wu, u24);
+    double z = cos(OR_PI * V1);
+    double c = b->k * b->gg * b->gg / (b->r + z);
+    double t1 = c * (2.0 - c) - U2;
+    int acc = 0;
+    if (fabs(t1) < *mg) *mg = fabs(t1);
+    if (t1 > 0.0) acc = 1;
+    else {
+        double t2 = log(c / U2) + 1.0 - c;
+        if (fabs(t2) < *mg) *mg = fabs(t2);
+        if (t2 >= 0.0) acc = 1;
+    }
+    if (acc) *X = 2.0 * atan(b->q * tan(0.5 * OR_PI * V1));
+    return acc;
+}
+
 static int vm_draw(double kappa, const uint32_t key[2], uint32_t c0, uint32_t c1base,
                    uint32_t c2, uint32_t c3, int u24, double *X, double *margin)
 {
@@ -284,38 +319,126 @@ static int vm_draw(double kappa, const uint32_t key[2], uint32_t c0, uint32_t c1
         if (margin) *margin = mg;
         return 1;
     }
-    double k = kappa;
-    double tau = 1.0 + sqrt(1.0 + 4.0 * k * k);
-    double rho = 2.0 * k / (tau + sqrt(2.0 * tau));
-    double r = (1.0 + rho * rho) / (2.0 * rho);
-    double gg = (1.0 - rho * rho) / (2.0 * rho); /* r^2 - 1 = gg^2 */
-    double q = (1.0 - rho) / (1.0 + rho);
+    bf_t b;
+    bf_setup(kappa, &b);
     for (int j = 0; j < VM_CAP; ++j) {
         if ((j & 1) == 0) {
             uint32_t ctr[4] = {c0, c1base | (uint32_t)(j >> 1), c2, c3};
             or_philox(ctr, key, w);
         }
-        double V1 = uni_signed(w[2 * (j & 1)], u24);
-        double U2 = uni01(w[2 * (j & 1) + 1], u24);
-        double z = cos(OR_PI * V1);
-        double c = k * gg * gg / (r + z);
-        double t1 = c * (2.0 - c) - U2;
-        int acc = 0;
-        if (fabs(t1) < mg) mg = fabs(t1);
-        if (t1 > 0.0) acc = 1;
-        else {
-            double t2 = log(c / U2) + 1.0 - c;
-            if (fabs(t2) < mg) mg = fabs(t2);
-            if (t2 >= 0.0) acc = 1;
-        }
-        if (acc) {
-            *X = 2.0 * atan(q * tan(0.5 * OR_PI * V1));
+        if (bf_attempt(&b, w[2 * (j & 1)], w[2 * (j & 1) + 1], u24, X, &mg)) {
             if (margin) *margin = mg;
             return j + 1;
         }
     }
     if (margin) *margin = mg;
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heatbath draw under the per-link analytic constraint (Sec. 2.4: the       */
+/* restriction imposed when the new variable is generated).  Target:         */
+/*   p(X) ~ exp(k cos X) on the candidates that ok() accepts, k >= 0,        */
+/* where ok() keeps the running energy inside the interval; [u_lo, u_hi] is  */
+/* the same window written on cos X (used for the envelope only).            */
+/* Stage 1, rejection from the unrestricted conditional: the class           */
+/* heatbath's own attempts 0..63 (same counters); the first one that passes  */
+/* Best-Fisher and ok() is taken.  Stage 2, if none does: with x = |X| in    */
+/* [x_a, x_b] = [acos u_hi, acos u_lo], exp(k cos x) <= exp(k u_hi -         */
+/* lam (x - x_a)) for lam = k min(sin x_a, (u_hi - u_lo)/(x_b - x_a)): the   */
+/* secant slope (cos x_a - cos x)/(x - x_a) is the mean of sin over          */
+/* [x_a, x], which has no interior minimum because sin is unimodal on        */
+/* [0, pi], so its smallest value is at an end.  x is drawn from that        */
+/* truncated exponential and kept with probability                           */
+/* exp(k (cos x - u_hi) + lam (x - x_a)); X = +-x with a fair sign bit.      */
+/* Attempt i of stage 2 uses counter word 1 attempt field 64 + i, words 0    */
+/* (envelope), 1 (acceptance), top bit of 2 (sign); 64 attempts at most.     */
+/* Both stages sample the target exactly, so their mixture does.  Returns 1  */
+/* or 2 (stage that produced X) or 0 (nothing within the caps: the caller    */
+/* keeps the link).                                                          */
+/* ------------------------------------------------------------------------ */
+#define LINK_B_BASE 64
+#define LINK_B_CAP 64
+#define LINK_TINY 1e-12
+
+typedef int (*window_fn)(double X, void *ctx, double *mg);
+
+static int link_draw(double k, double u_lo, double u_hi, window_fn ok, void *okc, const uint32_t key[2],
+                     uint32_t c0, int colour, int kind, int lattice_id, uint32_t c2, uint32_t c3, int u24,
+                     double *X, double *margin)
+{
+    uint32_t w[4] = {0, 0, 0, 0};
+    double mg = INFINITY, x;
+    int got = 0;
+    if (k == 0.0) {
+        uint32_t ctr[4] = {c0, ctr1_word(0, colour, kind, lattice_id), c2, c3};
+        or_philox(ctr, key, w);
+        x = OR_PI * uni_signed(w[0], u24);
+        got = ok(x, okc, &mg);
+    } else {
+        bf_t b;
+        bf_setup(k, &b);
+        for (int j = 0; j < VM_CAP && !got; ++j) {
+            if ((j & 1) == 0) {
+                uint32_t ctr[4] = {c0, ctr1_word(j >> 1, colour, kind, lattice_id), c2, c3};
+                or_philox(ctr, key, w);
+            }
+            if (bf_attempt(&b, w[2 * (j & 1)], w[2 * (j & 1) + 1], u24, &x, &mg)) got = ok(x, okc, &mg);
+        }
+    }
+    if (got) {
+        *X = x;
+        *margin = mg;
+        return 1;
+    }
+    double xa = acos(u_hi), xb = acos(u_lo), W = xb - xa;
+    if (W > 0.0) {
+        double lam = k * fmin(sin(xa), (u_hi - u_lo) / W);
+        for (int i = 0; i < LINK_B_CAP; ++i) {
+            uint32_t ctr[4] = {c0, ctr1_word(LINK_B_BASE + i, colour, kind, lattice_id), c2, c3};
+            or_philox(ctr, key, w);
+            double V = uni01(w[0], u24), U = uni01(w[1], u24);
+            double T = lam * W < LINK_TINY ? V * W : -log1p(V * expm1(-lam * W)) / lam;
+            double xx = fmin(xa + T, xb);
+            double lhs = log(U), rhs = k * (cos(xx) - u_hi) + lam * T;
+            if (fabs(lhs - rhs) < mg) mg = fabs(lhs - rhs);
+            if (lhs <= rhs) {
+                x = (w[2] >> 31) ? -xx : xx;
+                if (ok(x, okc, &mg)) {
+                    *X = x;
+                    *margin = mg;
+                    return 2;
+                }
+            }
+        }
+    }
+    *margin = mg;
+    return 0;
+}
+
+/* window test on cos X itself (the sampler's own test entry) */
+static int cos_window(double X, void *ctx, double *mg)
+{
+    const double *u = (const double *)ctx;
+    double c = cos(X);
+    double m = fmin(fabs(c - u[0]), fabs(u[1] - c));
+    if (m < *mg) *mg = m;
+    return c >= u[0] && c <= u[1];
+}
+
+/* Test entry: n draws of the restricted sampler with counters (i, colour 0,
+ * kind 0, lattice 0, c2, c3); how[i] = stage (1, 2) or 0. */
+void or_link_draw_batch(long n, double kappa, double u_lo, double u_hi, uint64_t seed, uint32_t c2,
+                        uint32_t c3, int u24, double *X, int *how)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    double u[2] = {u_lo, u_hi};
+    for (long i = 0; i < n; ++i) {
+        double x = NAN, m;
+        int h = link_draw(kappa, u_lo, u_hi, cos_window, u, key, (uint32_t)i, 0, 0, 0, c2, c3, u24, &x, &m);
+        X[i] = h ? x : NAN;
+        how[i] = h;
+    }
 }
 
 /* Test entry: n draws with counters (ctr0 = i, ctr1 = c1base, ctr2, ctr3). */
@@ -371,6 +494,9 @@ void or_hot_start(int d, int L, int n_chains, uint64_t seed, int lattice_id, int
 /*           normalisation that depends only on the other classes, so the     */
 /*           class is accepted with probability min(1, W(E+dE)/W(E) e^{-a dE}) */
 /*           against the uniform of Philox counter (interval, kind 6, sweep). */
+/*   mode 4: restricted with the constraint imposed per link when the new    */
+/*           angle is drawn (Sec. 2.4): see link_pass; the class is always   */
+/*           accepted.                                                       */
 /* Links are visited in ascending half index h = s >> 1 and Delta E is       */
 /* summed sequentially in that order.                                        */
 /* ------------------------------------------------------------------------ */
@@ -419,10 +545,83 @@ double or_muca_lnw(double E)
     return -(g_muca.lr[k] - g_muca.a[k] * (E - g_muca.c[k]));
 }
 
+/* Window test of a class link under the per-link constraint: the candidate
+ * angle is stored (rounded to single precision for an FP32 state) and the
+ * energy change is taken from the stored angle, so the running energy stays
+ * inside [lo, hi] in the arithmetic that carries it. */
+typedef struct {
+    double C, S, phi, eps_old, E, lo, hi;
+    int flip, f32;
+    double t, dE; /* out: the last candidate tested */
+} link_win_t;
+
+static int link_window(double X, void *ctx, double *mg)
+{
+    link_win_t *w = (link_win_t *)ctx;
+    double t = wrap(X - w->phi + (w->flip ? OR_PI : 0.0));
+    if (w->f32) t = (double)(float)t;
+    double dE = eps_local(w->C, w->S, t) - w->eps_old;
+    double En = w->E + dE;
+    double m = fmin(fabs(En - w->lo), fabs(w->hi - En));
+    if (m < *mg) *mg = m;
+    w->t = t;
+    w->dE = dE;
+    return En >= w->lo && En <= w->hi;
+}
+
+/* Heatbath pass of one colour under the per-link constraint (mode 4): the
+ * class links are updated one after another in site order, each from its
+ * conditional restricted to the values that keep the running energy E in
+ * [lo, hi], and E is carried from link to link.  Links of one class share no
+ * plaquette, so the staples do not depend on the order; only E does.  The
+ * pass is always accepted.  how_out (optional) receives the stage per link. */
+static void link_pass(const geo_t *g, double *th, int colour, double a, double lo, double hi, double *E,
+                      const pass_ctx_t *pc, double *margin_out, int *how_out)
+{
+    long V = g->V;
+    int mu = colour >> 1, p = colour & 1;
+    long nl = 0;
+    for (long s = 0; s < V; ++s) {
+        if (g->par[s] != p) continue;
+        double t_old = th[mu * V + s];
+        double C, S;
+        local_field(g, th, mu, s, &C, &S);
+        double R = hypot(C, S);
+        double kappa = a * R;
+        link_win_t w = {C, S, atan2(S, C), eps_local(C, S, t_old), *E, lo, hi, kappa < 0.0, pc->f32, 0.0, 0.0};
+        /* window on the link's new local action sg R cos X, sg = sign(kappa) */
+        double A = lo - (*E - w.eps_old), B = hi - (*E - w.eps_old);
+        double u_lo = -1.0, u_hi = 1.0;
+        if (R > 0.0) {
+            u_lo = kappa < 0.0 ? -B / R : A / R;
+            u_hi = kappa < 0.0 ? -A / R : B / R;
+            u_lo = fmin(1.0, fmax(-1.0, u_lo));
+            u_hi = fmin(1.0, fmax(-1.0, u_hi));
+        }
+        double X, mg;
+        int how = link_draw(fabs(kappa), u_lo, u_hi, link_window, &w, pc->key, (uint32_t)(s >> 1), colour,
+                            pc->kind, pc->lattice_id, pc->sweep, pc->interval, pc->f32, &X, &mg);
+        if (R < 1e-4) mg = 0.0; /* ill-conditioned phase: flagged */
+        if (how) {
+            th[mu * V + s] = w.t;
+            *E += w.dE;
+        }
+        if (margin_out) margin_out[nl] = mg;
+        if (how_out) how_out[nl] = how;
+        ++nl;
+    }
+}
+
 static int class_pass(const geo_t *g, double *th, double *scratch, int hb, int colour,
                       int mode, double a, double lo, double hi, double *E,
                       const pass_ctx_t *pc, double *margin_out, double *dE_out)
 {
+    if (hb && mode == 4) {
+        double E0 = *E;
+        link_pass(g, th, colour, a, lo, hi, E, pc, margin_out, NULL);
+        if (dE_out) *dE_out = *E - E0;
+        return 1;
+    }
     long V = g->V;
     int d = g->d;
     int mu = colour >> 1, p = colour & 1;
@@ -497,6 +696,19 @@ int or_class_pass(int d, int L, double *theta, int hb, int colour, int mode, dou
     free(scr);
     geo_free(&g);
     return acc;
+}
+
+/* Exported single pass under the per-link constraint (mode 4), with the
+ * decision margin and the sampler stage of every class link. */
+void or_link_pass(int d, int L, double *theta, int colour, double a, double lo, double hi, double *E,
+                  uint64_t seed, int kind, int lattice_id, uint32_t sweep, uint32_t interval, int f32,
+                  double *margin, int *how)
+{
+    geo_t g;
+    if (geo_init(&g, d, L)) return;
+    pass_ctx_t pc = {{(uint32_t)seed, (uint32_t)(seed >> 32)}, kind, lattice_id, sweep, interval, f32};
+    link_pass(&g, theta, colour, a, lo, hi, E, &pc, margin, how);
+    geo_free(&g);
 }
 
 /* One restricted sweep (heatbath over all 2d colours, then overrelaxation over
