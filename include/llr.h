@@ -69,7 +69,8 @@ enum {
 enum { LLR_FP64 = 0, LLR_FP32 = 1 }; /* precision of link angles and local arithmetic;
                                         energies, interval tests, a_k, RM always FP64 */
 enum { LLR_MODE_RESTRICTED = 0, LLR_MODE_APPROACH = 1, LLR_MODE_FREE = 2,
-       LLR_MODE_MUCA = 3 /* multicanonical; only through llr_muca_sweeps */ };
+       LLR_MODE_MUCA = 3 /* multicanonical; only through llr_muca_sweeps */,
+       LLR_MODE_LINK = 4 /* restricted, constraint imposed per link; llr_sweeps / llr_class_pass */ };
 
 typedef struct {
     int n_th;             /* thermalisation sweeps per RM iteration (Algorithm 1 N_TH) */
@@ -167,6 +168,24 @@ llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double 
  * measurement, no recompute).  bits (host, n_sweeps x total chains, optional):
  * bit c = heatbath colour c accepted, bit 8 + c = overrelaxation colour c. */
 llr_status llr_sweeps(llr_ctx *ctx, int n_sweeps, long long sweep0, int mode, uint16_t *bits);
+
+/* Restriction imposed per link (mode LLR_MODE_LINK of llr_sweeps and
+ * llr_class_pass; Sec. 2.4, the constraint applied when each new variable is
+ * generated, against the class-wise rejection of mode LLR_MODE_RESTRICTED).
+ * A heatbath pass of colour c takes the class links one after another in
+ * half-index order; each is drawn from its conditional restricted to the
+ * values that keep the running energy inside the chain's [lo, hi], and the
+ * energy is carried from link to link, so every pass is accepted.  Per link:
+ * the first of the class heatbath's 64 attempts (the same counters) that
+ * passes the sampler test and keeps E inside; if none does, an exact sampler
+ * of the restricted density on its arc (attempts 64..127 of the counter's
+ * attempt field).  Overrelaxation passes are those of the restricted mode.
+ * The first use allocates, per class link of all chains, 8 bytes plus three
+ * angles (the Delta E, staples and old angle of the candidate pre-pass).
+ * llr_link_stats: per chain (host, total chains each, optional), the links
+ * whose free candidate left the interval and were re-drawn, and how many of
+ * those the arc sampler produced, summed since the state was bound. */
+llr_status llr_link_stats(llr_ctx *ctx, long long *redrawn, long long *arc);
 /* Tiles of the class-pass kernels: class links per thread (1, 2 or 4) of the
  * heatbath and of the overrelaxation pass.  llr_autotune
  * times the choices on the bound, initialised state without changing it and

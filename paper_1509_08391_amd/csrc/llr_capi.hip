@@ -163,7 +163,7 @@ static llr_status layout(llr_ctx* c) {
     memset(&lt, 0, sizeof(lt));
     lt.n = (int)c->lats.size();
     int chain0 = 0, eblock0 = 0;
-    long long base = 0;
+    long long base = 0, lbase = 0;
     for (int i = 0; i < lt.n; ++i) {
         const HostLat& h = c->lats[i];
         LatDev& d = lt.l[i];
@@ -187,6 +187,8 @@ static llr_status layout(llr_ctx* c) {
         d.lat_id = i;
         d.ds = h.dE;
         d.base = base;
+        d.lbase = lbase;
+        lbase += (long long)h.n * (V / 2);
         // largest fxb with 6V 2^fxb <= 2^49
         const int fxb = (int)std::floor(49.0 - std::log2(6.0 * (double)V));
         d.fxb = fxb;
@@ -209,12 +211,15 @@ static llr_status layout(llr_ctx* c) {
     AL(E, n) AL(acc, n) AL(eacc, n) AL(oacc, n) AL(obs, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
     AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
     AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n) AL(mu_lnrho, n)
-    AL(mu_b, kMaxLat)
+    AL(mu_b, kMaxLat) AL(link_fix, n) AL(link_arc, n)
     AL(lat_done, kMaxLat) AL(lat_outside, kMaxLat) AL(lat_approach, kMaxLat) AL(sweep_ctr, 1)
     AL(approach_ctr, 1) AL(rm_iter, 1) AL(re_cnt, 2) AL(bits_row, 1)
 #undef AL
     s.a_hist = nullptr;
     s.bits_log = nullptr;
+    s.link_d = nullptr;
+    s.link_cst = nullptr;
+    s.link_n = lbase;
     s.bits_rows_max = 0;
     std::vector<int> ident(n);
     for (int i = 0; i < n; ++i) ident[i] = i;
@@ -846,11 +851,29 @@ llr_status llr_set_tiles(llr_ctx* c, int hb_lpt, int or_lpt) {
     return LLR_OK;
 }
 
+// Per-class-link buffers of the per-link constraint, allocated on first use:
+// the candidates' fixed-point Delta E and the staples and old angle of every
+// class link of one colour, for all chains.
+static llr_status ensure_link_buffers(llr_ctx* c) {
+    if (c->ds.link_d) return LLR_OK;
+    llr_status st = dalloc(c, &c->ds.link_d, (size_t)c->ds.link_n);
+    if (st != LLR_OK) return st;
+    unsigned char* p = nullptr;
+    if ((st = dalloc(c, &p, 3 * (size_t)c->ds.link_n * elem_size(c))) != LLR_OK) return st;
+    c->ds.link_cst = p;
+    drop_graphs(c);   // captured sweeps hold the device-state table by value
+    return LLR_OK;
+}
+
+static bool sweep_mode_ok(int mode) { return mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_LINK; }
+
 llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint16_t* bits) {
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
-    if (n_sweeps < 0 || mode < 0 || mode > 2) return fail(LLR_EINVAL, "bad n_sweeps or mode");
+    if (n_sweeps < 0 || !(sweep_mode_ok(mode) || mode == LLR_MODE_APPROACH))
+        return fail(LLR_EINVAL, "bad n_sweeps or mode");
     HIPCHK(hipSetDevice(c->device));
+    if (mode == LLR_MODE_LINK && (st = ensure_link_buffers(c)) != LLR_OK) return st;
     return c->precision == LLR_FP32 ? sweeps_impl<float>(c, n_sweeps, sweep0, mode, bits)
                                     : sweeps_impl<double>(c, n_sweeps, sweep0, mode, bits);
 }
@@ -858,8 +881,10 @@ llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint
 llr_status llr_class_pass(llr_ctx* c, int heatbath, int colour, int mode, long long sweep_index) {
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
-    if (colour < 0 || colour > 7 || mode < 0 || mode > 2) return fail(LLR_EINVAL, "bad colour or mode");
+    if (colour < 0 || colour > 7 || !(sweep_mode_ok(mode) || mode == LLR_MODE_APPROACH))
+        return fail(LLR_EINVAL, "bad colour or mode");
     HIPCHK(hipSetDevice(c->device));
+    if (heatbath && mode == LLR_MODE_LINK && (st = ensure_link_buffers(c)) != LLR_OK) return st;
     const uint32_t s0 = (uint32_t)sweep_index;
     HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
     if (c->precision == LLR_FP32) {
@@ -989,6 +1014,16 @@ llr_status llr_stats(llr_ctx* c, long long* hb_prop, long long* hb_acc, long lon
     HIPCHK(hipMemcpy(re, c->ds.re_cnt, 16, hipMemcpyDeviceToHost));
     if (re_prop) *re_prop = (long long)re[0];
     if (re_acc) *re_acc = (long long)re[1];
+    return LLR_OK;
+}
+
+llr_status llr_link_stats(llr_ctx* c, long long* redrawn, long long* arc) {
+    if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = c->lt.n_chains;
+    if (redrawn) HIPCHK(hipMemcpy(redrawn, c->ds.link_fix, 8 * n, hipMemcpyDeviceToHost));
+    if (arc) HIPCHK(hipMemcpy(arc, c->ds.link_arc, 8 * n, hipMemcpyDeviceToHost));
     return LLR_OK;
 }
 

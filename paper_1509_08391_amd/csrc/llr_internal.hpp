@@ -26,6 +26,7 @@ struct LatDev {
     int eblock0;           // first block of this lattice in the site grid
     int lat_id;
     long long base;        // element offset of the lattice's first chain
+    long long lbase;       // offset of its first chain in the per-class-link buffers (chain-major, V/2 each)
     int fxb;               // fraction bits of the per-chain energy sums
     double fx, fxinv;      // 2^fxb and 2^-fxb
 };
@@ -70,6 +71,12 @@ struct DevState {
     long long* conv_sweeps;
     double* a_hist;        // (n_rm + 1) x n_chains
     double* mu_lnrho;      // ln rho~ at the centre, for the multicanonical weight W = 1/rho~
+    // per-link constraint: one entry per class link of every chain (lbase layout)
+    long long* link_d;     // Delta E of the free heatbath candidate, fixed point (kLinkNone: none)
+    void* link_cst;        // staple sums C, S and the old angle, three T arrays of link_n each
+    long long link_n;
+    unsigned long long* link_fix;   // per chain: links re-drawn by the walk
+    unsigned long long* link_arc;   // per chain: of those, drawn by the arc sampler
     // per lattice
     int* lat_done;         // approach finished
     int* lat_outside;      // chains outside their interval (approach check)

@@ -19,7 +19,14 @@
 
 namespace llr {
 
-enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeMuca = 3, kModeTune = kHbModeTune };
+// heatbath pass modes: the public LLR_MODE_* values 0-4, the tuner's timing
+// mode, and the candidate pre-pass of the per-link constraint (every link's
+// free heatbath candidate written with its Delta E and staples, nothing
+// accepted, no counters touched; the walk kernel then decides)
+enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeMuca = 3, kModeLink = 4,
+       kModeTune = kHbModeTune, kModeLinkPre = 6 };
+
+constexpr long long kLinkNone = (long long)0x8000000000000000ull;   // no free candidate within the cap
 
 __device__ __forceinline__ int find_lat_site(const LatTable& lt, int b) {
     int li = 0;
@@ -196,6 +203,37 @@ __device__ __forceinline__ bool vm_attempt(uint32_t wa, uint32_t wb, T q, T rm1,
 // link, at most 4 links per thread) and shifts once: fxb >= 26 for L <= 32.
 __device__ __forceinline__ long long to_fixed(double v, const LatDev& L) { return __double2ll_rn(v * L.fx); }
 
+// The per-link walk carries the energy kWalkBits finer than the class sums:
+// it adds links into a plain 64-bit sum, so the 13 bits the class sums keep
+// for their arrival count are free (|sum| <= 6V 2^(fxb + 12) <= 2^61).  An
+// FP32 link's Delta E is the class sums' 2^-25 value shifted, so FP32 energies
+// are those of the class-wise passes exactly.
+constexpr int kWalkBits = 12;
+
+template <typename T>
+__device__ __forceinline__ long long link_fixed(T dE, const LatDev& L) {
+    if constexpr (Math<T>::f32) return (long long)__float2int_rn(dE * 33554432.0f) << (L.fxb + kWalkBits - 25);
+    else return __double2ll_rn((double)dE * (L.fx * (double)(1 << kWalkBits)));
+}
+
+// New angle and local-action change of a heatbath link from the accepted
+// half-angle pair (c_, s_) = (cos, q sin)(pi V1 / 2): e^{iX} is
+// (c_ + i s_)^2 / nrm, negated for a negative coupling, and
+// theta' = arg[e^{iX} (C - i S)].
+template <typename T>
+__device__ __forceinline__ void hb_new_angle(T c_, T s_, T C, T S, T R, T kap, T eps_old, T& t_new, T& dE) {
+    using M = Math<T>;
+    T er = fms2(c_, c_, s_, s_), ei = T(2) * c_ * s_;
+    const T nrm = fma2(c_, c_, s_, s_);
+    if (kap < T(0)) { er = -er; ei = -ei; }
+    T pr = C, pi = -S;
+    if (R == T(0)) { pr = T(1); pi = T(0); }
+    const T zr = fms2(er, pr, ei, pi), zi = fma2(er, pi, ei, pr);
+    t_new = M::atan2_(zi, zr);
+    if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
+    dE = M::div_(R * er, nrm) - eps_old;
+}
+
 // ln W(E) = -ln rho~(E) of the multicanonical weight (Sec. 2.6): in interval
 // k, -ln rho~(c_k) + a_k (E - c_k); below the first and above the last
 // interval the first and last pieces continue, i.e. W = e^{a_0 E + c_1} and
@@ -348,21 +386,20 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         }
         T t_new = t_old[r];
         T dE = T(0);
-        if (ok) {
-            T er = fms2(c_, c_, s_, s_), ei = T(2) * c_ * s_;
-            const T nrm = fma2(c_, c_, s_, s_);
-            if (kap[r] < T(0)) { er = -er; ei = -ei; }
-            T pr = C[r], pi = -S[r];
-            if (R[r] == T(0)) { pr = T(1); pi = T(0); }
-            const T zr = fms2(er, pr, ei, pi), zi = fma2(er, pi, ei, pr);
-            t_new = M::atan2_(zi, zr);
-            if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
-            dE = M::div_(R[r] * er, nrm) - eps_old[r];
-        }
+        if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
         st_plane(palt, h, t_new);
+        if (mode == kModeLinkPre) {
+            const size_t j = (size_t)L.lbase + (size_t)cl * L.V2 + h;
+            T* lc = static_cast<T*>(s.link_cst);
+            s.link_d[j] = ok ? link_fixed(dE, L) : kLinkNone;
+            lc[j] = C[r];
+            lc[s.link_n + j] = S[r];
+            lc[2 * s.link_n + j] = t_old[r];
+        }
         if constexpr (M::f32) fx32 += __float2int_rn(dE * 33554432.0f);
         else fx += to_fixed((double)dE, L);
     }
+    if (mode == kModeLinkPre) return;
     if constexpr (M::f32) fx = (long long)fx32 << (L.fxb - 25);
     const long long tot = block_sum_i64(fx);
     long long total = 0;
@@ -406,6 +443,241 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             s.hb_acc[g] += 1ull;
         }
         atomicExch(s.acc + g, 0ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Heatbath class pass under the per-link constraint (Sec. 2.4: the energy
+// restriction imposed when each new angle is generated).  The links of the
+// class are taken one after another in half-index order, each from its
+// conditional restricted to the values that keep the running energy in
+// [lo, hi], and the energy is carried from link to link.  Links of one class
+// share no plaquette, so only that energy couples them.  Per link: the first
+// of the class heatbath's own attempts (same counters) that passes the
+// sampler test AND keeps E inside; if none of the 64 does, the exact arc
+// sampler (attempts 64..127 of the counter's attempt field): on
+// x = |X| in [acos u_hi, acos u_lo], where the window on cos X is [u_lo, u_hi],
+// exp(k cos x) lies under exp(k u_hi - lam (x - x_a)) with
+// lam = k min(sin x_a, (u_hi - u_lo)/(x_b - x_a)), since the secant slope of
+// cos from x_a is the mean of sin over [x_a, x], smallest at an end of the
+// arc; x comes from that truncated exponential, is kept with probability
+// exp(k (cos x - u_hi) + lam (x - x_a)), and its sign is a fair bit.
+//
+// The candidate pre-pass (k_hb in kModeLinkPre) has written, per class link,
+// the free heatbath candidate into the alternate plane and its Delta E in
+// the walk's fixed point.  That candidate is the first attempt passing the
+// sampler test; it is the constrained draw whenever it keeps E inside.  The
+// walk (one block per chain) scans the candidates in order, 1024 at a time:
+// block prefix sums of Delta E give the running E before every link, the first
+// link whose candidate leaves [lo, hi] is re-drawn by one wavefront (attempt j
+// on lane j, then arc attempt i on lane i; the lowest successful lane wins,
+// which is the first success in attempt order), and the scan resumes after
+// it.  E is carried exactly in fixed point (12 bits finer than the class
+// sums), so the result does not depend on the scan's blocking.
+// ---------------------------------------------------------------------------
+constexpr int kWalkTile = 2048;          // candidates' Delta E staged in LDS per tile
+constexpr int kWalkWin = 4 * kBlock;     // links examined per scan step
+
+__device__ __forceinline__ long long fx_bound(double v) {
+    return v > 4.0e18 ? 4000000000000000000ll : (v < -4.0e18 ? -4000000000000000000ll : (long long)v);
+}
+
+// Re-draw class link h (all threads call; wavefront 0 works).  Returns its
+// fixed-point Delta E; writes its new angle into the alternate plane.
+template <typename T>
+__device__ __forceinline__ long long link_redraw(const LatDev& L, const DevState& s, T* palt, size_t j, uint32_t h,
+                                                 int colour, int kind, uint32_t sweep, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1, double a, double Erun, double lo, double hi,
+                                                 long long Ssum, long long lo_fx, long long hi_fx, unsigned& arcs,
+                                                 long long* s_fixd) {
+    using M = Math<T>;
+    if ((threadIdx.x >> 6) == 0) {
+        const int lane = threadIdx.x & 63;
+        const T* lc = static_cast<const T*>(s.link_cst);
+        const T C = lc[j], S = lc[s.link_n + j], t_old = lc[2 * s.link_n + j];
+        T so, co;
+        M::sincos_rad(t_old, &so, &co);
+        const T eps_old = fms2(C, co, S, so);
+        const T R = M::sqrt_(fma2(C, C, S, S));
+        const T kap = (T)a * R;
+        const T ak = kap < T(0) ? -kap : kap;
+        T q, rm1, kg2;
+        vm_constants(ak, q, rm1, kg2);
+        // the sampler's attempts, attempt j = lane on this lane
+        const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
+        const uint4 w = philox10(make_uint4(h, c1base | (uint32_t)(lane >> 1), sweep, c3), k0, k1);
+        T ch = T(1), sh = T(0);
+        bool acc;
+        if (ak == T(0)) {
+            acc = lane == 0;
+            M::sincos_halfpi(M::sunif(w.x), &sh, &ch);
+        } else {
+            acc = (lane & 1) ? vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh) : vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh);
+        }
+        T t_c = t_old, dE_c = T(0);
+        long long d_c = 0;
+        bool ok = false;
+        if (acc) {
+            hb_new_angle(ch, sh, C, S, R, kap, eps_old, t_c, dE_c);
+            d_c = link_fixed(dE_c, L);
+            ok = Ssum + d_c >= lo_fx && Ssum + d_c <= hi_fx;
+        }
+        const unsigned long long m1 = __ballot(ok);
+        if (m1) {
+            if (lane == __ffsll((long long)m1) - 1) {
+                st_plane(palt, h, t_c);
+                *s_fixd = d_c;
+            }
+        } else {
+            // exact arc sampler, in FP64 for either state precision
+            const double Rd = (double)R, kd = (double)kap, akd = (double)ak, ed = (double)eps_old;
+            const double Aw = lo - (Erun - ed), Bw = hi - (Erun - ed);
+            double ulo = -1.0, uhi = 1.0;
+            if (Rd > 0.0) {
+                ulo = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Bw / Rd : Aw / Rd));
+                uhi = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Aw / Rd : Bw / Rd));
+            }
+            const double xa = acos(uhi), xb = acos(ulo), W = xb - xa;
+            bool ok2 = false;
+            double t2 = 0.0;
+            long long d2 = 0;
+            if (W > 0.0) {
+                const double lam = akd * fmin(sin(xa), (uhi - ulo) / W);
+                const uint4 v = philox10(
+                    make_uint4(h, ctr1_word((uint32_t)(64 + lane), (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id),
+                               sweep, c3), k0, k1);
+                const double V = (double)M::unif(v.x), U = (double)M::unif(v.y);
+                const double Tt = lam * W < 1e-12 ? V * W : -log1p(V * expm1(-lam * W)) / lam;
+                const double xx = fmin(xa + Tt, xb);
+                if (log(U) <= akd * (cos(xx) - uhi) + lam * Tt) {
+                    const double X = (v.z >> 31) ? -xx : xx;
+                    const double sg = kd < 0.0 ? -1.0 : 1.0;
+                    double sx, cx;
+                    sincos(X, &sx, &cx);
+                    const double Cd = (double)C, Sd = (double)S;
+                    t2 = atan2(sg * (sx * Cd - cx * Sd), sg * (cx * Cd + sx * Sd));
+                    if (t2 >= 3.14159265358979323846) t2 -= 6.28318530717958647692;
+                    d2 = __double2ll_rn((sg * Rd * cx - ed) * (L.fx * (double)(1 << kWalkBits)));
+                    ok2 = Ssum + d2 >= lo_fx && Ssum + d2 <= hi_fx;
+                }
+            }
+            const unsigned long long m2 = __ballot(ok2);
+            if (m2) {
+                if (lane == __ffsll((long long)m2) - 1) {
+                    st_plane(palt, h, (T)t2);
+                    *s_fixd = d2;
+                }
+                ++arcs;
+            } else if (lane == 0) {
+                st_plane(palt, h, t_old);
+                *s_fixd = 0;
+            }
+        }
+    }
+    __syncthreads();
+    return *s_fixd;
+}
+
+template <typename T, int MU>
+__global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict__ th, DevState s, int parity, int kind,
+                                                      uint32_t k0, uint32_t k1) {
+    __shared__ long long s_d[kWalkTile];
+    __shared__ long long s_wave[kBlock / 64];
+    __shared__ int s_wbad[kBlock / 64];
+    __shared__ long long s_run, s_fixd;
+    const int g = (int)blockIdx.x;
+    int li = 0;
+#pragma unroll 1
+    while (li + 1 < lt.n && g >= lt.l[li + 1].chain0) ++li;
+    const LatDev& L = lt.l[li];
+    const int cl = g - L.chain0;
+    const int colour = 2 * MU + parity;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
+    T* chain = chain_base(L, th, cl);
+    const int own = (int)((curw >> (8 * colour)) & 1ull);
+    T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
+    const int gi = s.itv[g];
+    const double a = s.a[gi];
+    const double E0 = s.E[g];
+    const double lo = s.lo[gi], hi = s.hi[gi];
+    const double fxw = L.fx * (double)(1 << kWalkBits), fxwinv = L.fxinv / (double)(1 << kWalkBits);
+    const long long lo_fx = fx_bound(ceil((lo - E0) * fxw)), hi_fx = fx_bound(floor((hi - E0) * fxw));
+    const uint32_t sweep = *s.sweep_ctr;
+    const uint32_t c3 = (uint32_t)(gi - L.chain0);
+    const size_t jb = (size_t)L.lbase + (size_t)cl * L.V2;
+    long long Ssum = 0;
+    unsigned fixes = 0, arcs = 0;
+    for (uint32_t t0 = 0; t0 < L.V2; t0 += kWalkTile) {
+        const int nt = (int)min((uint32_t)kWalkTile, L.V2 - t0);
+        __syncthreads();
+        for (int i = tid; i < nt; i += kBlock) s_d[i] = s.link_d[jb + t0 + i];
+        __syncthreads();
+        int j0 = 0;
+        while (j0 < nt) {
+            const int e0 = j0 + 4 * tid;
+            long long dv[4], loc = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dv[q] = e0 + q < nt ? s_d[e0 + q] : 0;
+                if (dv[q] != kLinkNone) loc += dv[q];
+            }
+            long long incl = loc;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const long long v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            if (lane == 63) s_wave[wid] = incl;
+            __syncthreads();
+            long long wpre = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                if (w < wid) wpre += s_wave[w];
+                tot += s_wave[w];
+            }
+            long long run = Ssum + wpre + incl - loc;
+            int bad = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q;
+                if (bad != 0x7fffffff || e >= nt) continue;
+                const long long d = dv[q];
+                if (d == kLinkNone || run + d < lo_fx || run + d > hi_fx) bad = e;
+                else run += d;
+            }
+            int wb = bad;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) wb = min(wb, __shfl_xor(wb, off, 64));
+            if (lane == 0) s_wbad[wid] = wb;
+            __syncthreads();
+            int b = 0x7fffffff;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) b = min(b, s_wbad[w]);
+            if (b == 0x7fffffff) {
+                Ssum += tot;
+                j0 = min(j0 + kWalkWin, nt);
+            } else {
+                if (bad == b) s_run = run;
+                __syncthreads();
+                Ssum = s_run;
+                const uint32_t h = t0 + (uint32_t)b;
+                Ssum += link_redraw<T>(L, s, palt, jb + h, h, colour, kind, sweep, c3, k0, k1, a,
+                                       E0 + (double)Ssum * fxwinv, lo, hi, Ssum, lo_fx, hi_fx, arcs, &s_fixd);
+                ++fixes;
+                j0 = b + 1;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        s.E[g] = E0 + (double)Ssum * fxwinv;
+        s.cur[8 * g + colour] ^= (uint8_t)1;
+        s.bits[g] |= (uint16_t)(1u << colour);
+        s.hb_prop[g] += 1ull;
+        s.hb_acc[g] += 1ull;
+        s.link_fix[g] += fixes;
+        s.link_arc[g] += arcs;
     }
 }
 
@@ -801,10 +1073,20 @@ static void hb_dispatch(const LatTable& lt, T* th, DevState s, int colour, int m
 template <typename T>
 void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
                     hipStream_t st) {
+    const int m = mode == kModeLink ? kModeLinkPre : mode;
     switch (lt.hb_lpt) {
-        case 1: hb_dispatch<T, 1>(lt, th, s, colour, mode, kind, k0, k1, st); break;
-        case 2: hb_dispatch<T, 2>(lt, th, s, colour, mode, kind, k0, k1, st); break;
-        default: hb_dispatch<T, 4>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        case 1: hb_dispatch<T, 1>(lt, th, s, colour, m, kind, k0, k1, st); break;
+        case 2: hb_dispatch<T, 2>(lt, th, s, colour, m, kind, k0, k1, st); break;
+        default: hb_dispatch<T, 4>(lt, th, s, colour, m, kind, k0, k1, st); break;
+    }
+    if (mode != kModeLink) return;
+    const int p = colour & 1;
+    dim3 gr(lt.n_chains), bl(kBlock);
+    switch (colour >> 1) {
+        case 0: hipLaunchKernelGGL((k_link_walk<T, 0>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
+        case 1: hipLaunchKernelGGL((k_link_walk<T, 1>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
+        case 2: hipLaunchKernelGGL((k_link_walk<T, 2>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
+        default: hipLaunchKernelGGL((k_link_walk<T, 3>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
     }
 }
 

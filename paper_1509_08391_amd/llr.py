@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libllr.so")
 
 OK, WARN_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
-MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA = 0, 1, 2, 3
+MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
 N_PARAMS = 4417
 
 _lib = None
@@ -67,6 +67,7 @@ _SIGS = {
     "llr_enable_bits_log": [C.c_void_p, C.c_longlong],
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
     "llr_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong)],
+    "llr_link_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong)],
     "llr_set_timing": [C.c_void_p, C.c_int],
     "llr_get_timing": [C.c_void_p, _p(C.c_double), _p(C.c_longlong), _p(C.c_double), _p(C.c_longlong),
                        _p(C.c_double), _p(C.c_longlong)],
@@ -309,6 +310,15 @@ class Context:
         rp, ra = C.c_longlong(), C.c_longlong()
         _check(lib().llr_stats(self.h, _ptr(hp, C.c_longlong), _ptr(ha, C.c_longlong), C.byref(rp), C.byref(ra)))
         return hp, ha, rp.value, ra.value
+
+    def link_stats(self):
+        """Per chain: links re-drawn under the per-link constraint and, of
+        those, draws of the arc sampler (cumulative)."""
+        nch = sum(x[1] for x in self.lattices)
+        fx = np.zeros(nch, dtype=np.int64)
+        ar = np.zeros(nch, dtype=np.int64)
+        _check(lib().llr_link_stats(self.h, _ptr(fx, C.c_longlong), _ptr(ar, C.c_longlong)))
+        return fx, ar
 
     def set_timing(self, on):
         _check(lib().llr_set_timing(self.h, int(on)))
