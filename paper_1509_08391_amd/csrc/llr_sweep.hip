@@ -467,124 +467,156 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
 // the free heatbath candidate into the alternate plane and its Delta E in
 // the walk's fixed point.  That candidate is the first attempt passing the
 // sampler test; it is the constrained draw whenever it keeps E inside.  The
-// walk (one block per chain) scans the candidates in order, 1024 at a time:
-// block prefix sums of Delta E give the running E before every link, the first
-// link whose candidate leaves [lo, hi] is re-drawn by one wavefront (attempt j
+// walk (one wavefront per chain, the block's other wavefronts staging the
+// next tile of candidates in LDS) scans the candidates in order, 1024 at a
+// time: wavefront prefix sums of Delta E give the running E before every
+// link, the first link whose candidate leaves [lo, hi] is re-drawn (attempt j
 // on lane j, then arc attempt i on lane i; the lowest successful lane wins,
 // which is the first success in attempt order), and the scan resumes after
 // it.  E is carried exactly in fixed point (12 bits finer than the class
 // sums), so the result does not depend on the scan's blocking.
 // ---------------------------------------------------------------------------
-constexpr int kWalkTile = 2048;          // candidates' Delta E staged in LDS per tile
-constexpr int kWalkWin = 4 * kBlock;     // links examined per scan step
+constexpr int kWalkTile = 2048;          // class links staged in LDS per tile
+constexpr int kWalkPer = 16;             // links per lane per scan step (1024 per step)
 
 __device__ __forceinline__ long long fx_bound(double v) {
     return v > 4.0e18 ? 4000000000000000000ll : (v < -4.0e18 ? -4000000000000000000ll : (long long)v);
 }
 
-// Re-draw class link h (all threads call; wavefront 0 works).  Returns its
-// fixed-point Delta E; writes its new angle into the alternate plane.
+// Re-draw class link h with the running sum Ssum before it (whole wavefront;
+// staples and old angle from LDS).  Returns the link's fixed-point Delta E
+// on every lane and writes its new angle into the alternate plane.
 template <typename T>
-__device__ __forceinline__ long long link_redraw(const LatDev& L, const DevState& s, T* palt, size_t j, uint32_t h,
-                                                 int colour, int kind, uint32_t sweep, uint32_t c3, uint32_t k0,
-                                                 uint32_t k1, double a, double Erun, double lo, double hi,
-                                                 long long Ssum, long long lo_fx, long long hi_fx, unsigned& arcs,
-                                                 long long* s_fixd) {
+__device__ __forceinline__ long long link_redraw(const LatDev& L, T* palt, uint32_t h, T C, T S, T t_old, int colour,
+                                                 int kind, uint32_t sweep, uint32_t c3, uint32_t k0, uint32_t k1,
+                                                 double a, double fxw, double Erun, double lo, double hi,
+                                                 long long Ssum, long long lo_fx, long long hi_fx, unsigned& arcs) {
     using M = Math<T>;
-    if ((threadIdx.x >> 6) == 0) {
-        const int lane = threadIdx.x & 63;
-        const T* lc = static_cast<const T*>(s.link_cst);
-        const T C = lc[j], S = lc[s.link_n + j], t_old = lc[2 * s.link_n + j];
-        T so, co;
-        M::sincos_rad(t_old, &so, &co);
-        const T eps_old = fms2(C, co, S, so);
-        const T R = M::sqrt_(fma2(C, C, S, S));
-        const T kap = (T)a * R;
-        const T ak = kap < T(0) ? -kap : kap;
-        T q, rm1, kg2;
-        vm_constants(ak, q, rm1, kg2);
-        // the sampler's attempts, attempt j = lane on this lane
-        const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
-        const uint4 w = philox10(make_uint4(h, c1base | (uint32_t)(lane >> 1), sweep, c3), k0, k1);
-        T ch = T(1), sh = T(0);
-        bool acc;
-        if (ak == T(0)) {
-            acc = lane == 0;
-            M::sincos_halfpi(M::sunif(w.x), &sh, &ch);
-        } else {
-            acc = (lane & 1) ? vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh) : vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh);
+    const int lane = threadIdx.x & 63;
+    T so, co;
+    M::sincos_rad(t_old, &so, &co);
+    const T eps_old = fms2(C, co, S, so);
+    const T R = M::sqrt_(fma2(C, C, S, S));
+    const T kap = (T)a * R;
+    const T ak = kap < T(0) ? -kap : kap;
+    T q, rm1, kg2;
+    vm_constants(ak, q, rm1, kg2);
+    // the sampler's attempts, attempt j = lane on this lane
+    const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
+    const uint4 w = philox10(make_uint4(h, c1base | (uint32_t)(lane >> 1), sweep, c3), k0, k1);
+    T ch = T(1), sh = T(0);
+    bool acc;
+    if (ak == T(0)) {
+        acc = lane == 0;
+        M::sincos_halfpi(M::sunif(w.x), &sh, &ch);
+    } else {
+        acc = (lane & 1) ? vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh) : vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh);
+    }
+    T t_c = t_old, dE_c = T(0);
+    long long d_c = 0;
+    bool ok = false;
+    if (acc) {
+        hb_new_angle(ch, sh, C, S, R, kap, eps_old, t_c, dE_c);
+        d_c = link_fixed(dE_c, L);
+        ok = Ssum + d_c >= lo_fx && Ssum + d_c <= hi_fx;
+    }
+    const unsigned long long m1 = __ballot(ok);
+    if (m1) {
+        const int f = __ffsll((long long)m1) - 1;
+        if (lane == f) st_plane(palt, h, t_c);
+        return __shfl(d_c, f, 64);
+    }
+    // exact arc sampler, in FP64 for either state precision
+    const double Rd = (double)R, kd = (double)kap, akd = (double)ak, ed = (double)eps_old;
+    const double Aw = lo - (Erun - ed), Bw = hi - (Erun - ed);
+    double ulo = -1.0, uhi = 1.0;
+    if (Rd > 0.0) {
+        ulo = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Bw / Rd : Aw / Rd));
+        uhi = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Aw / Rd : Bw / Rd));
+    }
+    const double xa = acos(uhi), xb = acos(ulo), W = xb - xa;
+    bool ok2 = false;
+    double t2 = 0.0;
+    long long d2 = 0;
+    if (W > 0.0) {
+        const double lam = akd * fmin(sin(xa), (uhi - ulo) / W);
+        const uint4 v = philox10(
+            make_uint4(h, ctr1_word((uint32_t)(64 + lane), (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id),
+                       sweep, c3), k0, k1);
+        const double V = (double)M::unif(v.x), U = (double)M::unif(v.y);
+        const double Tt = lam * W < 1e-12 ? V * W : -log1p(V * expm1(-lam * W)) / lam;
+        const double xx = fmin(xa + Tt, xb);
+        if (log(U) <= akd * (cos(xx) - uhi) + lam * Tt) {
+            const double X = (v.z >> 31) ? -xx : xx;
+            const double sg = kd < 0.0 ? -1.0 : 1.0;
+            double sx, cx;
+            sincos(X, &sx, &cx);
+            const double Cd = (double)C, Sd = (double)S;
+            t2 = atan2(sg * (sx * Cd - cx * Sd), sg * (cx * Cd + sx * Sd));
+            if (t2 >= 3.14159265358979323846) t2 -= 6.28318530717958647692;
+            d2 = __double2ll_rn((sg * Rd * cx - ed) * fxw);
+            ok2 = Ssum + d2 >= lo_fx && Ssum + d2 <= hi_fx;
         }
-        T t_c = t_old, dE_c = T(0);
-        long long d_c = 0;
-        bool ok = false;
-        if (acc) {
-            hb_new_angle(ch, sh, C, S, R, kap, eps_old, t_c, dE_c);
-            d_c = link_fixed(dE_c, L);
-            ok = Ssum + d_c >= lo_fx && Ssum + d_c <= hi_fx;
+    }
+    const unsigned long long m2 = __ballot(ok2);
+    if (m2) {
+        const int f = __ffsll((long long)m2) - 1;
+        if (lane == f) st_plane(palt, h, (T)t2);
+        ++arcs;
+        return __shfl(d2, f, 64);
+    }
+    if (lane == 0) st_plane(palt, h, t_old);
+    return 0;
+}
+
+// Stage tile k of a chain's candidates (Delta E, staples, old angle) into LDS
+// buffer `buf`, by threads [first, first + count) of the block; every thread
+// issues its loads for several entries before its LDS stores, so a tile costs
+// a few memory round trips, not one per entry.
+template <typename T>
+__device__ __forceinline__ void walk_stage(const DevState& s, size_t jb, uint32_t V2, int k, long long* sd, T* sc,
+                                           T* ss, T* st, int first, int count) {
+    constexpr int U = 8;
+    const uint32_t t0 = (uint32_t)k * kWalkTile;
+    const int nt = (int)min((uint32_t)kWalkTile, V2 - t0);
+    const T* lc = static_cast<const T*>(s.link_cst);
+    for (int base = (int)threadIdx.x - first; base < nt; base += U * count) {
+        long long dd[U];
+        T cc[U], sn[U], tt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * count;
+            if (i < nt) {
+                const size_t j = jb + t0 + i;
+                dd[u] = s.link_d[j];
+                cc[u] = lc[j];
+                sn[u] = lc[s.link_n + j];
+                tt[u] = lc[2 * s.link_n + j];
+            }
         }
-        const unsigned long long m1 = __ballot(ok);
-        if (m1) {
-            if (lane == __ffsll((long long)m1) - 1) {
-                st_plane(palt, h, t_c);
-                *s_fixd = d_c;
-            }
-        } else {
-            // exact arc sampler, in FP64 for either state precision
-            const double Rd = (double)R, kd = (double)kap, akd = (double)ak, ed = (double)eps_old;
-            const double Aw = lo - (Erun - ed), Bw = hi - (Erun - ed);
-            double ulo = -1.0, uhi = 1.0;
-            if (Rd > 0.0) {
-                ulo = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Bw / Rd : Aw / Rd));
-                uhi = fmin(1.0, fmax(-1.0, kd < 0.0 ? -Aw / Rd : Bw / Rd));
-            }
-            const double xa = acos(uhi), xb = acos(ulo), W = xb - xa;
-            bool ok2 = false;
-            double t2 = 0.0;
-            long long d2 = 0;
-            if (W > 0.0) {
-                const double lam = akd * fmin(sin(xa), (uhi - ulo) / W);
-                const uint4 v = philox10(
-                    make_uint4(h, ctr1_word((uint32_t)(64 + lane), (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id),
-                               sweep, c3), k0, k1);
-                const double V = (double)M::unif(v.x), U = (double)M::unif(v.y);
-                const double Tt = lam * W < 1e-12 ? V * W : -log1p(V * expm1(-lam * W)) / lam;
-                const double xx = fmin(xa + Tt, xb);
-                if (log(U) <= akd * (cos(xx) - uhi) + lam * Tt) {
-                    const double X = (v.z >> 31) ? -xx : xx;
-                    const double sg = kd < 0.0 ? -1.0 : 1.0;
-                    double sx, cx;
-                    sincos(X, &sx, &cx);
-                    const double Cd = (double)C, Sd = (double)S;
-                    t2 = atan2(sg * (sx * Cd - cx * Sd), sg * (cx * Cd + sx * Sd));
-                    if (t2 >= 3.14159265358979323846) t2 -= 6.28318530717958647692;
-                    d2 = __double2ll_rn((sg * Rd * cx - ed) * (L.fx * (double)(1 << kWalkBits)));
-                    ok2 = Ssum + d2 >= lo_fx && Ssum + d2 <= hi_fx;
-                }
-            }
-            const unsigned long long m2 = __ballot(ok2);
-            if (m2) {
-                if (lane == __ffsll((long long)m2) - 1) {
-                    st_plane(palt, h, (T)t2);
-                    *s_fixd = d2;
-                }
-                ++arcs;
-            } else if (lane == 0) {
-                st_plane(palt, h, t_old);
-                *s_fixd = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * count;
+            if (i < nt) {
+                sd[i] = dd[u];
+                sc[i] = cc[u];
+                ss[i] = sn[u];
+                st[i] = tt[u];
             }
         }
     }
-    __syncthreads();
-    return *s_fixd;
 }
 
+// One block per chain.  The walk is a chain of dependent steps and runs on
+// wavefront 0 alone (no barriers inside a tile; the first link whose
+// candidate leaves the window is found with one ballot, since lane l owns
+// links 16 l .. 16 l + 15 of the step), while wavefronts 1-3 stage the next
+// tile into the other LDS buffer.
 template <typename T, int MU>
 __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict__ th, DevState s, int parity, int kind,
                                                       uint32_t k0, uint32_t k1) {
-    __shared__ long long s_d[kWalkTile];
-    __shared__ long long s_wave[kBlock / 64];
-    __shared__ int s_wbad[kBlock / 64];
-    __shared__ long long s_run, s_fixd;
+    __shared__ long long s_d[2][kWalkTile];
+    __shared__ T s_c[2][kWalkTile], s_s[2][kWalkTile], s_t[2][kWalkTile];
     const int g = (int)blockIdx.x;
     int li = 0;
 #pragma unroll 1
@@ -593,91 +625,89 @@ __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict
     const int cl = g - L.chain0;
     const int colour = 2 * MU + parity;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
-    T* chain = chain_base(L, th, cl);
-    const int own = (int)((curw >> (8 * colour)) & 1ull);
-    T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
-    const int gi = s.itv[g];
-    const double a = s.a[gi];
-    const double E0 = s.E[g];
-    const double lo = s.lo[gi], hi = s.hi[gi];
-    const double fxw = L.fx * (double)(1 << kWalkBits), fxwinv = L.fxinv / (double)(1 << kWalkBits);
-    const long long lo_fx = fx_bound(ceil((lo - E0) * fxw)), hi_fx = fx_bound(floor((hi - E0) * fxw));
-    const uint32_t sweep = *s.sweep_ctr;
-    const uint32_t c3 = (uint32_t)(gi - L.chain0);
     const size_t jb = (size_t)L.lbase + (size_t)cl * L.V2;
-    long long Ssum = 0;
-    unsigned fixes = 0, arcs = 0;
-    for (uint32_t t0 = 0; t0 < L.V2; t0 += kWalkTile) {
-        const int nt = (int)min((uint32_t)kWalkTile, L.V2 - t0);
-        __syncthreads();
-        for (int i = tid; i < nt; i += kBlock) s_d[i] = s.link_d[jb + t0 + i];
-        __syncthreads();
-        int j0 = 0;
-        while (j0 < nt) {
-            const int e0 = j0 + 4 * tid;
-            long long dv[4], loc = 0;
+    const int ntiles = (int)((L.V2 + kWalkTile - 1) / kWalkTile);
+    walk_stage<T>(s, jb, L.V2, 0, s_d[0], s_c[0], s_s[0], s_t[0], 0, kBlock);
+    __syncthreads();
+    if (wid == 0) {
+        const uint64_t curw = *reinterpret_cast<const uint64_t*>(s.cur + 8 * g);
+        T* chain = chain_base(L, th, cl);
+        const int own = (int)((curw >> (8 * colour)) & 1ull);
+        T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
+        const int gi = s.itv[g];
+        const double a = s.a[gi];
+        const double E0 = s.E[g];
+        const double lo = s.lo[gi], hi = s.hi[gi];
+        const double fxw = L.fx * (double)(1 << kWalkBits), fxwinv = L.fxinv / (double)(1 << kWalkBits);
+        const long long lo_fx = fx_bound(ceil((lo - E0) * fxw)), hi_fx = fx_bound(floor((hi - E0) * fxw));
+        const uint32_t sweep = *s.sweep_ctr;
+        const uint32_t c3 = (uint32_t)(gi - L.chain0);
+        long long Ssum = 0;
+        unsigned fixes = 0, arcs = 0;
+        for (int k = 0; k < ntiles; ++k) {
+            const int buf = k & 1;
+            const uint32_t t0 = (uint32_t)k * kWalkTile;
+            const int nt = (int)min((uint32_t)kWalkTile, L.V2 - t0);
+            const long long* sd = s_d[buf];
+            int j0 = 0;
+            while (j0 < nt) {
+                const int e0 = j0 + kWalkPer * lane;
+                long long dv[kWalkPer], loc = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                dv[q] = e0 + q < nt ? s_d[e0 + q] : 0;
-                if (dv[q] != kLinkNone) loc += dv[q];
-            }
-            long long incl = loc;
+                for (int q = 0; q < kWalkPer; ++q) {
+                    dv[q] = e0 + q < nt ? sd[e0 + q] : 0;
+                    if (dv[q] != kLinkNone) loc += dv[q];
+                }
+                long long incl = loc;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const long long v = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += v;
-            }
-            if (lane == 63) s_wave[wid] = incl;
-            __syncthreads();
-            long long wpre = 0, tot = 0;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const long long v = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += v;
+                }
+                long long run = Ssum + incl - loc;
+                int bad = -1;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) {
-                if (w < wid) wpre += s_wave[w];
-                tot += s_wave[w];
-            }
-            long long run = Ssum + wpre + incl - loc;
-            int bad = 0x7fffffff;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = e0 + q;
-                if (bad != 0x7fffffff || e >= nt) continue;
-                const long long d = dv[q];
-                if (d == kLinkNone || run + d < lo_fx || run + d > hi_fx) bad = e;
-                else run += d;
-            }
-            int wb = bad;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) wb = min(wb, __shfl_xor(wb, off, 64));
-            if (lane == 0) s_wbad[wid] = wb;
-            __syncthreads();
-            int b = 0x7fffffff;
-#pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) b = min(b, s_wbad[w]);
-            if (b == 0x7fffffff) {
-                Ssum += tot;
-                j0 = min(j0 + kWalkWin, nt);
-            } else {
-                if (bad == b) s_run = run;
-                __syncthreads();
-                Ssum = s_run;
-                const uint32_t h = t0 + (uint32_t)b;
-                Ssum += link_redraw<T>(L, s, palt, jb + h, h, colour, kind, sweep, c3, k0, k1, a,
-                                       E0 + (double)Ssum * fxwinv, lo, hi, Ssum, lo_fx, hi_fx, arcs, &s_fixd);
+                for (int q = 0; q < kWalkPer; ++q) {
+                    const int e = e0 + q;
+                    if (bad >= 0 || e >= nt) continue;
+                    const long long d = dv[q];
+                    if (d == kLinkNone || run + d < lo_fx || run + d > hi_fx) bad = e;
+                    else run += d;
+                }
+                const unsigned long long mb = __ballot(bad >= 0);
+                if (mb == 0) {
+                    Ssum += __shfl(incl, 63, 64);
+                    j0 = min(j0 + kWalkPer * 64, nt);
+                    continue;
+                }
+                const int f = __ffsll((long long)mb) - 1;
+                const int b = __shfl(bad, f, 64);
+                Ssum = __shfl(run, f, 64);
+                Ssum += link_redraw<T>(L, palt, t0 + (uint32_t)b, s_c[buf][b], s_s[buf][b], s_t[buf][b], colour, kind,
+                                       sweep, c3, k0, k1, a, fxw, E0 + (double)Ssum * fxwinv, lo, hi, Ssum, lo_fx,
+                                       hi_fx, arcs);
                 ++fixes;
                 j0 = b + 1;
             }
-            __syncthreads();
+            __syncthreads();   // pairs with the stagers' barrier of this tile
         }
-    }
-    if (tid == 0) {
-        s.E[g] = E0 + (double)Ssum * fxwinv;
-        s.cur[8 * g + colour] ^= (uint8_t)1;
-        s.bits[g] |= (uint16_t)(1u << colour);
-        s.hb_prop[g] += 1ull;
-        s.hb_acc[g] += 1ull;
-        s.link_fix[g] += fixes;
-        s.link_arc[g] += arcs;
+        if (lane == 0) {
+            s.E[g] = E0 + (double)Ssum * fxwinv;
+            s.cur[8 * g + colour] ^= (uint8_t)1;
+            s.bits[g] |= (uint16_t)(1u << colour);
+            s.hb_prop[g] += 1ull;
+            s.hb_acc[g] += 1ull;
+            s.link_fix[g] += fixes;
+            s.link_arc[g] += arcs;
+        }
+    } else {
+        for (int k = 0; k < ntiles; ++k) {
+            if (k + 1 < ntiles) {
+                const int nb = (k + 1) & 1;
+                walk_stage<T>(s, jb, L.V2, k + 1, s_d[nb], s_c[nb], s_s[nb], s_t[nb], 64, kBlock - 64);
+            }
+            __syncthreads();   // tile k walked, tile k + 1 staged
+        }
     }
 }
 
