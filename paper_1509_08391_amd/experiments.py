@@ -53,6 +53,15 @@
            under --inputs, else a_k = 1.011 ~ beta_c(20) throughout).
   linkprof 60 sweeps per mode of the L = 20 set only, for a kernel trace.
 
+  fss      beta_c(L) and the C_V peak for the finite-size analysis of Sec. 3.4
+           on this implementation's own runs: L = 8, 10, 12, 14 (part 0) and
+           16, 18 (part 1), 96 intervals over u in [0.56, 0.70], four replicas
+           each (lattices of one context), replica exchange, FP32,
+           N_TH = 200, N_A = 800, N_RM = 80, warm start from the network of
+           config3 evaluated at (u, 1/L); per L a bootstrap over the replicas.
+           "fss --combine" adds L = 20 from the config4b parts and fits
+           beta_c(L) = beta_c + sum_k B_k L^-4k and C_V/(6V) = G^2/4 + ...
+
 Each writes a JSON record.  Usage:
     python -m paper_1509_08391_amd.experiments config1 [--out DIR]
 """
@@ -533,11 +542,79 @@ def link_profile(log, a20, n=60):
     return dict(redrawn_per_pass=float(f.sum() / (n * 8 * len(E_low))), arc_per_pass=float(r.sum() / (n * 8 * len(E_low))))
 
 
+FSS_PARTS = {0: (8, 10, 12, 14), 1: (16, 18)}
+
+
+def fss_part(log, c3, part, n_rep=4, n_int=96, n_rm=80, n_boot=1000):
+    w = np.array(c3["weights"], dtype=np.float32)
+    out = {}
+    for L in FSS_PARTS[part]:
+        V6 = 6 * L ** 4
+        dE = 0.14 / n_int * V6
+        E_low = 0.56 * V6 + dE * np.arange(n_int)
+        cen = E_low + 0.5 * dE
+        ctx = llr.Context(precision=llr.FP32, device=0)
+        a0 = ctx.mlp_predict(w, cen / V6, np.full(n_int, 1.0 / L))
+        ctx.close()
+        res, meta = _run([(L, E_low, dE)] * n_rep, llr.FP32, 200, 800, n_rm, True, seed=SEED + 100 * L,
+                         a0=[a0] * n_rep, log=log)
+        A = np.array([r["a"] for r in res])
+        ctx = llr.Context(precision=llr.FP64, device=0)
+        per = np.array([ctx.beta_c(cen, A[i], dE, V6, 0.995, 1.02, h=1e-5, tol=1e-9) for i in range(n_rep)])
+        bc_b, pk_b = ctx.bootstrap(cen, A, dE, V6, 0.995, 1.02, n_boot=n_boot, seed=SEED + L)
+        bc, pk = ctx.beta_c(cen, A.mean(axis=0), dE, V6, 0.995, 1.02, h=1e-5, tol=1e-9)
+        ctx.close()
+        out[str(L)] = dict(L=L, dE=dE, a_runs=A.tolist(), a0=a0.tolist(), per_run=per.tolist(), beta_c=bc,
+                           beta_c_err=float(bc_b.std(ddof=1)), cv_peak_over_6v=pk / V6,
+                           cv_peak_over_6v_err=float(pk_b.std(ddof=1) / V6), meta=meta,
+                           conv_iter=[r["conv_iter"] for r in res])
+        log(f"L={L}: beta_c {bc:.6f} +- {bc_b.std(ddof=1):.6f}, C_V/(6V) {pk / V6:.4e} +- "
+            f"{pk_b.std(ddof=1) / V6:.1e} ({meta['seconds_rm']:.0f} s)")
+    return out
+
+
+def fss_combine(log, parts, c4b_parts, n_boot=2000):
+    rows = {}
+    for p in parts:
+        for k, v in p.items():
+            if k.isdigit():
+                rows[int(k)] = (v["beta_c"], v["beta_c_err"], v["cv_peak_over_6v"], v["cv_peak_over_6v_err"])
+    if c4b_parts:
+        L, E_low, dE = config4_intervals()
+        V6 = 6 * L ** 4
+        cen = E_low + 0.5 * dE
+        A = np.array([r["a"] for p in c4b_parts for r in p["runs"]])
+        ctx = llr.Context(precision=llr.FP64, device=0)
+        bc_b, pk_b = ctx.bootstrap(cen, A, dE, V6, 1.008, 1.012, n_boot=n_boot, seed=SEED)
+        bc, pk = ctx.beta_c(cen, A.mean(axis=0), dE, V6, 1.008, 1.012, h=1e-5, tol=1e-9)
+        ctx.close()
+        rows[20] = (bc, float(bc_b.std(ddof=1)), pk / V6, float(pk_b.std(ddof=1) / V6))
+        log(f"L=20 ({A.shape[0]} runs): beta_c {bc:.7f} +- {bc_b.std(ddof=1):.7f}, C_V/(6V) {pk / V6:.4e} +- "
+            f"{pk_b.std(ddof=1) / V6:.1e}")
+    Ls = np.array(sorted(rows))
+    tab = np.array([rows[L] for L in Ls])
+    fits = []
+    for Lmin in (8, 10, 12, 14):
+        m = Ls >= Lmin
+        for kmax in (1, 2):
+            if m.sum() <= kmax + 1:
+                continue
+            pw = np.array([0.0] + [-4.0 * k for k in range(1, kmax + 1)])
+            pb, eb, cb = llr.fss_fit(Ls[m], tab[m, 0], tab[m, 1], pw)
+            pc, ec, cc = llr.fss_fit(Ls[m], tab[m, 2], tab[m, 3], pw)
+            G = 2.0 * np.sqrt(max(pc[0], 0.0))
+            fits.append(dict(L_min=int(Lmin), k_max=kmax, beta_c=pb[0], beta_c_err=eb[0], chi2_beta=cb,
+                             G=G, G_err=ec[0] / max(G, 1e-300) * 2.0, chi2_cv=cc))
+            log(f"L >= {Lmin}, k_max {kmax}: beta_c(inf) {pb[0]:.7f} +- {eb[0]:.7f} (chi2/dof {cb:.2f}); "
+                f"G {G:.5f} +- {fits[-1]['G_err']:.5f} (chi2/dof {cc:.2f})")
+    return dict(L=Ls.tolist(), table=tab.tolist(), fits=fits)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
                                             "dE8", "obs8",
-                                            "config4b", "linkcmp", "linkprof"])
+                                            "config4b", "linkcmp", "linkprof", "fss"])
     ap.add_argument("--out", default="experiment_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
                     "(config3 reads config1 and config2, config4 reads config3); default --out")
@@ -569,6 +646,19 @@ def main():
         rec = dE_study_8(log)
     elif args.which == "obs8":
         rec = obs8(log)
+    elif args.which == "fss" and args.combine:
+        import glob
+        src = args.inputs or args.out
+
+        def recs(pattern):
+            out = []
+            for f in sorted(glob.glob(os.path.join(src, pattern))):
+                with open(f) as fh:
+                    out.append(json.load(fh))
+            return out
+        rec = fss_combine(log, recs("fss_part*.json"), recs("config4b_part*.json"))
+    elif args.which == "fss":
+        rec = fss_part(log, load("config3"), args.part)
     elif args.which in ("linkcmp", "linkprof"):
         # converged L=20 a_k when a config4b record is given, else beta_c(20) throughout
         src = os.path.join(args.inputs or args.out, "config4b_part0.json")
@@ -587,8 +677,8 @@ def main():
         rec = config4_replicas(log, load("config3"), n_rm=args.n_rm or 25)
     rec["wall_seconds"] = time.perf_counter() - t0
     name = args.which
-    if args.which == "config4b":
-        name = "config4b_combined" if args.combine else f"config4b_part{args.part}"
+    if args.which in ("config4b", "fss"):
+        name = f"{args.which}_combined" if args.combine else f"{args.which}_part{args.part}"
     with open(os.path.join(args.out, f"{name}.json"), "w") as f:
         json.dump(rec, f)
     log(f"done in {rec['wall_seconds']:.1f} s")
