@@ -610,8 +610,10 @@ __device__ __forceinline__ void walk_stage(const DevState& s, size_t jb, uint32_
 // One block per chain.  The walk is a chain of dependent steps and runs on
 // wavefront 0 alone (no barriers inside a tile; the first link whose
 // candidate leaves the window is found with one ballot, since lane l owns
-// links 16 l .. 16 l + 15 of the step), while wavefronts 1-3 stage the next
-// tile into the other LDS buffer.
+// links 16 l .. 16 l + 15 of the step; after a re-draw only the entries
+// after it are checked again, with their running sums shifted by the change
+// of that link's Delta E), while wavefronts 1-3 stage the next tile into the
+// other LDS buffer.
 template <typename T, int MU>
 __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict__ th, DevState s, int parity, int kind,
                                                       uint32_t k0, uint32_t k1) {
@@ -651,12 +653,18 @@ __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict
             const long long* sd = s_d[buf];
             int j0 = 0;
             while (j0 < nt) {
+                // one step: candidates j0 .. j0 + 1023, lane l owning 16 l .. 16 l + 15
                 const int e0 = j0 + kWalkPer * lane;
                 long long dv[kWalkPer], loc = 0;
+                unsigned none = 0;   // entries without a free candidate
 #pragma unroll
                 for (int q = 0; q < kWalkPer; ++q) {
                     dv[q] = e0 + q < nt ? sd[e0 + q] : 0;
-                    if (dv[q] != kLinkNone) loc += dv[q];
+                    if (dv[q] == kLinkNone) {
+                        dv[q] = 0;
+                        none |= 1u << q;
+                    }
+                    loc += dv[q];
                 }
                 long long incl = loc;
 #pragma unroll
@@ -664,30 +672,44 @@ __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict
                     const long long v = __shfl_up(incl, off, 64);
                     if (lane >= off) incl += v;
                 }
-                long long run = Ssum + incl - loc;
-                int bad = -1;
+                // running sum before this lane's first entry; a re-draw shifts
+                // it by the same delta for every later entry of the step
+                long long base = Ssum + incl - loc;
+                const long long tot = __shfl(incl, 63, 64);
+                long long shift = 0;
+                int pos = j0;
+                for (;;) {
+                    long long run = base, before = 0;
+                    int bad = -1;
 #pragma unroll
-                for (int q = 0; q < kWalkPer; ++q) {
-                    const int e = e0 + q;
-                    if (bad >= 0 || e >= nt) continue;
-                    const long long d = dv[q];
-                    if (d == kLinkNone || run + d < lo_fx || run + d > hi_fx) bad = e;
-                    else run += d;
-                }
-                const unsigned long long mb = __ballot(bad >= 0);
-                if (mb == 0) {
-                    Ssum += __shfl(incl, 63, 64);
-                    j0 = min(j0 + kWalkPer * 64, nt);
-                    continue;
-                }
-                const int f = __ffsll((long long)mb) - 1;
-                const int b = __shfl(bad, f, 64);
-                Ssum = __shfl(run, f, 64);
-                Ssum += link_redraw<T>(L, palt, t0 + (uint32_t)b, s_c[buf][b], s_s[buf][b], s_t[buf][b], colour, kind,
-                                       sweep, c3, k0, k1, a, fxw, E0 + (double)Ssum * fxwinv, lo, hi, Ssum, lo_fx,
+                    for (int q = 0; q < kWalkPer; ++q) {
+                        const int e = e0 + q;
+                        if (bad >= 0 || e >= nt) continue;
+                        const long long r1 = run + dv[q];
+                        if (e >= pos && (((none >> q) & 1u) || r1 < lo_fx || r1 > hi_fx)) {
+                            bad = e;
+                            before = run;
+                        }
+                        run = r1;
+                    }
+                    const unsigned long long mb = __ballot(bad >= 0);
+                    if (mb == 0) break;
+                    const int f = __ffsll((long long)mb) - 1;
+                    const int b = __shfl(bad, f, 64);
+                    const long long S_b = __shfl(before, f, 64);
+                    const long long d_old = sd[b] == kLinkNone ? 0 : sd[b];
+                    const long long d_new =
+                        link_redraw<T>(L, palt, t0 + (uint32_t)b, s_c[buf][b], s_s[buf][b], s_t[buf][b], colour, kind,
+                                       sweep, c3, k0, k1, a, fxw, E0 + (double)S_b * fxwinv, lo, hi, S_b, lo_fx,
                                        hi_fx, arcs);
-                ++fixes;
-                j0 = b + 1;
+                    ++fixes;
+                    const long long delta = d_new - d_old;
+                    shift += delta;
+                    if (lane >= f) base += delta;
+                    pos = b + 1;
+                }
+                Ssum += tot + shift;
+                j0 = min(j0 + kWalkPer * 64, nt);
             }
             __syncthreads();   // pairs with the stagers' barrier of this tile
         }
