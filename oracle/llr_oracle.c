@@ -18,6 +18,7 @@
  *   - the observable Delta E and its root: eqs. (kk10)-(kk15)
  *   - the under-relaxed Newton-Raphson / Robbins-Monro update: eq. (kk21) and
  *     Algorithm 1 (update with the minus sign, beta-convention a ~ beta)
+ *   - the restriction imposed per link when each angle is drawn: Sec. 2.4
  *   - replica exchange between overlapping intervals: Sec. 2.5
  *   - reconstruction: trapezium recursion eq. (kk3a), midpoint sums
  *     eqs. (l19)-(l20), specific heat of Sec. 3.4
