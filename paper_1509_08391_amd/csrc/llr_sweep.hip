@@ -262,7 +262,7 @@ __device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, d
 // paid per block, not per wavefront.  Each link still takes its first
 // accepted attempt in order.
 // ---------------------------------------------------------------------------
-template <typename T, int MU, int LPT>
+template <typename T, int MU, int LPT, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
                                                int kind, uint32_t k0, uint32_t k1, int reverse) {
     using M = Math<T>;
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         T dE = T(0);
         if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
         st_plane(palt, h, t_new);
-        if (mode == kModeLinkPre) {
+        if constexpr (PRE) {
             const size_t j = (size_t)L.lbase + (size_t)cl * L.V2 + h;
             T* lc = static_cast<T*>(s.link_cst);
             s.link_d[j] = ok ? link_fixed(dE, L) : kLinkNone;
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         if constexpr (M::f32) fx32 += __float2int_rn(dE * 33554432.0f);
         else fx += to_fixed((double)dE, L);
     }
-    if (mode == kModeLinkPre) return;
+    if constexpr (PRE) return;
     if constexpr (M::f32) fx = (long long)fx32 << (L.fxb - 25);
     const long long tot = block_sum_i64(fx);
     long long total = 0;
@@ -1108,30 +1108,40 @@ void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32
     hipLaunchKernelGGL(k_hot_start<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, k0, k1);
 }
 
-template <typename T, int LPT>
+// PRE: the candidate pre-pass of the per-link constraint, a separate
+// instantiation so that the class-wise passes carry none of its code
+template <typename T, int LPT, bool PRE>
 static void hb_dispatch(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0,
                         uint32_t k1, hipStream_t st) {
     const int p = colour & 1;
     const int rv = lt.serpentine ? p : 0;
     dim3 gr(lt.hb_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        default: hipLaunchKernelGGL((k_hb<T, 3, LPT>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        default: hipLaunchKernelGGL((k_hb<T, 3, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+    }
+}
+
+template <typename T, bool PRE>
+static void hb_tiles(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
+                     hipStream_t st) {
+    switch (lt.hb_lpt) {
+        case 1: hb_dispatch<T, 1, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        case 2: hb_dispatch<T, 2, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        default: hb_dispatch<T, 4, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
     }
 }
 
 template <typename T>
 void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
                     hipStream_t st) {
-    const int m = mode == kModeLink ? kModeLinkPre : mode;
-    switch (lt.hb_lpt) {
-        case 1: hb_dispatch<T, 1>(lt, th, s, colour, m, kind, k0, k1, st); break;
-        case 2: hb_dispatch<T, 2>(lt, th, s, colour, m, kind, k0, k1, st); break;
-        default: hb_dispatch<T, 4>(lt, th, s, colour, m, kind, k0, k1, st); break;
+    if (mode != kModeLink) {
+        hb_tiles<T, false>(lt, th, s, colour, mode, kind, k0, k1, st);
+        return;
     }
-    if (mode != kModeLink) return;
+    hb_tiles<T, true>(lt, th, s, colour, kModeLinkPre, kind, k0, k1, st);
     const int p = colour & 1;
     dim3 gr(lt.n_chains), bl(kBlock);
     switch (colour >> 1) {
