@@ -36,3 +36,16 @@ def test_binding_imports_without_gpu():
     from paper_1509_08391_amd import llr
     assert llr.lib() is not None
     assert set(llr._SIGS) | {"llr_last_error", "llr_destroy"} == set(declared())
+
+
+def test_null_context_is_rejected_without_a_device():
+    """Entry points taking a context fail with an error status, not a fault,
+    when handed none; these checks run before any HIP call."""
+    from paper_1509_08391_amd import llr
+    L = llr.lib()
+    n = ctypes.c_longlong()
+    assert L.llr_link_stats(None, None, None) < 0
+    assert L.llr_stats(None, None, None, ctypes.byref(n), ctypes.byref(n)) < 0
+    assert L.llr_sweeps(None, 1, 0, llr.MODE_LINK, None) < 0
+    assert L.llr_class_pass(None, 1, 0, llr.MODE_LINK, 0) < 0
+    assert b"context" in L.llr_last_error() or b"state" in L.llr_last_error()

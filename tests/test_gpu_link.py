@@ -177,3 +177,22 @@ def test_link_walk_stays_inside_fp32(llr):
         ctx.close()
         drift[mode] = max(d)
     assert drift[llr.MODE_LINK] < 2.0 * drift[llr.MODE_FREE] + 1e-4, drift
+
+
+def test_link_mode_arguments(llr):
+    """Modes outside the public set and the multicanonical mode through the
+    plain sweep hooks are rejected; the per-link counters need bound state
+    and start at zero."""
+    ctx = llr.Context(precision=llr.FP64)
+    with pytest.raises(llr.LLRError):
+        ctx.link_stats()
+    ctx.set_params(seed=SEED)
+    ctx.add_lattice(4, [100.0, 200.0], 50.0)
+    ctx.bind_state()
+    with pytest.raises(llr.LLRError):
+        ctx.sweeps(1, mode=5)
+    with pytest.raises(llr.LLRError):
+        ctx.class_pass(1, 0, mode=llr.MODE_MUCA)
+    fixes, arcs = ctx.link_stats()
+    ctx.close()
+    assert fixes.sum() == 0 and arcs.sum() == 0
