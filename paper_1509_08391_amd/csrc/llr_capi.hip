@@ -855,9 +855,9 @@ llr_status llr_set_tiles(llr_ctx* c, int hb_lpt, int or_lpt) {
 // the candidates' fixed-point Delta E and the staples and old angle of every
 // class link of one colour, for all chains.
 static llr_status ensure_link_buffers(llr_ctx* c) {
-    if (c->ds.link_d) return LLR_OK;
-    llr_status st = dalloc(c, &c->ds.link_d, (size_t)c->ds.link_n);
-    if (st != LLR_OK) return st;
+    if (c->ds.link_d && c->ds.link_cst) return LLR_OK;
+    llr_status st;
+    if (!c->ds.link_d && (st = dalloc(c, &c->ds.link_d, (size_t)c->ds.link_n)) != LLR_OK) return st;
     unsigned char* p = nullptr;
     if ((st = dalloc(c, &p, 3 * (size_t)c->ds.link_n * elem_size(c))) != LLR_OK) return st;
     c->ds.link_cst = p;
