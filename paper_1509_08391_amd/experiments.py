@@ -478,7 +478,10 @@ def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed):
     start = ctx.export_state(0).clone()
     n = len(E_low)
     out = {}
-    for name, mode in (("class", llr.MODE_RESTRICTED), ("link", llr.MODE_LINK)):
+    # class2: the class-wise mode again with other random numbers (other sweep
+    # indices), the reference for how far two runs of one ensemble differ
+    for name, mode, s0 in (("class", llr.MODE_RESTRICTED, 1 << 22), ("class2", llr.MODE_RESTRICTED, 1 << 23),
+                           ("link", llr.MODE_LINK, 1 << 22)):
         ctx.import_state(0, start)
         ctx.sweeps(5, sweep0=1 << 21, mode=mode, want_bits=False)          # warm-up (first use allocates)
         t0 = time.perf_counter()
@@ -489,28 +492,44 @@ def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed):
         f0, r0 = ctx.link_stats()
         E = np.empty((n_meas, n))
         for t in range(n_meas):
-            ctx.sweeps(1, sweep0=(1 << 22) + t, mode=mode, want_bits=False)
+            ctx.sweeps(1, sweep0=s0 + t, mode=mode, want_bits=False)
             if (t + 1) % 10 == 0:
                 ctx.recompute_energy()
             E[t] = ctx.get_energy(0)[0]
         hp1, ha1, _, _ = ctx.stats()
         f1, r1 = ctx.link_stats()
         tau = _tau_int(E)
+        # error of the mean per interval from 20 batch means (blind to the
+        # window choice of tau_int)
+        nb = 20
+        bm = E[: (n_meas // nb) * nb].reshape(nb, -1, n).mean(axis=1)
+        err_b = bm.std(axis=0, ddof=1) / np.sqrt(nb)
         acc = float((ha1 - ha0).sum() / max((hp1 - hp0).sum(), 1))
         red = float((f1 - f0).sum() / (n_meas * 8 * n))
         arc = float((r1 - r0).sum() / (n_meas * 8 * n))
         eff = 1.0 / (2.0 * np.median(tau) * ms * 1e-3)
         out[name] = dict(ms_per_sweep=ms, tau_int=tau.tolist(), tau_median=float(np.median(tau)),
                          tau_max=float(tau.max()), class_acceptance=acc, redrawn_per_pass=red, arc_per_pass=arc,
-                         independent_per_s=eff, E_mean=E.mean(axis=0).tolist(), E_std=E.std(axis=0).tolist())
+                         independent_per_s=eff, E_mean=E.mean(axis=0).tolist(), E_std=E.std(axis=0).tolist(),
+                         E_err_batch=err_b.tolist())
         log(f"L={L} {name}: {ms:.3f} ms/sweep, tau_int median {np.median(tau):.2f} (max {tau.max():.2f}) sweeps, "
             f"class acceptance {acc:.3f}, re-drawn links per class pass {red:.1f} (arc {arc:.2f}), "
             f"{eff:.1f} independent samples/s per chain")
     ctx.close()
+    # both modes sample the same restricted ensemble: compare the means, and
+    # two class-wise runs with each other for the spread one ensemble shows
+    for a_, b_ in (("class", "class2"), ("class", "link"), ("class2", "link")):
+        z = (np.array(out[a_]["E_mean"]) - np.array(out[b_]["E_mean"])) / np.hypot(
+            out[a_]["E_err_batch"], out[b_]["E_err_batch"])
+        out[f"mean_difference_{a_}_{b_}"] = dict(chi2_per_interval=float(np.mean(z ** 2)),
+                                                 max_abs_z=float(np.abs(z).max()), argmax=int(np.abs(z).argmax()),
+                                                 mean_z=float(z.mean()), n=int(z.size), z=z.tolist())
+        log(f"L={L} {a_} vs {b_}, mean E per interval (batch errors): chi2/n {np.mean(z ** 2):.2f}, "
+            f"max |z| {np.abs(z).max():.2f} (interval {int(np.abs(z).argmax())}), mean z {z.mean():+.2f} over {z.size}")
     return out
 
 
-def link_compare(log, a20, n_meas8=4000, n_meas20=2000):
+def link_compare(log, a20, n_meas8=8000, n_meas20=4000):
     L = 8
     V6 = 6 * L ** 4
     dE = 0.005 * V6
