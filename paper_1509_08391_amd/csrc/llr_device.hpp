@@ -22,17 +22,31 @@ __host__ __device__ inline uint32_t ctr1_word(uint32_t attempt_pair, uint32_t co
     return (attempt_pair & 0xffu) | ((colour & 0xfu) << 8) | ((kind & 0xfu) << 12) | ((lat & 0xffu) << 16);
 }
 
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise operation with
+// the truth table of the three-way exclusive or (0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
 // multiplications with the published multipliers, key bumped by the published
-// Weyl constants between rounds.
+// Weyl constants between rounds.  In the first two rounds some words are
+// uniform over the wavefront (the sweep and interval counter words and the
+// key), and the compiler keeps that work on the scalar unit; from the third
+// round on every word differs per lane, and each round's two double xors are
+// one three-input operation each.
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
-                       (uint32_t)p0);
+        if (r < 2)
+            c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                           (uint32_t)p0);
+        else
+            c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
+                           (uint32_t)p0);
     }
     return c;
 }
