@@ -63,6 +63,10 @@ template <> struct Math<double> {
     __device__ static __forceinline__ void sincos_rad(double x, double* s, double* c) { sincos(x, s, c); }
     // sin, cos of (pi/2) v for |v| < 1
     __device__ static __forceinline__ void sincos_halfpi(double v, double* s, double* c) { sincospi(0.5 * v, s, c); }
+    // sin and cos of (pi/2) sunif(w)
+    __device__ static __forceinline__ void sincos_halfpi_w(uint32_t w, double* s, double* c) {
+        sincos_halfpi(sunif(w), s, c);
+    }
     __device__ static __forceinline__ double atan2_(double y, double x) { return atan2(y, x); }
     __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
     __device__ static __forceinline__ double log_(double x) { return log(x); }
@@ -73,7 +77,8 @@ template <> struct Math<double> {
 
 template <> struct Math<float> {
     static constexpr bool f32 = true;
-    __device__ static __forceinline__ float unif(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+    // ((w >> 9) + 1/2) 2^-23 = (w >> 9) 2^-23 + 2^-24: exact, so one fma gives it
+    __device__ static __forceinline__ float unif(uint32_t w) { return __fmaf_rn((float)(w >> 9), 0x1p-23f, 0x1p-24f); }
     __device__ static __forceinline__ float sunif(uint32_t w) { return ((float)((int32_t)w >> 9) + 0.5f) * 0x1p-22f; }
     __device__ static __forceinline__ void sincos_rad(float x, float* s, float* c) {
         const float r = x * 0.15915494309189535f;
@@ -86,6 +91,13 @@ template <> struct Math<float> {
     // amplifies the error of c by ~2/q, large at large coupling.
     __device__ static __forceinline__ void sincos_halfpi(float v, float* s, float* c) {
         const float r = 0.25f * v;
+        *s = __builtin_amdgcn_sinf(r);
+        *c = __builtin_amdgcn_sinf(0.25f - __builtin_fabsf(r));
+    }
+    // the same for v = sunif(w): the angle in revolutions, 0.25 ((w >> 9) + 1/2) 2^-22
+    // = (w >> 9) 2^-24 + 2^-25, is exact and one fma from the integer
+    __device__ static __forceinline__ void sincos_halfpi_w(uint32_t w, float* s, float* c) {
+        const float r = __fmaf_rn((float)((int32_t)w >> 9), 0x1p-24f, 0x1p-25f);
         *s = __builtin_amdgcn_sinf(r);
         *c = __builtin_amdgcn_sinf(0.25f - __builtin_fabsf(r));
     }

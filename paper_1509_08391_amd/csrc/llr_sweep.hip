@@ -187,9 +187,8 @@ __device__ __forceinline__ void vm_constants(T ak, T& q, T& rm1, T& kg2) {
 template <typename T>
 __device__ __forceinline__ bool vm_attempt(uint32_t wa, uint32_t wb, T q, T rm1, T kg2, T& ch, T& sh) {
     using M = Math<T>;
-    const T V1 = M::sunif(wa);
     T s_, c_;
-    M::sincos_halfpi(V1, &s_, &c_);
+    M::sincos_halfpi_w(wa, &s_, &c_);
     const T U2 = M::unif(wb);
     const T cc = M::div_(kg2, M::fma_(T(2) * c_, c_, rm1));   // kappa (r^2 - 1)/(r + z)
     bool acc = M::fma_(cc, T(2) - cc, -U2) > T(0);
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             vm_constants(ak, q, rm1, kg2);
             const uint4 w = philox10(make_uint4(h, c1base, sweep, c3), k0, k1);
             if (ak == T(0)) {
-                M::sincos_halfpi(M::sunif(w.x), &sh[r], &ch[r]);
+                M::sincos_halfpi_w(w.x, &sh[r], &ch[r]);
             } else {
                 got[r] = vm_attempt(w.x, w.y, q, rm1, kg2, ch[r], sh[r]);
                 if (!got[r]) got[r] = vm_attempt(w.z, w.w, q, rm1, kg2, ch[r], sh[r]);
@@ -508,7 +507,7 @@ __device__ __forceinline__ long long link_redraw(const LatDev& L, T* palt, uint3
     bool acc;
     if (ak == T(0)) {
         acc = lane == 0;
-        M::sincos_halfpi(M::sunif(w.x), &sh, &ch);
+        M::sincos_halfpi_w(w.x, &sh, &ch);
     } else {
         acc = (lane & 1) ? vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh) : vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh);
     }
@@ -1094,7 +1093,7 @@ __global__ void k_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, 
     T ch = T(1), sh = T(0);
     for (int m = 0; m < kVmCap / 2 && !a; ++m) {
         const uint4 w = philox10(make_uint4((uint32_t)i, c1 | (uint32_t)m, c2, c3), k0, k1);
-        if (ak == T(0)) { M::sincos_halfpi(M::sunif(w.x), &sh, &ch); a = 1; break; }
+        if (ak == T(0)) { M::sincos_halfpi_w(w.x, &sh, &ch); a = 1; break; }
         if (vm_attempt(w.x, w.y, q, rm1, kg2, ch, sh)) a = 2 * m + 1;
         else if (vm_attempt(w.z, w.w, q, rm1, kg2, ch, sh)) a = 2 * m + 2;
     }
