@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 on this kernel version with 4 class links per thread,
 # profiles/k_hb_L20x128_fp32_counters.md); None once the kernel changes until
 # the counters are taken again.
-HB_TRAFFIC = {("fp32", 4): 374.6e6}
+HB_TRAFFIC = {("fp32", 4): 374.0e6}
 
 
 def cpu_baseline(target_s=12.0):
