@@ -462,18 +462,20 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
 // arc; x comes from that truncated exponential, is kept with probability
 // exp(k (cos x - u_hi) + lam (x - x_a)), and its sign is a fair bit.
 //
-// The candidate pre-pass (k_hb in kModeLinkPre) has written, per class link,
-// the free heatbath candidate into the alternate plane and its Delta E in
-// the walk's fixed point.  That candidate is the first attempt passing the
-// sampler test; it is the constrained draw whenever it keeps E inside.  The
-// walk (one wavefront per chain, the block's other wavefronts staging the
-// next tile of candidates in LDS) scans the candidates in order, 1024 at a
-// time: wavefront prefix sums of Delta E give the running E before every
-// link, the first link whose candidate leaves [lo, hi] is re-drawn (attempt j
-// on lane j, then arc attempt i on lane i; the lowest successful lane wins,
-// which is the first success in attempt order), and the scan resumes after
-// it.  E is carried exactly in fixed point (12 bits finer than the class
-// sums), so the result does not depend on the scan's blocking.
+// The candidate pre-pass (k_hb<..., PRE = true>, mode kModeLinkPre) has
+// written, per class link, the free heatbath candidate into the alternate
+// plane, its Delta E in the walk's fixed point, and the link's staples and
+// old angle.  That candidate is the first attempt passing the sampler test;
+// it is the constrained draw whenever it keeps E inside.  The walk (one
+// wavefront per chain, the block's other wavefronts staging the next tile of
+// candidates in LDS) scans the candidates in order, 1024 at a time:
+// wavefront prefix sums of Delta E give the running E before every link, the
+// first link whose candidate leaves [lo, hi] is re-drawn (attempt j on lane
+// j, then arc attempt i on lane i; the lowest successful lane wins, which is
+// the first success in attempt order), and the rest of the step is checked
+// again with its running sums shifted by that link's change of Delta E.  E
+// is carried exactly in fixed point (12 bits finer than the class sums), so
+// the result does not depend on the scan's blocking.
 // ---------------------------------------------------------------------------
 constexpr int kWalkTile = 2048;          // class links staged in LDS per tile
 constexpr int kWalkPer = 16;             // links per lane per scan step (1024 per step)
