@@ -53,6 +53,11 @@
            under --inputs, else a_k = 1.011 ~ beta_c(20) throughout).
   linkprof 60 sweeps per mode of the L = 20 set only, for a kernel trace.
 
+  batchprof the config2 lattice set (L = 12, 16, 20, 64 intervals each, one
+           launch per class pass for all three), FP32, replica exchange,
+           a_k = 1: hot start, approach, autotune, then 200 restricted sweeps
+           timed; for a kernel trace of the batched launch.
+
   fss      beta_c(L) and the C_V peak for the finite-size analysis of Sec. 3.4
            on this implementation's own runs: L = 8, 10, 12, 14 (part 0) and
            16, 18 (part 1), 96 intervals over u in [0.56, 0.70], four replicas
@@ -561,6 +566,33 @@ def link_profile(log, a20, n=60):
     return dict(redrawn_per_pass=float(f.sum() / (n * 8 * len(E_low))), arc_per_pass=float(r.sum() / (n * 8 * len(E_low))))
 
 
+def batch_profile(log, n=200):
+    lats = []
+    for L in (12, 16, 20):
+        V6 = 6 * L ** 4
+        dE = 0.1 / 64 * V6
+        lats.append((L, 0.58 * V6 + dE * np.arange(64), dE))
+    ctx = llr.Context(precision=llr.FP32, device=0)
+    ctx.set_params(seed=SEED, replica_exchange=True, recompute_every=10, approach_cap=20000)
+    for (L, E_low, dE) in lats:
+        ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    for i in range(3):
+        ctx.set_a(i, 1.0)
+    ctx.hot_start()
+    ap = ctx.approach()
+    tiles = ctx.autotune()
+    ctx.sweeps(10, sweep0=1 << 20, mode=llr.MODE_RESTRICTED, want_bits=False)
+    t0 = time.perf_counter()
+    ctx.sweeps(n, sweep0=(1 << 20) + 16, mode=llr.MODE_RESTRICTED, want_bits=False)
+    dt = (time.perf_counter() - t0) / n
+    upd = sum(2 * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lats)
+    ctx.close()
+    log(f"{dt * 1e3:.3f} ms per sweep of 192 chains (L = 12, 16, 20), {upd / dt:.4g} link updates/s, "
+        f"tiles {tiles}, approach sweeps {[int(x) for x in ap]}")
+    return dict(ms_per_sweep=dt * 1e3, updates_per_s=upd / dt, tiles=list(tiles), approach_sweeps=list(map(int, ap)))
+
+
 FSS_PARTS = {0: (8, 10, 12, 14), 1: (16, 18)}
 
 
@@ -633,7 +665,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
                                             "dE8", "obs8",
-                                            "config4b", "linkcmp", "linkprof", "fss"])
+                                            "config4b", "linkcmp", "linkprof", "fss", "batchprof"])
     ap.add_argument("--out", default="experiment_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
                     "(config3 reads config1 and config2, config4 reads config3); default --out")
@@ -665,6 +697,8 @@ def main():
         rec = dE_study_8(log)
     elif args.which == "obs8":
         rec = obs8(log)
+    elif args.which == "batchprof":
+        rec = batch_profile(log)
     elif args.which == "fss" and args.combine:
         import glob
         src = args.inputs or args.out
