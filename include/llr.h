@@ -118,8 +118,10 @@ llr_status llr_set_a(llr_ctx *ctx, int lattice_id, const double *a);
  * full FP64 energy computation. */
 llr_status llr_hot_start(llr_ctx *ctx);
 /* Import/export one lattice's angles in canonical layout (device pointer,
- * n_intervals x 4 x V values of the context precision).  Import resets the
- * chain <-> interval assignment to the identity and recomputes E. */
+ * n_intervals x 4 x V values of the context precision), in radians and
+ * expected in [-pi, pi) as every pass writes them (the energy and the FP64
+ * staple arithmetic take plaquette and staple sums of such angles).  Import
+ * resets the chain <-> interval assignment to the identity and recomputes E. */
 llr_status llr_import_state(llr_ctx *ctx, int lattice_id, const void *dev_canonical);
 llr_status llr_export_state(llr_ctx *ctx, int lattice_id, void *dev_canonical);
 
