@@ -152,6 +152,14 @@ llr_status llr_run(llr_ctx *ctx);
  * met the stopping rule.  llr_run = llr_rm_begin + llr_rm_step(n_rm). */
 llr_status llr_rm_begin(llr_ctx *ctx);
 llr_status llr_rm_step(llr_ctx *ctx, int iterations);
+/* Which restriction the restricted sweeps of llr_run / llr_rm_step and of the
+ * measurements of llr_observables impose (Sec. 2.4: rejection of a
+ * colour class whose energy leaves the interval, or the constraint applied per
+ * link when each new angle is drawn).  per_link 0 (default): class-wise,
+ * mode LLR_MODE_RESTRICTED; 1: per link, mode LLR_MODE_LINK (its buffers are
+ * allocated by the next sweep).  The approach is unchanged.  LLR_EINVAL for a
+ * null context or another value. */
+llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
 /* Final a_k, first RM iteration n with |a^(n+1)-a^(n)| < eps (-1 if never)
  * and sweeps up to it (approach + (n+1)(N_TH+N_A)); host arrays, n_intervals. */
 llr_status llr_get_a(llr_ctx *ctx, int lattice_id, double *a, int *conv_iter, long long *conv_sweeps);

@@ -65,7 +65,7 @@ class RunParams(C.Structure):
                 ("recompute_every", C.c_int), ("approach_cap", C.c_int),
                 ("replica_exchange", C.c_int), ("f32", C.c_int), ("lattice_id", C.c_int),
                 ("hot_start", C.c_int), ("seed", C.c_uint64),
-                ("dE", C.c_double), ("w", C.c_double), ("eps", C.c_double)]
+                ("dE", C.c_double), ("w", C.c_double), ("eps", C.c_double), ("link", C.c_int)]
 
 
 class RunOut(C.Structure):
@@ -241,15 +241,17 @@ def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_REST
 
 def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=10,
             approach_cap=100000, replica_exchange=False, f32=False, lattice_id=0, eps=1e-4,
-            theta=None, record_bits=False):
-    """Algorithm 1 on every interval of one lattice.  Returns a dict of results."""
+            theta=None, record_bits=False, per_link=False):
+    """Algorithm 1 on every interval of one lattice.  Returns a dict of results.
+    per_link: the restricted sweeps impose the restriction per link (Sec. 2.4)
+    instead of rejecting whole colour classes."""
     E_low = _f64(E_low)
     n = E_low.size
     V = L ** d
     if w is None:
         w = 2.0 * dE if replica_exchange else dE
     p = RunParams(d, L, n, n_th, n_a, n_rm, recompute_every, approach_cap, int(replica_exchange),
-                  int(f32), lattice_id, int(theta is None), seed, dE, w, eps)
+                  int(f32), lattice_id, int(theta is None), seed, dE, w, eps, int(per_link))
     a = _f64(a0).copy() if np.ndim(a0) else np.full(n, float(a0))
     th = np.empty((n, d, V)) if theta is None else _f64(theta).copy()
     a_hist = np.zeros((n_rm + 1, n))

@@ -770,6 +770,7 @@ typedef struct {
     double dE;            /* centre spacing */
     double w;             /* restriction width */
     double eps;           /* convergence threshold on |a^(n+1) - a^(n)| */
+    int link;             /* 1: restriction imposed per link (Sec. 2.4), 0: class-wise rejection */
 } or_run_params;
 
 typedef struct {
@@ -903,7 +904,8 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                 double *scr = (double *)malloc(sizeof(double) * (g.V / 2 + 1));
                 int k = itv[c];
                 pass_ctx_t pc = {{key[0], key[1]}, KIND_SWEEP, p->lattice_id, t_glob, (uint32_t)k, p->f32};
-                int bits = sweep_chain(&g, o->theta + c * nl, scr, 0, o->a[k], lo[k], hi[k], &o->E[c], &pc, 1);
+                int bits = sweep_chain(&g, o->theta + c * nl, scr, p->link ? 4 : 0, o->a[k], lo[k], hi[k],
+                                       &o->E[c], &pc, 1);
                 if (o->bits) o->bits[(bitrow + (long long)it * nsw + j) * n + c] = (uint16_t)bits;
                 if (recompute) o->E[c] = energy(&g, o->theta + c * nl);
                 free(scr);

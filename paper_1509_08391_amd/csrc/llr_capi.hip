@@ -47,6 +47,7 @@ struct TimingPair {
 
 struct llr_ctx {
     bool muca_ready = false;   // multicanonical weights built (llr_muca_begin)
+    bool per_link = false;     // Algorithm 1's restricted sweeps impose the restriction per link
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = LLR_FP64;
@@ -310,14 +311,23 @@ static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bo
     launch_end_sweep(c->lt, c->ds, measure ? 1 : 0, 0, 1, c->stream);
 }
 
+static llr_status ensure_link_buffers(llr_ctx* c);
+
+// the heatbath mode of Algorithm 1's restricted sweeps
+static int restricted_mode(const llr_ctx* c) { return c->per_link ? LLR_MODE_LINK : LLR_MODE_RESTRICTED; }
+
 // One restricted sweep of the Robbins-Monro loop.  Without per-kernel timing
 // the 18-20 launches of a sweep are captured once per variant into a HIP graph
 // (kernel nodes only) and replayed; the sweep index lives in device memory, so
 // every replay advances it.
 template <typename T>
 static llr_status launch_sweep(llr_ctx* c, bool recompute, bool replica, bool measure) {
+    if (c->per_link) {   // before any capture: the first use allocates
+        const llr_status st = ensure_link_buffers(c);
+        if (st != LLR_OK) return st;
+    }
     if (!c->use_graphs || c->timing) {
-        enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, recompute, replica, measure);
+        enqueue_sweep<T>(c, restricted_mode(c), recompute, replica, measure);
         return LLR_OK;
     }
     const int key = (recompute ? 1 : 0) | (replica ? 2 : 0) | (measure ? 4 : 0);
@@ -330,7 +340,7 @@ static llr_status launch_sweep(llr_ctx* c, bool recompute, bool replica, bool me
         c->stream = c->cap_stream;
         hipError_t e0 = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e0 == hipSuccess) {
-            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, recompute, replica, measure);
+            enqueue_sweep<T>(c, restricted_mode(c), recompute, replica, measure);
             e0 = hipStreamEndCapture(c->stream, &g);
         }
         c->stream = user;
@@ -573,6 +583,10 @@ static llr_status muca_sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, d
 
 template <typename T>
 static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sweep0, double* E_out, double* B_out) {
+    if (c->per_link) {
+        const llr_status st = ensure_link_buffers(c);
+        if (st != LLR_OK) return st;
+    }
     const uint32_t s0 = (uint32_t)sweep0;
     HIPCHK(hipMemcpyAsync(c->ds.sweep_ctr, &s0, 4, hipMemcpyHostToDevice, c->stream));
     const int n = c->lt.n_chains;
@@ -580,7 +594,7 @@ static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sw
     std::vector<int> conf(n);
     for (int m = 0; m < n_meas; ++m) {
         for (int t = 0; t < gap; ++t)
-            enqueue_sweep<T>(c, LLR_MODE_RESTRICTED, false, c->prm.replica_exchange != 0, false);
+            enqueue_sweep<T>(c, restricted_mode(c), false, c->prm.replica_exchange != 0, false);
         {
             TimeScope ts(c, 2);
             launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream, true);
@@ -1014,6 +1028,16 @@ llr_status llr_stats(llr_ctx* c, long long* hb_prop, long long* hb_acc, long lon
     HIPCHK(hipMemcpy(re, c->ds.re_cnt, 16, hipMemcpyDeviceToHost));
     if (re_prop) *re_prop = (long long)re[0];
     if (re_acc) *re_acc = (long long)re[1];
+    return LLR_OK;
+}
+
+llr_status llr_set_restriction(llr_ctx* c, int per_link) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    if (per_link != 0 && per_link != 1) return fail(LLR_EINVAL, "per_link must be 0 or 1");
+    if (c->per_link != (per_link != 0)) {
+        c->per_link = per_link != 0;
+        drop_graphs(c);   // the captured sweeps hold the heatbath mode
+    }
     return LLR_OK;
 }
 

@@ -53,6 +53,7 @@ _SIGS = {
     "llr_run": [C.c_void_p],
     "llr_rm_begin": [C.c_void_p],
     "llr_rm_step": [C.c_void_p, C.c_int],
+    "llr_set_restriction": [C.c_void_p, C.c_int],
     "llr_get_a": [C.c_void_p, C.c_int, _p(C.c_double), _p(C.c_int), _p(C.c_longlong)],
     "llr_get_history": [C.c_void_p, C.c_int, _p(C.c_double)],
     "llr_get_energy": [C.c_void_p, C.c_int, _p(C.c_double), _p(C.c_int)],
@@ -279,6 +280,11 @@ class Context:
 
     def set_graphs(self, on):
         _check(lib().llr_set_graphs(self.h, int(on)))
+
+    def set_restriction(self, per_link):
+        """Restricted sweeps of run / rm_step and the measurements: per link
+        (True) or class-wise rejection (False, the default)."""
+        _check(lib().llr_set_restriction(self.h, int(per_link)))
 
     def set_order(self, serpentine):
         _check(lib().llr_set_order(self.h, int(serpentine)))

@@ -25,12 +25,18 @@
   * the walk keeps every chain inside its interval, and its carried FP32
     energy drifts from a full recomputation no more than the class-wise
     passes' does (measured: ~1e-3 after 5 sweeps at L=6, ~2e-8 per link
-    update, the reason the FP64 recompute runs every K sweeps)."""
+    update, the reason the FP64 recompute runs every K sweeps);
+  * Algorithm 1 with the restriction imposed per link (llr_set_restriction):
+    two Robbins-Monro iterations of one sweep each, replayed from captured
+    graphs, against the oracle's run from the same states (a_k, energies,
+    angles), and the full L=4 run over 4 seeds as distributions of the final
+    a_k, FP64 and FP32."""
 import numpy as np
 import pytest
 
 import oracle
 from tests.inputs import circ_dist, random_state
+from tests.test_gpu_parity import _states_in_intervals
 
 pytestmark = pytest.mark.gpu
 
@@ -196,3 +202,96 @@ def test_link_mode_arguments(llr):
     fixes, arcs = ctx.link_stats()
     ctx.close()
     assert fixes.sum() == 0 and arcs.sum() == 0
+
+
+def test_run_per_link_matches_oracle_fp64(llr):
+    """Two Robbins-Monro iterations (N_TH = 0, N_A = 1, E recomputed after
+    every sweep) with the per-link restriction from the same states: the
+    trajectories separate only through the window bounds' rounding (see the
+    module notes), ~1e-8 after two sweeps."""
+    import torch
+    d, L, n = 4, 4, 6
+    V6 = 6 * L ** 4
+    dE = 0.02 * V6
+    E_low = 0.58 * V6 + dE * np.arange(n)
+    th = _states_in_intervals(L, E_low, dE, seed=31)
+    ctx = llr.Context(precision=llr.FP64)
+    ctx.set_params(seed=SEED, n_th=0, n_a=1, n_rm=2, recompute_every=1)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    ctx.set_a(0, 1.0)
+    ctx.import_state(0, torch.from_numpy(th))
+    ctx.set_restriction(True)
+    ctx.run()
+    a, _, _ = ctx.get_a(0)
+    hist = ctx.get_history(0)
+    E, _ = ctx.get_energy(0)
+    got = ctx.export_state(0).cpu().numpy()
+    fixes, _ = ctx.link_stats()
+    ctx.close()
+    r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=0, n_a=1, n_rm=2, seed=SEED, recompute_every=1,
+                       theta=th, approach_cap=0, per_link=True)
+    assert fixes.sum() > 0
+    assert np.max(np.abs(hist - r["a_hist"])) < 1e-7
+    assert np.max(np.abs(a - r["a"])) < 1e-7
+    assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-9
+    dist = circ_dist(got, r["theta"])
+    assert np.max(dist) < 1e-5 and np.median(dist) < 1e-10, (np.max(dist), np.median(dist))
+
+
+def test_set_restriction_arguments(llr):
+    """Only 0 and 1 are accepted; switching back to the class-wise restriction
+    leaves the per-link counters untouched."""
+    ctx = llr.Context(precision=llr.FP32)
+    ctx.set_params(seed=SEED, n_th=0, n_a=2, n_rm=1)
+    L = 4
+    V6 = 6 * L ** 4
+    dE = 0.02 * V6
+    E_low = 0.58 * V6 + dE * np.arange(3)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    with pytest.raises(llr.LLRError):
+        ctx.set_restriction(2)
+    import torch
+    ctx.import_state(0, torch.from_numpy(_states_in_intervals(L, E_low, dE, seed=32).astype(np.float32)))
+    ctx.set_a(0, 1.0)
+    ctx.set_restriction(False)
+    ctx.run()
+    fixes0, _ = ctx.link_stats()
+    ctx.close()
+    assert fixes0.sum() == 0
+
+
+@pytest.mark.slow
+def test_full_run_per_link_statistical(llr):
+    """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
+    dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start) with the
+    per-link restriction: final a_k over 4 seeds, GPU FP64 and FP32 against
+    the oracle's per-link runs, means within 4 combined standard errors."""
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.5 * V6 + dE * np.arange(8)
+    seeds = [SEED + 17 * i for i in range(4)]
+    O = np.array([oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd,
+                                 approach_cap=20000, per_link=True)["a"] for sd in seeds])
+    for prec in ("FP64", "FP32"):
+        G = []
+        for sd in seeds:
+            ctx = llr.Context(precision=getattr(llr, prec))
+            ctx.set_params(seed=sd, n_th=100, n_a=100, n_rm=20, approach_cap=20000)
+            ctx.add_lattice(L, E_low, dE)
+            ctx.bind_state()
+            ctx.set_a(0, 1.0)
+            ctx.set_restriction(True)
+            ctx.hot_start()
+            ctx.approach()
+            ctx.run()
+            G.append(ctx.get_a(0)[0])
+            fixes, _ = ctx.link_stats()
+            assert fixes.sum() > 0
+            ctx.close()
+        G = np.array(G)
+        se = np.maximum(np.sqrt(G.var(0, ddof=1) / len(seeds) + O.var(0, ddof=1) / len(seeds)), 2e-4)
+        z = np.abs(G.mean(0) - O.mean(0)) / se
+        assert np.all(z < 4.0), (prec, z, G.mean(0) - O.mean(0))

@@ -3,8 +3,8 @@
     cos(theta_P), theta_P uniform (character expansion; the winding terms are
     below 1e-20 here), so the exact restricted root a*_k of <<Delta E>>_k = 0
     (eqs. (kk11)-(kk12)) follows by quadrature; the full oracle LLR run
-    (approach, class-restricted heatbath/overrelaxation, Robbins-Monro) must
-    land on it;
+    (approach, restricted heatbath/overrelaxation, Robbins-Monro) must land
+    on it, with the restriction imposed class-wise or per link;
   * 2D canonical heatbath vs the exact <cos theta_P> = sum I_n^{N_P-1} I_n' / sum I_n^{N_P};
   * 4D: a_k agrees with beta where the canonical <E>(beta) is the interval
     centre, away from beta_c (eq. (kk15); O(1/V) saddle-point offset, appendix);
@@ -38,12 +38,15 @@ def _astar(lo, hi, NP):
 
 
 @pytest.mark.slow
-def test_llr_2d_matches_exact_restricted_root():
+@pytest.mark.parametrize("per_link", [False, True])
+def test_llr_2d_matches_exact_restricted_root(per_link):
+    """Both restrictions of Sec. 2.4 (class-wise rejection and the per-link
+    constraint) drive Algorithm 1 to the same exact root."""
     d, L, w = 2, 8, 8.0
     NP = L * L
     El = np.array([16.0, 22.0, 28.0])
     exact = np.array([_astar(e, e + w, NP) for e in El])
-    runs = [oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s)["a"]
+    runs = [oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link)["a"]
             for s in range(3)]
     A = np.array(runs)
     # per-seed spread measured at ~2e-3; mean of 3 seeds within 4e-3
