@@ -13,6 +13,10 @@ heatbath + 8 overrelaxation class passes of all chains, recompute, replica
 exchange, measurement), the a_k update, and the FP64 reconstruction of
 beta_c and the C_V peak on beta in [1.008, 1.012].  One link update = one
 heatbath or one overrelaxation of one link; a sweep is 2 x 4V updates.
+
+--order: interleaved (default; heatbath then overrelaxation per colour, one
+fused launch per colour) or grouped (heatbath of every colour, then
+overrelaxation of every colour, 16 launches); the same updates either way.
 """
 import argparse
 import json
@@ -34,13 +38,14 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 on this kernel version with 4 class links per thread,
 # profiles/k_hb_L20x128_fp32_counters.md); None once the kernel changes until
 # the counters are taken again.
-HB_TRAFFIC = {("fp32", 4): 374.0e6}
+HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6}
 
 
-def cpu_baseline(target_s=12.0):
+def cpu_baseline(order, target_s=12.0):
     """The oracle (plain FP64 C, OpenMP over chains) on a bounded sample of the
     same workload: one L=20 chain per thread from the oracle's hot start,
-    sweeps (heatbath + overrelaxation) until ~target_s seconds of CPU work."""
+    sweeps (heatbath + overrelaxation, in the given order) until ~target_s
+    seconds of CPU work."""
     import oracle
     oracle.build(force=False)
     threads = oracle.num_threads()
@@ -53,14 +58,15 @@ def cpu_baseline(target_s=12.0):
     t0 = time.perf_counter()
     while True:
         E, _ = oracle.sweeps(4, L, th, a, lo, hi, np.arange(nch), E, 1, done, mode=oracle.MODE_RESTRICTED,
-                             seed=SEED)
+                             seed=SEED, order=oracle.SWEEP_INTERLEAVED if order == "interleaved"
+                             else oracle.SWEEP_GROUPED)
         done += 1
         if time.perf_counter() - t0 > target_s:
             break
     dt = time.perf_counter() - t0
     upd = 2.0 * 4 * L ** 4 * nch * done
     return {"value": upd / dt, "unit": "link updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} restricted sweep(s) (8 heatbath + 8 overrelaxation passes) of {nch} "
+            "sample": f"{done} restricted sweep(s) (8 heatbath + 8 overrelaxation passes, {order}) of {nch} "
                       f"L=20 chains, one per thread, from the oracle's hot start; {dt:.1f} s"}
 
 
@@ -71,6 +77,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", choices=["interleaved", "grouped"], default="interleaved")
     ap.add_argument("--n-th", type=int, default=500)
     ap.add_argument("--n-a", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -112,6 +119,7 @@ def main():
     ctx.add_lattice(L, E_low, dE)
     ctx.bind_state()
     ctx.set_a(0, np.full(N_INT, 1.0))
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if args.order == "interleaved" else llr.SWEEP_GROUPED)
     t_setup = time.perf_counter()
     ctx.hot_start()
     ctx.approach_begin()
@@ -153,9 +161,13 @@ def main():
     value = updates / dt
     esz = 4 if prec == llr.FP32 else 8
     # algorithmic bytes of one heatbath pass: the pass reads the whole lattice
-    # once (4V angles for V/2 class links = 8 angles per link update) and
-    # writes one proposal per class link: 9 angles per update
-    bytes_per_hb_launch = N_INT * (V // 2) * 9 * esz
+    # once (4V angles for V/2 class links = 8 angles per class link) and
+    # writes one proposal per class link: 9 angles per class link (one
+    # update); the fused pass of the interleaved order writes two (the
+    # overrelaxed candidate and the overrelaxed old angle): 10 angles per
+    # class link for its two updates
+    per_link = 10 if args.order == "interleaved" else 9
+    bytes_per_hb_launch = N_INT * (V // 2) * per_link * esz
     hb_avg_s = tm["hb_ms"] / max(tm["hb_n"], 1) / 1e3
     achieved = bytes_per_hb_launch / hb_avg_s / 1e9 if hb_avg_s > 0 else 0.0
     or_avg_s = tm["or_ms"] / max(tm["or_n"], 1) / 1e3
@@ -176,11 +188,13 @@ def main():
                                "replica exchange (w=2dE), N_TH=500, N_A=2000; step = one Robbins-Monro "
                                "iteration (2500 sweeps) + beta_c reconstruction",
                    "L": L, "intervals": N_INT, "sweeps_per_step": nsw, "tiles": list(tiles),
+                   "sweep_order": args.order,
                    "precision": "fp32 angles, fp64 energy/test/RM" if prec == llr.FP32 else "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": HB_TRAFFIC.get((args.precision, tiles[0])),
-                     "kernel": "heatbath class pass (k_hb)",
+                     "traffic": HB_TRAFFIC.get((args.precision, tiles[0], args.order)),
+                     "kernel": "heatbath class pass (k_hb)" if args.order == "grouped"
+                               else "heatbath + overrelaxation class pass (k_hb, fused)",
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
                      "overrelaxation_avg_launch_us": or_avg_s * 1e6},
         "acceptance": {"heatbath_class": float(ha.sum() / max(hp.sum(), 1)),
@@ -188,7 +202,7 @@ def main():
         "approach_sweeps": int(ap_sweeps[0]),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.order)
     print(json.dumps(out))
 
 

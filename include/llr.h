@@ -108,7 +108,9 @@ llr_status llr_add_lattice(llr_ctx *ctx, int L, int n_intervals, const double *E
  * written to the non-current plane). */
 llr_status llr_state_bytes(llr_ctx *ctx, size_t *bytes);
 /* Bind caller-owned device memory of exactly llr_state_bytes bytes, aligned
- * to 256 bytes.  The library reads and writes it until destroy/rebind. */
+ * to 256 bytes.  The library reads and writes it until destroy/rebind.  It
+ * sets every angle to 0 (a cold start); llr_hot_start or llr_import_state
+ * then set the configuration. */
 llr_status llr_bind_state(llr_ctx *ctx, void *dev_state, size_t bytes);
 
 /* Initial a_k^(0) per interval (host, n_intervals); default 1.0. */
@@ -160,6 +162,23 @@ llr_status llr_rm_step(llr_ctx *ctx, int iterations);
  * allocated by the next sweep).  The approach is unchanged.  LLR_EINVAL for a
  * null context or another value. */
 llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
+/* Order of the class passes within one sweep (Algorithm 1 fixes only that a
+ * sweep evolves the whole system once; each link gets one heatbath and one
+ * overrelaxation update either way):
+ *   LLR_SWEEP_GROUPED (default): heatbath of colours 0..7, then
+ *     overrelaxation of colours 0..7;
+ *   LLR_SWEEP_INTERLEAVED: for c = 0..7, heatbath of colour c, then the
+ *     overrelaxation of colour c.  The class's staples do not change between
+ *     the two, so both run in one launch that writes the overrelaxed heatbath
+ *     candidate and the overrelaxed old angle; the restricted decision of the
+ *     heatbath picks one (overrelaxation leaves E unchanged).  The result is
+ *     that of the two separate passes in this order, bit for bit.
+ * Applies to the restricted, free and multicanonical sweeps of llr_run /
+ * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run;
+ * sweeps with the per-link restriction and approach-mode sweeps stay grouped.
+ * LLR_EINVAL for a null context or another value. */
+enum { LLR_SWEEP_GROUPED = 0, LLR_SWEEP_INTERLEAVED = 1 };
+llr_status llr_set_sweep_order(llr_ctx *ctx, int order);
 /* Final a_k, first RM iteration n with |a^(n+1)-a^(n)| < eps (-1 if never)
  * and sweeps up to it (approach + (n+1)(N_TH+N_A)); host arrays, n_intervals. */
 llr_status llr_get_a(llr_ctx *ctx, int lattice_id, double *a, int *conv_iter, long long *conv_sweeps);

@@ -29,6 +29,9 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP, KIND_BOOT, KIND_MUCA = 0, 1, 2, 3, 4, 5, 6
 MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
+# order of the class passes in a sweep: heatbath of every colour then
+# overrelaxation of every colour, or heatbath and overrelaxation per colour
+SWEEP_GROUPED, SWEEP_INTERLEAVED = 0, 1
 N_PARAMS = 4417
 
 
@@ -65,7 +68,8 @@ class RunParams(C.Structure):
                 ("recompute_every", C.c_int), ("approach_cap", C.c_int),
                 ("replica_exchange", C.c_int), ("f32", C.c_int), ("lattice_id", C.c_int),
                 ("hot_start", C.c_int), ("seed", C.c_uint64),
-                ("dE", C.c_double), ("w", C.c_double), ("eps", C.c_double), ("link", C.c_int)]
+                ("dE", C.c_double), ("w", C.c_double), ("eps", C.c_double), ("link", C.c_int),
+                ("interleave", C.c_int)]
 
 
 class RunOut(C.Structure):
@@ -225,8 +229,9 @@ def class_pass(d, L, theta, hb, colour, mode, a, lo, hi, E, seed, kind=KIND_SWEE
 
 
 def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_RESTRICTED,
-           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False):
-    """n_sweeps sweeps of every chain of theta (n_chains, d, V), in place.  Returns bits."""
+           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False, order=SWEEP_GROUPED):
+    """n_sweeps sweeps of every chain of theta (n_chains, d, V), in place.  Returns bits.
+    order (with do_or): SWEEP_GROUPED or SWEEP_INTERLEAVED."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous
     nch = theta.shape[0]
     a, lo, hi = _f64(a), _f64(lo), _f64(hi)
@@ -235,23 +240,26 @@ def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_REST
     bits = np.zeros((n_sweeps, nch), dtype=np.int32)
     lib().or_sweeps(d, L, nch, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
                     _ptr(hi, C.c_double), _ptr(itv, C.c_int), _ptr(Earr, C.c_double), n_sweeps,
-                    sweep0, mode, kind, int(do_or), seed, lattice_id, int(f32), _ptr(bits, C.c_int))
+                    sweep0, mode, kind, (2 if order == SWEEP_INTERLEAVED else 1) if do_or else 0, seed,
+                    lattice_id, int(f32), _ptr(bits, C.c_int))
     return Earr, bits
 
 
 def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=10,
             approach_cap=100000, replica_exchange=False, f32=False, lattice_id=0, eps=1e-4,
-            theta=None, record_bits=False, per_link=False):
+            theta=None, record_bits=False, per_link=False, order=SWEEP_GROUPED):
     """Algorithm 1 on every interval of one lattice.  Returns a dict of results.
     per_link: the restricted sweeps impose the restriction per link (Sec. 2.4)
-    instead of rejecting whole colour classes."""
+    instead of rejecting whole colour classes.  order: of the class passes in
+    a sweep (SWEEP_GROUPED or SWEEP_INTERLEAVED; per-link sweeps stay grouped)."""
     E_low = _f64(E_low)
     n = E_low.size
     V = L ** d
     if w is None:
         w = 2.0 * dE if replica_exchange else dE
     p = RunParams(d, L, n, n_th, n_a, n_rm, recompute_every, approach_cap, int(replica_exchange),
-                  int(f32), lattice_id, int(theta is None), seed, dE, w, eps, int(per_link))
+                  int(f32), lattice_id, int(theta is None), seed, dE, w, eps, int(per_link),
+                  int(order == SWEEP_INTERLEAVED))
     a = _f64(a0).copy() if np.ndim(a0) else np.full(n, float(a0))
     th = np.empty((n, d, V)) if theta is None else _f64(theta).copy()
     a_hist = np.zeros((n_rm + 1, n))

@@ -712,17 +712,25 @@ void or_link_pass(int d, int L, double *theta, int colour, double a, double lo, 
     geo_free(&g);
 }
 
-/* One restricted sweep (heatbath over all 2d colours, then overrelaxation over
- * all 2d colours) of one chain; bits receives the accept bit of each pass
- * (bit c: heatbath colour c, bit 2d + c: overrelaxation colour c). */
+/* One restricted sweep of one chain.  do_or 0: heatbath over all 2d colours;
+ * 1: then overrelaxation over all 2d colours (grouped order); 2: heatbath and
+ * overrelaxation of colour 0, then of colour 1, ... (interleaved order).
+ * Algorithm 1 asks only for one sweep of the whole system: either order gives
+ * every link one heatbath and one overrelaxation update.  bits receives the
+ * accept bit of each pass (bit c: heatbath colour c, bit 2d + c:
+ * overrelaxation colour c). */
 static int sweep_chain(const geo_t *g, double *th, double *scr, int mode, double a, double lo,
                        double hi, double *E, const pass_ctx_t *pc, int do_or)
 {
     int bits = 0;
     int nc = 2 * g->d;
-    for (int c = 0; c < nc; ++c)
+    if (do_or == 2 && (mode == 1 || mode == 4)) do_or = 1;   /* approach and per-link sweeps stay grouped */
+    for (int c = 0; c < nc; ++c) {
         if (class_pass(g, th, scr, 1, c, mode, a, lo, hi, E, pc, NULL, NULL)) bits |= 1 << c;
-    if (do_or)
+        if (do_or == 2 && class_pass(g, th, scr, 0, c, mode, a, lo, hi, E, pc, NULL, NULL))
+            bits |= 1 << (nc + c);
+    }
+    if (do_or == 1)
         for (int c = 0; c < nc; ++c)
             if (class_pass(g, th, scr, 0, c, mode, a, lo, hi, E, pc, NULL, NULL)) bits |= 1 << (nc + c);
     return bits;
@@ -771,6 +779,7 @@ typedef struct {
     double w;             /* restriction width */
     double eps;           /* convergence threshold on |a^(n+1) - a^(n)| */
     int link;             /* 1: restriction imposed per link (Sec. 2.4), 0: class-wise rejection */
+    int interleave;       /* 1: sweeps in the interleaved order (sweep_chain) */
 } or_run_params;
 
 typedef struct {
@@ -905,7 +914,7 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                 int k = itv[c];
                 pass_ctx_t pc = {{key[0], key[1]}, KIND_SWEEP, p->lattice_id, t_glob, (uint32_t)k, p->f32};
                 int bits = sweep_chain(&g, o->theta + c * nl, scr, p->link ? 4 : 0, o->a[k], lo[k], hi[k],
-                                       &o->E[c], &pc, 1);
+                                       &o->E[c], &pc, (p->interleave && !p->link) ? 2 : 1);
                 if (o->bits) o->bits[(bitrow + (long long)it * nsw + j) * n + c] = (uint16_t)bits;
                 if (recompute) o->E[c] = energy(&g, o->theta + c * nl);
                 free(scr);

@@ -48,6 +48,7 @@ struct TimingPair {
 struct llr_ctx {
     bool muca_ready = false;   // multicanonical weights built (llr_muca_begin)
     bool per_link = false;     // Algorithm 1's restricted sweeps impose the restriction per link
+    bool interleave = false;   // sweep = (heatbath, overrelaxation) per colour, fused in one launch
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = LLR_FP64;
@@ -298,13 +299,20 @@ static void enqueue_energy(llr_ctx* c) {
 // one restricted sweep of all chains, then recompute / replica exchange / measurement
 template <typename T>
 static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bool measure) {
-    {
+    if (c->interleave && (mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_MUCA)) {
         TimeScope ts(c, 0, 8);
-        for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, mode, kSweep);
-    }
-    {
-        TimeScope ts(c, 1, 8);
-        for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
+        for (int col = 0; col < 8; ++col)
+            launch_hb_or_pass<T>(c->lt, (T*)c->state, c->ds, col, mode, (uint32_t)c->prm.seed,
+                                 (uint32_t)(c->prm.seed >> 32), c->stream);
+    } else {
+        {
+            TimeScope ts(c, 0, 8);
+            for (int col = 0; col < 8; ++col) enqueue_hb_pass<T>(c, col, mode, kSweep);
+        }
+        {
+            TimeScope ts(c, 1, 8);
+            for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
+        }
     }
     if (recompute) enqueue_energy<T>(c);
     if (replica) launch_replica(c->lt, c->ds, (uint32_t)c->prm.seed, (uint32_t)(c->prm.seed >> 32), c->stream);
@@ -710,6 +718,12 @@ llr_status llr_bind_state(llr_ctx* c, void* dev_state, size_t bytes) {
     drop_graphs(c);
     c->state = dev_state;
     c->have_energy = false;
+    // every angle 0 (a cold start): the energy pass that follows the import of
+    // one lattice covers all lattices, and an uninitialised one would feed it
+    // values outside [-pi, pi) whose fixed-point sums overflow into the
+    // per-chain arrival counters
+    HIPCHK(hipMemsetAsync(dev_state, 0, bytes, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return LLR_OK;
 }
 
@@ -852,6 +866,17 @@ llr_status llr_set_order(llr_ctx* c, int serpentine) {
     if (!c || !c->laid_out) return fail(LLR_ESTATE, "lay out the lattices first");
     c->lt.serpentine = serpentine ? 1 : 0;
     drop_graphs(c);
+    return LLR_OK;
+}
+
+llr_status llr_set_sweep_order(llr_ctx* c, int order) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    if (order != LLR_SWEEP_GROUPED && order != LLR_SWEEP_INTERLEAVED)
+        return fail(LLR_EINVAL, "order must be LLR_SWEEP_GROUPED or LLR_SWEEP_INTERLEAVED");
+    if (c->interleave != (order == LLR_SWEEP_INTERLEAVED)) {
+        c->interleave = order == LLR_SWEEP_INTERLEAVED;
+        drop_graphs(c);   // the captured sweeps hold the pass sequence
+    }
     return LLR_OK;
 }
 

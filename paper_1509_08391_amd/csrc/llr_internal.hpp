@@ -105,6 +105,10 @@ template <typename T> void launch_hb_pass(const LatTable& lt, T* th, DevState s,
                                           uint32_t k0, uint32_t k1, hipStream_t st);
 template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_alt,
                                           hipStream_t st);
+// heatbath pass of colour c (sweep counters) immediately followed by the
+// overrelaxation of the same class, in one launch
+template <typename T> void launch_hb_or_pass(const LatTable& lt, T* th, DevState s, int colour, int mode,
+                                             uint32_t k0, uint32_t k1, hipStream_t st);
 template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st,
                                           bool with_obs = false);
 template <typename T> void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st);

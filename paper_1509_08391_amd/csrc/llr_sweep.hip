@@ -25,6 +25,8 @@ namespace llr {
 // accepted, no counters touched; the walk kernel then decides)
 enum { kModeRestricted = 0, kModeApproach = 1, kModeFree = 2, kModeMuca = 3, kModeLink = 4,
        kModeTune = kHbModeTune, kModeLinkPre = 6 };
+// instantiations of the heatbath class pass
+enum { kHbPlain = 0, kHbPre = 1, kHbFuseOr = 2 };
 
 constexpr long long kLinkNone = (long long)0x8000000000000000ull;   // no free candidate within the cap
 
@@ -233,6 +235,26 @@ __device__ __forceinline__ void hb_new_angle(T c_, T s_, T C, T S, T R, T kap, T
     dE = M::div_(R * er, nrm) - eps_old;
 }
 
+// Overrelaxation of one link with staple sums (C, S): theta' = -2 phi - theta
+// = arg[(C - i S)^2 e^{-i theta}]; a link with vanishing staples is reflected.
+template <typename T>
+__device__ __forceinline__ T or_angle(T t, T C, T S) {
+    using M = Math<T>;
+    T t_new;
+    if (C == T(0) && S == T(0)) {
+        t_new = -t;
+    } else {
+        T so, co;
+        M::sincos_rad(t, &so, &co);
+        const T ar = fms2(C, C, S, S), ai = T(-2) * C * S;   // (C - iS)^2
+        const T zr = fma2(ar, co, ai, so);                   // times (cos - i sin)
+        const T zi = fms2(ai, co, ar, so);
+        t_new = M::atan2_(zi, zr);
+    }
+    if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
+    return t_new;
+}
+
 // ln W(E) = -ln rho~(E) of the multicanonical weight (Sec. 2.6): in interval
 // k, -ln rho~(c_k) + a_k (E - c_k); below the first and above the last
 // interval the first and last pieces continue, i.e. W = e^{a_0 E + c_1} and
@@ -261,7 +283,7 @@ __device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, d
 // paid per block, not per wavefront.  Each link still takes its first
 // accepted attempt in order.
 // ---------------------------------------------------------------------------
-template <typename T, int MU, int LPT, bool PRE>
+template <typename T, int MU, int LPT, int VAR>
 __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
                                                int kind, uint32_t k0, uint32_t k1, int reverse) {
     using M = Math<T>;
@@ -291,7 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
     const uint32_t c3 = (uint32_t)(gi - L.chain0);
     const int own = (int)((curw >> (8 * colour)) & 1ull);
-    const T* pown = chain + (size_t)(own * 8 + colour) * L.V2;
+    T* pcur = chain + (size_t)(own * 8 + colour) * L.V2;
+    const T* pown = pcur;
     T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
     const uint32_t hbase = (uint32_t)tile * NT;
 
@@ -386,8 +409,16 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         T t_new = t_old[r];
         T dE = T(0);
         if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
-        st_plane(palt, h, t_new);
-        if constexpr (PRE) {
+        if constexpr (VAR == kHbFuseOr) {
+            // the class's overrelaxation follows at once, on the same staples:
+            // of the heatbath candidate into the alternate plane, of the old
+            // angle in place; the pass's decision picks the plane
+            st_plane(palt, h, or_angle(t_new, C[r], S[r]));
+            st_plane(pcur, h, or_angle(t_old[r], C[r], S[r]));
+        } else {
+            st_plane(palt, h, t_new);
+        }
+        if constexpr (VAR == kHbPre) {
             const size_t j = (size_t)L.lbase + (size_t)cl * L.V2 + h;
             T* lc = static_cast<T*>(s.link_cst);
             s.link_d[j] = ok ? link_fixed(dE, L) : kLinkNone;
@@ -398,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         if constexpr (M::f32) fx32 += __float2int_rn(dE * 33554432.0f);
         else fx += to_fixed((double)dE, L);
     }
-    if constexpr (PRE) return;
+    if constexpr (VAR == kHbPre) return;
     if constexpr (M::f32) fx = (long long)fx32 << (L.fxb - 25);
     const long long tot = block_sum_i64(fx);
     long long total = 0;
@@ -462,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
 // arc; x comes from that truncated exponential, is kept with probability
 // exp(k (cos x - u_hi) + lam (x - x_a)), and its sign is a fair bit.
 //
-// The candidate pre-pass (k_hb<..., PRE = true>, mode kModeLinkPre) has
+// The candidate pre-pass (k_hb<..., kHbPre>, mode kModeLinkPre) has
 // written, per class link, the free heatbath candidate into the alternate
 // plane, its Delta E in the walk's fixed point, and the link's staples and
 // old angle.  That candidate is the first attempt passing the sampler test;
@@ -776,19 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
     for (int r = 0; r < LPT; ++r) {
         const uint32_t h = hbase + r * kBlock + threadIdx.x;
         if (h >= L.V2) continue;
-        T t_new;
-        if (C[r] == T(0) && S[r] == T(0)) {
-            t_new = -t_old[r];
-        } else {
-            T so, co;
-            M::sincos_rad(t_old[r], &so, &co);
-            const T ar = fms2(C[r], C[r], S[r], S[r]), ai = T(-2) * C[r] * S[r];   // (C - iS)^2
-            const T zr = fma2(ar, co, ai, so);                                       // times (cos - i sin)
-            const T zi = fms2(ai, co, ar, so);
-            t_new = M::atan2_(zi, zr);
-        }
-        if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
-        st_plane(pout, h, t_new);
+        st_plane(pout, h, or_angle(t_old[r], C[r], S[r]));
     }
 }
 
@@ -1109,29 +1128,30 @@ void launch_hot_start(const LatTable& lt, T* th, DevState s, uint32_t k0, uint32
     hipLaunchKernelGGL(k_hot_start<T>, dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, k0, k1);
 }
 
-// PRE: the candidate pre-pass of the per-link constraint, a separate
-// instantiation so that the class-wise passes carry none of its code
-template <typename T, int LPT, bool PRE>
+// VAR: kHbPlain, the candidate pre-pass of the per-link constraint (kHbPre),
+// or the pass followed by the class's overrelaxation (kHbFuseOr); separate
+// instantiations, so that the plain pass carries none of the others' code
+template <typename T, int LPT, int VAR>
 static void hb_dispatch(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0,
                         uint32_t k1, hipStream_t st) {
     const int p = colour & 1;
     const int rv = lt.serpentine ? p : 0;
     dim3 gr(lt.hb_blocks), bl(kBlock);
     switch (colour >> 1) {
-        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
-        default: hipLaunchKernelGGL((k_hb<T, 3, LPT, PRE>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 0: hipLaunchKernelGGL((k_hb<T, 0, LPT, VAR>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 1: hipLaunchKernelGGL((k_hb<T, 1, LPT, VAR>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        case 2: hipLaunchKernelGGL((k_hb<T, 2, LPT, VAR>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
+        default: hipLaunchKernelGGL((k_hb<T, 3, LPT, VAR>), gr, bl, 0, st, lt, th, s, p, mode, kind, k0, k1, rv); break;
     }
 }
 
-template <typename T, bool PRE>
+template <typename T, int VAR>
 static void hb_tiles(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
                      hipStream_t st) {
     switch (lt.hb_lpt) {
-        case 1: hb_dispatch<T, 1, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
-        case 2: hb_dispatch<T, 2, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
-        default: hb_dispatch<T, 4, PRE>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        case 1: hb_dispatch<T, 1, VAR>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        case 2: hb_dispatch<T, 2, VAR>(lt, th, s, colour, mode, kind, k0, k1, st); break;
+        default: hb_dispatch<T, 4, VAR>(lt, th, s, colour, mode, kind, k0, k1, st); break;
     }
 }
 
@@ -1139,10 +1159,10 @@ template <typename T>
 void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, int kind, uint32_t k0, uint32_t k1,
                     hipStream_t st) {
     if (mode != kModeLink) {
-        hb_tiles<T, false>(lt, th, s, colour, mode, kind, k0, k1, st);
+        hb_tiles<T, kHbPlain>(lt, th, s, colour, mode, kind, k0, k1, st);
         return;
     }
-    hb_tiles<T, true>(lt, th, s, colour, kModeLinkPre, kind, k0, k1, st);
+    hb_tiles<T, kHbPre>(lt, th, s, colour, kModeLinkPre, kind, k0, k1, st);
     const int p = colour & 1;
     dim3 gr(lt.n_chains), bl(kBlock);
     switch (colour >> 1) {
@@ -1151,6 +1171,12 @@ void launch_hb_pass(const LatTable& lt, T* th, DevState s, int colour, int mode,
         case 2: hipLaunchKernelGGL((k_link_walk<T, 2>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
         default: hipLaunchKernelGGL((k_link_walk<T, 3>), gr, bl, 0, st, lt, th, s, p, kind, k0, k1); break;
     }
+}
+
+template <typename T>
+void launch_hb_or_pass(const LatTable& lt, T* th, DevState s, int colour, int mode, uint32_t k0, uint32_t k1,
+                       hipStream_t st) {
+    hb_tiles<T, kHbFuseOr>(lt, th, s, colour, mode, kSweep, k0, k1, st);
 }
 
 template <typename T, int LPT>
@@ -1224,6 +1250,7 @@ void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32
     template void launch_hot_start<T>(const LatTable&, T*, DevState, uint32_t, uint32_t, hipStream_t);          \
     template void launch_hb_pass<T>(const LatTable&, T*, DevState, int, int, int, uint32_t, uint32_t, hipStream_t); \
     template void launch_or_pass<T>(const LatTable&, T*, DevState, int, int, hipStream_t);                           \
+    template void launch_hb_or_pass<T>(const LatTable&, T*, DevState, int, int, uint32_t, uint32_t, hipStream_t);     \
     template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t, bool);                    \
     template void launch_export<T>(const LatTable&, int, const T*, DevState, T*, hipStream_t);                 \
     template void launch_import<T>(const LatTable&, int, T*, DevState, const T*, hipStream_t);                 \

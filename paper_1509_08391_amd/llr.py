@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libllr.so")
 OK, WARN_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
 MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
+SWEEP_GROUPED, SWEEP_INTERLEAVED = 0, 1
 N_PARAMS = 4417
 
 _lib = None
@@ -64,6 +65,7 @@ _SIGS = {
     "llr_autotune": [C.c_void_p, _p(C.c_int), _p(C.c_int)],
     "llr_set_tiles": [C.c_void_p, C.c_int, C.c_int],
     "llr_set_order": [C.c_void_p, C.c_int],
+    "llr_set_sweep_order": [C.c_void_p, C.c_int],
     "llr_set_graphs": [C.c_void_p, C.c_int],
     "llr_enable_bits_log": [C.c_void_p, C.c_longlong],
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
@@ -288,6 +290,12 @@ class Context:
 
     def set_order(self, serpentine):
         _check(lib().llr_set_order(self.h, int(serpentine)))
+
+    def set_sweep_order(self, order):
+        """SWEEP_GROUPED (heatbath of every colour, then overrelaxation of
+        every colour) or SWEEP_INTERLEAVED (heatbath then overrelaxation per
+        colour, fused in one launch)."""
+        _check(lib().llr_set_sweep_order(self.h, int(order)))
 
     def set_tiles(self, hb_lpt, or_lpt):
         _check(lib().llr_set_tiles(self.h, hb_lpt, or_lpt))

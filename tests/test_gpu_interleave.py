@@ -1,0 +1,203 @@
+"""GPU parity of the interleaved sweep order (llr_set_sweep_order): per colour
+c, the heatbath pass of c and then the overrelaxation of c, fused in one
+launch that writes the overrelaxed heatbath candidate and the overrelaxed old
+angle and lets the heatbath decision pick one.
+
+  * the fused launches give, bit for bit, the state and energies of the two
+    separate passes (llr_class_pass) taken in the same order, for the
+    restricted and the free mode, FP32 and FP64, with two lattice sizes and
+    several chains in one launch and intervals narrow enough that heatbath
+    passes are rejected;
+  * FP64 sweeps against the oracle's interleaved sweeps from the same state:
+    accept bits identical, angles within 1e-12 after one sweep and 1e-6 after
+    three more (the bars of the grouped order), energies within 1e-9;
+  * Algorithm 1 in the interleaved order: a short driver run against the
+    oracle's (a_k history within 1e-7, accept bits identical), and, marked
+    slow, the full L=4 run over 16 seeds as distributions of the final a_k,
+    FP64 and FP32;
+  * the order is rejected outside {grouped, interleaved}."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.inputs import circ_dist, random_state
+from tests.test_gpu_parity import _states_in_intervals
+
+pytestmark = pytest.mark.gpu
+
+SEED = 1509083910
+
+
+@pytest.fixture(scope="module")
+def llr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1509_08391_amd import llr as m
+    m.lib()
+    return m
+
+
+def _lattices(dtype):
+    """(L, E_low, dE, states): L=4 with 4 chains and L=6 with 3, every chain
+    in a window of 16 around its own energy (heatbath passes get rejected)."""
+    d = 4
+    out = []
+    for L, n in [(4, 4), (6, 3)]:
+        th = np.concatenate([random_state(d, L, 1, seed=70 * L + k, u_target=0.5 + 0.05 * k, dtype=dtype)
+                             for k in range(n)]).astype(np.float64)
+        E = np.array([oracle.energy(d, L, th[k]) for k in range(n)])
+        o = np.argsort(E)
+        out.append((L, E[o] - 8.0, 16.0, np.ascontiguousarray(th[o])))
+    return out
+
+
+def _ctx(llr, prec, lats, a=1.0, **params):
+    import torch
+    ctx = llr.Context(precision=prec)
+    p = dict(seed=SEED)
+    p.update(params)
+    ctx.set_params(**p)
+    for L, E_low, dE, _ in lats:
+        ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    dt = np.float32 if prec == llr.FP32 else np.float64
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        ctx.set_a(i, a)
+        ctx.import_state(i, torch.from_numpy(th.astype(dt)))
+    return ctx
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+@pytest.mark.parametrize("mode", ["MODE_RESTRICTED", "MODE_FREE"])
+def test_fused_launch_equals_separate_passes(llr, prec, mode):
+    p = getattr(llr, prec)
+    m = getattr(llr, mode)
+    lats = _lattices(np.float32 if prec == "FP32" else np.float64)
+    fused = _ctx(llr, p, lats, a=1.05)
+    fused.set_sweep_order(llr.SWEEP_INTERLEAVED)
+    bits = fused.sweeps(3, sweep0=7, mode=m)
+    sep = _ctx(llr, p, lats, a=1.05)
+    for t in range(3):
+        for c in range(8):
+            sep.class_pass(1, c, mode=m, sweep_index=7 + t)
+            sep.class_pass(0, c, mode=m, sweep_index=7 + t)
+    for i in range(len(lats)):
+        assert np.array_equal(fused.export_state(i).cpu().numpy(), sep.export_state(i).cpu().numpy()), i
+        assert np.array_equal(fused.get_energy(i)[0], sep.get_energy(i)[0]), i
+    hp_f, ha_f, _, _ = fused.stats()
+    hp_s, ha_s, _, _ = sep.stats()
+    assert np.array_equal(hp_f, hp_s) and np.array_equal(ha_f, ha_s)
+    if mode == "MODE_RESTRICTED":
+        assert np.any((bits & 0xff) != 0xff)          # some heatbath passes rejected
+    assert np.all((bits >> 8) == 0xff)                # overrelaxation always accepted
+    fused.close()
+    sep.close()
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_interleaved_sweeps_match_oracle_fp64(llr, L):
+    import torch
+    d, n = 4, 3
+    th = random_state(d, L, n, seed=L * 11 + 3, u_target=0.6)
+    for k in range(n):
+        E0 = oracle.energy(d, L, th[k])
+        width = max(6.0, 0.3 * np.sqrt(6 * L ** 4))
+        lo = E0 - (0.2 + 0.25 * k) * width
+        a = 0.95 + 0.05 * k
+        ctx = llr.Context(precision=llr.FP64)
+        ctx.set_params(seed=SEED)
+        ctx.add_lattice(L, [lo], width)
+        ctx.bind_state()
+        ctx.set_a(0, a)
+        ctx.import_state(0, torch.from_numpy(th[k:k + 1].copy()))
+        ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+        tr = th[k:k + 1].copy()
+        Er = np.array([E0])
+        for (n_sw, s0, tol) in [(1, 11, 1e-12), (3, 12, 1e-6)]:
+            bits = ctx.sweeps(n_sw, sweep0=s0)
+            got = ctx.export_state(0).cpu().numpy()
+            Eg, _ = ctx.get_energy(0)
+            Er, br = oracle.sweeps(d, L, tr, [a], [lo], [lo + width], [0], Er, n_sw, s0, seed=SEED,
+                                   order=oracle.SWEEP_INTERLEAVED)
+            assert np.array_equal(bits[:, 0].astype(np.int64), br[:, 0].astype(np.int64)), (bits, br)
+            assert np.max(circ_dist(got, tr)) < tol
+            assert abs(Eg[0] - Er[0]) < 1e-9 * abs(Er[0])
+        ctx.close()
+
+
+def test_interleaved_driver_short_run_fp64(llr):
+    """N_TH = 1, N_A = 1, N_RM = 3 from states inside their intervals, replica
+    exchange after every sweep, sweeps replayed from captured graphs."""
+    import torch
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.55 * V6 + dE * np.arange(8)
+    th = _states_in_intervals(L, E_low, dE, seed=6)
+    a0 = np.linspace(0.95, 1.1, 8)
+    ctx = llr.Context(precision=llr.FP64)
+    ctx.set_params(seed=SEED, n_th=1, n_a=1, n_rm=3, recompute_every=2, replica_exchange=True)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    ctx.set_a(0, a0)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+    ctx.enable_bits_log(100)
+    ctx.import_state(0, torch.from_numpy(th))
+    ctx.run()
+    hist = ctx.get_history(0)
+    E, conf = ctx.get_energy(0)
+    bits = ctx.get_bits_log()
+    ctx.close()
+    r = oracle.llr_run(d, L, E_low, dE, a0, n_th=1, n_a=1, n_rm=3, seed=SEED, recompute_every=2,
+                       replica_exchange=True, theta=th, record_bits=True, approach_cap=0,
+                       order=oracle.SWEEP_INTERLEAVED)
+    assert np.array_equal(bits.astype(np.int64), r["bits"].astype(np.int64))
+    assert np.array_equal(conf, r["conf"])
+    assert np.max(np.abs(hist - r["a_hist"])) < 1e-7
+    assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-9
+
+
+def test_sweep_order_arguments(llr):
+    ctx = llr.Context(precision=llr.FP64)
+    with pytest.raises(llr.LLRError):
+        ctx.set_sweep_order(2)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+    ctx.set_sweep_order(llr.SWEEP_GROUPED)
+    ctx.close()
+
+
+@pytest.mark.slow
+def test_full_run_interleaved_statistical(llr):
+    """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
+    dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start) in the
+    interleaved order: final a_k over 16 seeds, GPU FP64 and FP32 against the
+    oracle's interleaved runs, means within 4 combined standard errors."""
+    L, d = 4, 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.5 * V6 + dE * np.arange(8)
+    # 16 seeds: with 4, a sample standard deviation can fall several times below
+    # the true one (measured: 0.0009 against 0.0036 over 12 seeds) and the
+    # 4-standard-error bar with it
+    seeds = [SEED + 17 * i for i in range(16)]
+    O = np.array([oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd,
+                                 approach_cap=20000, order=oracle.SWEEP_INTERLEAVED)["a"] for sd in seeds])
+    for prec in ("FP64", "FP32"):
+        G = []
+        for sd in seeds:
+            ctx = llr.Context(precision=getattr(llr, prec))
+            ctx.set_params(seed=sd, n_th=100, n_a=100, n_rm=20, approach_cap=20000)
+            ctx.add_lattice(L, E_low, dE)
+            ctx.bind_state()
+            ctx.set_a(0, 1.0)
+            ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+            ctx.hot_start()
+            ctx.approach()
+            ctx.run()
+            G.append(ctx.get_a(0)[0])
+            ctx.close()
+        G = np.array(G)
+        se = np.maximum(np.sqrt(G.var(0, ddof=1) / len(seeds) + O.var(0, ddof=1) / len(seeds)), 2e-4)
+        z = np.abs(G.mean(0) - O.mean(0)) / se
+        assert np.all(z < 4.0), (prec, z, G.mean(0) - O.mean(0))

@@ -29,7 +29,7 @@
   * Algorithm 1 with the restriction imposed per link (llr_set_restriction):
     two Robbins-Monro iterations of one sweep each, replayed from captured
     graphs, against the oracle's run from the same states (a_k, energies,
-    angles), and the full L=4 run over 4 seeds as distributions of the final
+    angles), and the full L=4 run over 8 seeds as distributions of the final
     a_k, FP64 and FP32."""
 import numpy as np
 import pytest
@@ -266,13 +266,16 @@ def test_set_restriction_arguments(llr):
 def test_full_run_per_link_statistical(llr):
     """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
     dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start) with the
-    per-link restriction: final a_k over 4 seeds, GPU FP64 and FP32 against
+    per-link restriction: final a_k over 8 seeds, GPU FP64 and FP32 against
     the oracle's per-link runs, means within 4 combined standard errors."""
     L, d = 4, 4
     V6 = 6 * L ** 4
     dE = 0.025 * V6
     E_low = 0.5 * V6 + dE * np.arange(8)
-    seeds = [SEED + 17 * i for i in range(4)]
+    # 8 seeds: with 4, a sample standard deviation can fall several times below
+    # the true one (measured: 0.0009 against 0.0036 over 12 seeds) and the
+    # 4-standard-error bar with it
+    seeds = [SEED + 17 * i for i in range(8)]
     O = np.array([oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd,
                                  approach_cap=20000, per_link=True)["a"] for sd in seeds])
     for prec in ("FP64", "FP32"):

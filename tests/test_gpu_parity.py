@@ -442,6 +442,48 @@ def test_mlp_training_matches_oracle(llr):
     assert histb[-1] < 0.1 * histb[0]
 
 
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_bind_clears_memory_before_imports(llr, prec):
+    """Memory bound with NaN in it, then two lattices imported one after the
+    other: the energy pass after the first import also covers the second
+    lattice, so binding must leave valid angles.  Both lattices' energies
+    match the oracle after the imports and stay inside their intervals
+    through restricted sweeps (a poisoned per-chain reduction would leave E
+    at a stale value and reject every heatbath pass)."""
+    import ctypes as C
+    import torch
+    d = 4
+    ctx = llr.Context(precision=getattr(llr, prec))
+    ctx.set_params(seed=SEED)
+    dt = np.float32 if prec == "FP32" else np.float64
+    lats = []
+    for L, n in [(4, 2), (6, 2)]:
+        V6 = 6 * L ** 4
+        dE = 0.03 * V6
+        E_low = 0.55 * V6 + dE * np.arange(n)
+        th = _states_in_intervals(L, E_low, dE, seed=40 + L).astype(dt)
+        lats.append((L, E_low, dE, th))
+        ctx.add_lattice(L, E_low, dE)
+    nb = C.c_size_t()
+    assert llr.lib().llr_state_bytes(ctx.h, C.byref(nb)) == 0
+    ctx.state = torch.full((nb.value // np.dtype(dt).itemsize,), float("nan"), dtype=ctx.dtype, device="cuda:0")
+    assert llr.lib().llr_bind_state(ctx.h, C.c_void_p(ctx.state.data_ptr()), nb.value) == 0
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        ctx.set_a(i, 1.0)
+        ctx.import_state(i, torch.from_numpy(th))
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        E, _ = ctx.get_energy(i)
+        Eo = np.array([oracle.energy(d, L, th[k].astype(np.float64)) for k in range(len(E_low))])
+        assert np.max(np.abs(E - Eo)) < 1e-9 * np.max(np.abs(Eo)), (i, E, Eo)
+    bits = ctx.sweeps(4, sweep0=3)
+    assert np.any(bits & 0xff)
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        E, _ = ctx.get_energy(i)
+        assert np.all((E >= E_low) & (E <= E_low + dE)), (i, E)
+    ctx.recompute_energy()
+    ctx.close()
+
+
 def test_invalid_arguments_are_rejected(llr):
     ctx = llr.Context(precision=llr.FP64)
     with pytest.raises(llr.LLRError):

@@ -12,7 +12,8 @@ to rejecting a whole colour class):
     uniform subject to sum_P theta_P = 0 (mod 2 pi) and so are sampled
     exactly, the energies visited by restricted sweeps follow
     rho(E) e^{a E} on [lo, hi], for the per-link constraint and for the
-    class-wise rejection alike;
+    class-wise rejection alike, the latter in both orders of a sweep's
+    class passes;
   * the running energy of a 4D chain stays inside its interval after every
     link and agrees with a full recomputation."""
 import numpy as np
@@ -103,21 +104,22 @@ def test_restricted_sweeps_sample_rho_e_aE_2d(lo, hi, a):
     bins = np.linspace(lo, hi, 9)
     p, _ = np.histogram(Ex[m], bins=bins, weights=np.exp(a * (Ex[m] - hi)))
     p /= p.sum()
-    for mode in (oracle.MODE_LINK, oracle.MODE_RESTRICTED):
+    for mode, order in ((oracle.MODE_LINK, oracle.SWEEP_GROUPED), (oracle.MODE_RESTRICTED, oracle.SWEEP_GROUPED),
+                        (oracle.MODE_RESTRICTED, oracle.SWEEP_INTERLEAVED)):
         th = _start_inside(d, L, lo, hi, nch, 11)
         E = np.array([oracle.energy(d, L, th[i]) for i in range(nch)])
         args = ([a] * nch, [lo] * nch, [hi] * nch, list(range(nch)))
-        E, _ = oracle.sweeps(d, L, th, *args, E, 200, 0, mode=mode, seed=4)
+        E, _ = oracle.sweeps(d, L, th, *args, E, 200, 0, mode=mode, seed=4, order=order)
         vis = []
         for k in range(6000):
-            E, _ = oracle.sweeps(d, L, th, *args, E, 2, 1000 + 2 * k, mode=mode, seed=4)
+            E, _ = oracle.sweeps(d, L, th, *args, E, 2, 1000 + 2 * k, mode=mode, seed=4, order=order)
             vis.append(E.copy())
         vis = np.ravel(vis)
         assert np.all((vis >= lo) & (vis <= hi))
         h, _ = np.histogram(vis, bins=bins)
         chi2 = np.sum((h - h.sum() * p) ** 2 / (h.sum() * p)) / (bins.size - 1)
         # consecutive samples are mildly correlated: an inflated chi2 bar
-        assert chi2 < 4.0, (mode, chi2)
+        assert chi2 < 4.0, (mode, order, chi2)
 
 
 def test_running_energy_stays_inside_4d():

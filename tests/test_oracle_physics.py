@@ -5,7 +5,8 @@
     (eqs. (kk11)-(kk12)) follows by quadrature; the full oracle LLR run
     (approach, restricted heatbath/overrelaxation, Robbins-Monro) must land
     on it, with the restriction imposed class-wise or per link;
-  * 2D canonical heatbath vs the exact <cos theta_P> = sum I_n^{N_P-1} I_n' / sum I_n^{N_P};
+  * 2D canonical heatbath vs the exact <cos theta_P> = sum I_n^{N_P-1} I_n' / sum I_n^{N_P},
+    in both orders;
   * 4D: a_k agrees with beta where the canonical <E>(beta) is the interval
     centre, away from beta_c (eq. (kk15); O(1/V) saddle-point offset, appendix);
   * restricted class moves sample rho(E) e^{aE} 1_I (tiny 2D lattice histogram)."""
@@ -38,15 +39,18 @@ def _astar(lo, hi, NP):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("per_link", [False, True])
-def test_llr_2d_matches_exact_restricted_root(per_link):
+@pytest.mark.parametrize("per_link,order", [(False, oracle.SWEEP_GROUPED), (True, oracle.SWEEP_GROUPED),
+                                            (False, oracle.SWEEP_INTERLEAVED)])
+def test_llr_2d_matches_exact_restricted_root(per_link, order):
     """Both restrictions of Sec. 2.4 (class-wise rejection and the per-link
-    constraint) drive Algorithm 1 to the same exact root."""
+    constraint), and both orders of the class passes in a sweep, drive
+    Algorithm 1 to the same exact root."""
     d, L, w = 2, 8, 8.0
     NP = L * L
     El = np.array([16.0, 22.0, 28.0])
     exact = np.array([_astar(e, e + w, NP) for e in El])
-    runs = [oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link)["a"]
+    runs = [oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link,
+                           order=order)["a"]
             for s in range(3)]
     A = np.array(runs)
     # per-seed spread measured at ~2e-3; mean of 3 seeds within 4e-3
@@ -54,7 +58,8 @@ def test_llr_2d_matches_exact_restricted_root(per_link):
     assert np.all(np.abs(A.mean(0) - exact) < 4e-3)
 
 
-def test_canonical_2d_plaquette_exact():
+@pytest.mark.parametrize("order", [oracle.SWEEP_GROUPED, oracle.SWEEP_INTERLEAVED])
+def test_canonical_2d_plaquette_exact(order):
     d, L = 2, 8
     V = L * L
     beta = 1.0
@@ -67,11 +72,11 @@ def test_canonical_2d_plaquette_exact():
     E = np.array([oracle.energy(d, L, th[i]) for i in range(nch)])
     big = [1e9] * nch
     E, _ = oracle.sweeps(d, L, th, [beta] * nch, [-1e9] * nch, big, list(range(nch)), E, 100, 0,
-                         mode=oracle.MODE_FREE, seed=5)
+                         mode=oracle.MODE_FREE, seed=5, order=order)
     samples = []
     for k in range(300):
         E, _ = oracle.sweeps(d, L, th, [beta] * nch, [-1e9] * nch, big, list(range(nch)), E, 4,
-                             1000 + 4 * k, mode=oracle.MODE_FREE, seed=5)
+                             1000 + 4 * k, mode=oracle.MODE_FREE, seed=5, order=order)
         samples.append(E / V)
     s = np.array(samples)
     err = s.mean(axis=0).std() / np.sqrt(nch)
