@@ -35,10 +35,12 @@ N_INT = 128
 SEED = 1509083910
 PEAK_HBM_GBS = 8000.0
 # Calibrated HBM bytes per heatbath launch (FETCH_SIZE x 2 + WRITE_SIZE x 1,
-# rocprofv3 on this kernel version with 4 class links per thread,
-# profiles/k_hb_L20x128_fp32_counters.md); None once the kernel changes until
-# the counters are taken again.
-HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6}
+# rocprofv3 on this kernel version with 4 class links per thread;
+# profiles/k_hb_L20x128_fp32_counters.md for the plain pass of the grouped
+# order, profiles/k_hb_or_fused_L20x128_fp32_counters.md for the fused pass of
+# the interleaved order); None once the kernel changes until the counters are
+# taken again.
+HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6, ("fp32", 4, "interleaved"): 417.0e6}
 
 
 def cpu_baseline(order, target_s=12.0):
