@@ -235,6 +235,24 @@ __device__ __forceinline__ void hb_new_angle(T c_, T s_, T C, T S, T R, T kap, T
     dE = M::div_(R * er, nrm) - eps_old;
 }
 
+// The fused pass's version of hb_new_angle: the heatbath angle is not
+// stored, only its overrelaxation -2 phi - theta' = -phi - X (mod 2 pi), i.e.
+// arg[e^{-iX} (C - i S)] (for vanishing staples, -X), so neither the heatbath
+// angle's arctangent nor its sine and cosine are needed; dE as there.
+template <typename T>
+__device__ __forceinline__ void hb_or_new_angle(T c_, T s_, T C, T S, T R, T kap, T eps_old, T& t_or, T& dE) {
+    using M = Math<T>;
+    T er = fms2(c_, c_, s_, s_), ei = T(2) * c_ * s_;
+    const T nrm = fma2(c_, c_, s_, s_);
+    if (kap < T(0)) { er = -er; ei = -ei; }
+    T pr = C, pi = -S;
+    if (R == T(0)) { pr = T(1); pi = T(0); }
+    const T zr = fma2(er, pr, ei, pi), zi = fms2(er, pi, ei, pr);   // (er - i ei)(pr + i pi)
+    t_or = M::atan2_(zi, zr);
+    if (!M::f32 && t_or >= M::pi()) t_or -= T(2) * M::pi();
+    dE = M::div_(R * er, nrm) - eps_old;
+}
+
 // Overrelaxation of one link with staple sums (C, S): theta' = -2 phi - theta
 // = arg[(C - i S)^2 e^{-i theta}]; a link with vanishing staples is reflected.
 template <typename T>
@@ -408,14 +426,17 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         }
         T t_new = t_old[r];
         T dE = T(0);
-        if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
         if constexpr (VAR == kHbFuseOr) {
             // the class's overrelaxation follows at once, on the same staples:
             // of the heatbath candidate into the alternate plane, of the old
             // angle in place; the pass's decision picks the plane
-            st_plane(palt, h, or_angle(t_new, C[r], S[r]));
-            st_plane(pcur, h, or_angle(t_old[r], C[r], S[r]));
+            const T t_or_old = or_angle(t_old[r], C[r], S[r]);
+            T t_or_new = t_or_old;
+            if (ok) hb_or_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_or_new, dE);
+            st_plane(palt, h, t_or_new);
+            st_plane(pcur, h, t_or_old);
         } else {
+            if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
             st_plane(palt, h, t_new);
         }
         if constexpr (VAR == kHbPre) {

@@ -3,11 +3,16 @@ c, the heatbath pass of c and then the overrelaxation of c, fused in one
 launch that writes the overrelaxed heatbath candidate and the overrelaxed old
 angle and lets the heatbath decision pick one.
 
-  * the fused launches give, bit for bit, the state and energies of the two
-    separate passes (llr_class_pass) taken in the same order, for the
-    restricted and the free mode, FP32 and FP64, with two lattice sizes and
-    several chains in one launch and intervals narrow enough that heatbath
-    passes are rejected;
+  * the fused launches against the two separate passes (llr_class_pass)
+    taken in the same order, for the restricted and the free mode, FP32 and
+    FP64, with two lattice sizes and several chains in one launch and
+    intervals narrow enough that heatbath passes are rejected: the same
+    acceptance decisions, energies within 1e-11 relative (FP64) and 1e-3
+    (FP32), angles within 1e-11 (FP64) and, in FP32, a median within 1e-6
+    and a maximum within 1e-3.  The fused pass computes the overrelaxed
+    heatbath angle as arg[e^{-iX}(C - iS)] = -2 phi - theta' (mod 2 pi)
+    instead of reflecting the rounded theta', so the two agree to rounding,
+    which the later passes of a sweep amplify by up to 2/R per reflection;
   * FP64 sweeps against the oracle's interleaved sweeps from the same state:
     accept bits identical, angles within 1e-12 after one sweep and 1e-6 after
     three more (the bars of the grouped order), energies within 1e-9;
@@ -83,8 +88,15 @@ def test_fused_launch_equals_separate_passes(llr, prec, mode):
             sep.class_pass(1, c, mode=m, sweep_index=7 + t)
             sep.class_pass(0, c, mode=m, sweep_index=7 + t)
     for i in range(len(lats)):
-        assert np.array_equal(fused.export_state(i).cpu().numpy(), sep.export_state(i).cpu().numpy()), i
-        assert np.array_equal(fused.get_energy(i)[0], sep.get_energy(i)[0]), i
+        dist = circ_dist(fused.export_state(i).cpu().numpy().astype(np.float64),
+                         sep.export_state(i).cpu().numpy().astype(np.float64))
+        Ef, Es = fused.get_energy(i)[0], sep.get_energy(i)[0]
+        if prec == "FP64":
+            assert np.max(dist) < 1e-11, (i, np.max(dist))
+            assert np.max(np.abs(Ef - Es) / np.abs(Es)) < 1e-11, (i, Ef - Es)
+        else:
+            assert np.median(dist) < 1e-6 and np.max(dist) < 1e-3, (i, np.median(dist), np.max(dist))
+            assert np.max(np.abs(Ef - Es)) < 1e-3, (i, Ef - Es)
     hp_f, ha_f, _, _ = fused.stats()
     hp_s, ha_s, _, _ = sep.stats()
     assert np.array_equal(hp_f, hp_s) and np.array_equal(ha_f, ha_s)
