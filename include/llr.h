@@ -219,7 +219,9 @@ llr_status llr_link_stats(llr_ctx *ctx, long long *redrawn, long long *arc);
  * heatbath and of the overrelaxation pass.  llr_autotune
  * times the choices on the bound, initialised state without changing it and
  * keeps the fastest per kernel (llr_rm_begin calls it if no choice was made);
- * llr_set_tiles fixes them.  Results are bit-identical for every choice. */
+ * in the interleaved sweep order the heatbath tile is timed on the fused
+ * heatbath + overrelaxation pass.  llr_set_tiles fixes them.  Results are
+ * bit-identical for every choice. */
 llr_status llr_autotune(llr_ctx *ctx, int *hb_lpt, int *or_lpt);
 llr_status llr_set_tiles(llr_ctx *ctx, int hb_lpt, int or_lpt);
 /* Block order of the class passes: serpentine != 0 (default) walks the chains

@@ -387,9 +387,16 @@ static llr_status autotune_impl(llr_ctx* c) {
         set_tiles(c->lt, cand[ci], cand[ci]);
         for (int rep = 0; rep < 4; ++rep) {   // first repetition warms up; minimum of the others
             HIPCHK(hipEventRecord(e0, c->stream));
-            for (int col = 0; col < 8; ++col)
-                launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, kHbModeTune, kSweep, (uint32_t)c->prm.seed,
-                                  (uint32_t)(c->prm.seed >> 32), c->stream);
+            // the heatbath pass the sweeps run: fused with the overrelaxation
+            // in the interleaved order
+            for (int col = 0; col < 8; ++col) {
+                if (c->interleave)
+                    launch_hb_or_pass<T>(c->lt, (T*)c->state, c->ds, col, kHbModeTune, (uint32_t)c->prm.seed,
+                                         (uint32_t)(c->prm.seed >> 32), c->stream);
+                else
+                    launch_hb_pass<T>(c->lt, (T*)c->state, c->ds, col, kHbModeTune, kSweep, (uint32_t)c->prm.seed,
+                                      (uint32_t)(c->prm.seed >> 32), c->stream);
+            }
             HIPCHK(hipEventRecord(e1, c->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;

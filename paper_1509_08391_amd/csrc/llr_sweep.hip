@@ -333,6 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     const int own = (int)((curw >> (8 * colour)) & 1ull);
     T* pcur = chain + (size_t)(own * 8 + colour) * L.V2;
     const T* pown = pcur;
+    // the fused pass's in-place store; a tuner's timing launch leaves the
+    // state as it is and writes both angles into the non-current plane
+    T* pinpl = mode == kModeTune ? chain + (size_t)((own ^ 1) * 8 + colour) * L.V2 : pcur;
     T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
     const uint32_t hbase = (uint32_t)tile * NT;
 
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             T t_or_new = t_or_old;
             if (ok) hb_or_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_or_new, dE);
             st_plane(palt, h, t_or_new);
-            st_plane(pcur, h, t_or_old);
+            st_plane(pinpl, h, t_or_old);
         } else {
             if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
             st_plane(palt, h, t_new);

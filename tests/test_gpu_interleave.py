@@ -20,6 +20,8 @@ angle and lets the heatbath decision pick one.
     oracle's (a_k history within 1e-7, accept bits identical), and, marked
     slow, the full L=4 run over 16 seeds as distributions of the final a_k,
     FP64 and FP32;
+  * the tuner times the fused pass without changing the state, and every tile
+    choice of the fused pass gives bit-identical sweeps;
   * the order is rejected outside {grouped, interleaved}."""
 import numpy as np
 import pytest
@@ -168,6 +170,35 @@ def test_interleaved_driver_short_run_fp64(llr):
     assert np.array_equal(conf, r["conf"])
     assert np.max(np.abs(hist - r["a_hist"])) < 1e-7
     assert np.max(np.abs(E - r["E"]) / np.abs(r["E"])) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_interleaved_autotune_and_tiles(llr, prec):
+    """The tuner times the fused pass without changing the state, and every
+    tile choice of the fused pass gives bit-identical sweeps."""
+    p = getattr(llr, prec)
+    lats = _lattices(np.float32 if prec == "FP32" else np.float64)
+    ctx = _ctx(llr, p, lats, a=1.05)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+    before = [ctx.export_state(i).cpu().numpy() for i in range(len(lats))]
+    E_before = [ctx.get_energy(i)[0] for i in range(len(lats))]
+    tiles = ctx.autotune()
+    assert tiles[0] in (1, 2, 4) and tiles[1] in (1, 2, 4)
+    for i in range(len(lats)):
+        assert np.array_equal(ctx.export_state(i).cpu().numpy(), before[i])
+        assert np.array_equal(ctx.get_energy(i)[0], E_before[i])
+    ctx.close()
+    out = []
+    for lpt in (1, 2, 4):
+        c = _ctx(llr, p, lats, a=1.05)
+        c.set_sweep_order(llr.SWEEP_INTERLEAVED)
+        c.set_tiles(lpt, 2)
+        c.sweeps(2, sweep0=4)
+        out.append([(c.export_state(i).cpu().numpy(), c.get_energy(i)[0]) for i in range(len(lats))])
+        c.close()
+    for o in out[1:]:
+        for (s0, e0), (s1, e1) in zip(out[0], o):
+            assert np.array_equal(s0, s1) and np.array_equal(e0, e1)
 
 
 def test_sweep_order_arguments(llr):
