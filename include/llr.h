@@ -172,7 +172,9 @@ llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
  *     the two, so both run in one launch that writes the overrelaxed heatbath
  *     candidate and the overrelaxed old angle; the restricted decision of the
  *     heatbath picks one (overrelaxation leaves E unchanged).  The result is
- *     that of the two separate passes in this order, bit for bit.
+ *     that of the two separate passes in this order up to rounding: the
+ *     overrelaxed heatbath angle is computed as arg[e^{-iX}(C - iS)] rather
+ *     than by reflecting the rounded heatbath angle.
  * Applies to the restricted, free and multicanonical sweeps of llr_run /
  * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run;
  * sweeps with the per-link restriction and approach-mode sweeps stay grouped.
