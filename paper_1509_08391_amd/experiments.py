@@ -53,6 +53,14 @@
            under --inputs, else a_k = 1.011 ~ beta_c(20) throughout).
   linkprof 60 sweeps per mode of the L = 20 set only, for a kernel trace.
 
+  ordercmp the two orders of a sweep's class passes (grouped, and
+           interleaved with fused launches) on the lattices and a_k of
+           linkcmp, 8000 sweeps each: mean E per interval against a second
+           grouped run with other random numbers.
+
+  --order  grouped (default) or interleaved: the sweep order of the
+           Algorithm 1 runs of every configuration.
+
   batchprof the config2 lattice set (L = 12, 16, 20, 64 intervals each, one
            launch per class pass for all three), FP32, replica exchange,
            a_k = 1: hot start, approach, autotune, then 200 restricted sweeps
@@ -83,6 +91,8 @@ import numpy as np
 from . import llr
 
 SEED = 1509083910
+# order of the class passes in the sweeps of _run (command-line --order)
+SWEEP_ORDER = llr.SWEEP_GROUPED
 
 
 def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None, eps=1e-4):
@@ -90,6 +100,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
     ctx = llr.Context(precision=prec, device=0)
     ctx.set_params(n_th=n_th, n_a=n_a, n_rm=n_rm, seed=seed, replica_exchange=replica, overlap=1.0,
                    recompute_every=10, eps=eps, approach_cap=20000)
+    ctx.set_sweep_order(SWEEP_ORDER)
     for (L, E_low, dE) in lattices:
         ctx.add_lattice(L, E_low, dE)
     ctx.bind_state()
@@ -127,6 +138,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
     nsw = n_th + n_a
     upd = sum(2 * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lattices) * nsw * n_rm
     meta = dict(precision="fp32" if prec == llr.FP32 else "fp64", n_th=n_th, n_a=n_a, n_rm=n_rm, replica=replica,
+                sweep_order="interleaved" if SWEEP_ORDER == llr.SWEEP_INTERLEAVED else "grouped",
                 seed=seed, seconds_approach=t_ap, seconds_rm=t_rm, updates_per_s=upd / t_rm, tiles=list(tiles),
                 hb_acceptance=float(ha.sum() / max(hp.sum(), 1)),
                 re_acceptance=float(ra / max(rp, 1)) if replica else None)
@@ -470,7 +482,15 @@ def _tau_int(x, c=6.0):
     return tau
 
 
-def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed):
+def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed, runs=None, pairs=None):
+    """runs: (name, mode, first sweep index, sweep order) of each sampler;
+    pairs: the runs whose mean energies are compared."""
+    if runs is None:
+        runs = (("class", llr.MODE_RESTRICTED, 1 << 22, llr.SWEEP_GROUPED),
+                ("class2", llr.MODE_RESTRICTED, 1 << 23, llr.SWEEP_GROUPED),
+                ("link", llr.MODE_LINK, 1 << 22, llr.SWEEP_GROUPED))
+    if pairs is None:
+        pairs = (("class", "class2"), ("class", "link"), ("class2", "link"))
     ctx = llr.Context(precision=llr.FP32, device=0)
     ctx.set_params(seed=seed, replica_exchange=False, recompute_every=10, approach_cap=20000)
     ctx.add_lattice(L, E_low, dE)
@@ -485,8 +505,8 @@ def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed):
     out = {}
     # class2: the class-wise mode again with other random numbers (other sweep
     # indices), the reference for how far two runs of one ensemble differ
-    for name, mode, s0 in (("class", llr.MODE_RESTRICTED, 1 << 22), ("class2", llr.MODE_RESTRICTED, 1 << 23),
-                           ("link", llr.MODE_LINK, 1 << 22)):
+    for name, mode, s0, order in runs:
+        ctx.set_sweep_order(order)
         ctx.import_state(0, start)
         ctx.sweeps(5, sweep0=1 << 21, mode=mode, want_bits=False)          # warm-up (first use allocates)
         t0 = time.perf_counter()
@@ -523,7 +543,7 @@ def _link_lattice(log, L, E_low, dE, a, n_meas, n_time, seed):
     ctx.close()
     # both modes sample the same restricted ensemble: compare the means, and
     # two class-wise runs with each other for the spread one ensemble shows
-    for a_, b_ in (("class", "class2"), ("class", "link"), ("class2", "link")):
+    for a_, b_ in pairs:
         z = (np.array(out[a_]["E_mean"]) - np.array(out[b_]["E_mean"])) / np.hypot(
             out[a_]["E_err_batch"], out[b_]["E_err_batch"])
         out[f"mean_difference_{a_}_{b_}"] = dict(chi2_per_interval=float(np.mean(z ** 2)),
@@ -543,6 +563,25 @@ def link_compare(log, a20, n_meas8=8000, n_meas20=4000):
     rec = dict(L8=_link_lattice(log, L, E_low, dE, res[0]["a"], n_meas8, 500, SEED + 17))
     L, E_low, dE = config4_intervals()
     rec["L20"] = _link_lattice(log, L, E_low, dE, a20, n_meas20, 200, SEED + 19)
+    return rec
+
+
+def order_compare(log, a20, n_meas8=8000, n_meas20=8000):
+    """The two orders of a sweep's class passes (grouped; interleaved, fused
+    launches) at fixed a_k: mean E per interval against a second grouped run
+    with other random numbers, which gives the spread of one ensemble."""
+    runs = (("grouped", llr.MODE_RESTRICTED, 1 << 22, llr.SWEEP_GROUPED),
+            ("grouped2", llr.MODE_RESTRICTED, 1 << 23, llr.SWEEP_GROUPED),
+            ("interleaved", llr.MODE_RESTRICTED, 1 << 22, llr.SWEEP_INTERLEAVED))
+    pairs = (("grouped", "grouped2"), ("grouped", "interleaved"), ("grouped2", "interleaved"))
+    L = 8
+    V6 = 6 * L ** 4
+    dE = 0.005 * V6
+    E_low = 0.55 * V6 + dE * np.arange(32)
+    res, _ = _run([(L, E_low, dE)], llr.FP32, 200, 500, 20, False, log=log)
+    rec = dict(L8=_link_lattice(log, L, E_low, dE, res[0]["a"], n_meas8, 500, SEED + 23, runs, pairs))
+    L, E_low, dE = config4_intervals()
+    rec["L20"] = _link_lattice(log, L, E_low, dE, a20, n_meas20, 200, SEED + 29, runs, pairs)
     return rec
 
 
@@ -665,14 +704,18 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
                                             "dE8", "obs8",
-                                            "config4b", "linkcmp", "linkprof", "fss", "batchprof"])
+                                            "config4b", "linkcmp", "linkprof", "fss", "batchprof", "ordercmp"])
     ap.add_argument("--out", default="experiment_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
                     "(config3 reads config1 and config2, config4 reads config3); default --out")
     ap.add_argument("--n-rm", type=int, default=None)
     ap.add_argument("--part", type=int, default=0)
     ap.add_argument("--combine", action="store_true")
+    ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped",
+                    help="order of the class passes in the sweeps of the Algorithm 1 runs")
     args = ap.parse_args()
+    global SWEEP_ORDER
+    SWEEP_ORDER = llr.SWEEP_INTERLEAVED if args.order == "interleaved" else llr.SWEEP_GROUPED
     os.makedirs(args.out, exist_ok=True)
 
     def log(msg):
@@ -712,11 +755,16 @@ def main():
         rec = fss_combine(log, recs("fss_part*.json"), recs("config4b_part*.json"))
     elif args.which == "fss":
         rec = fss_part(log, load("config3"), args.part)
-    elif args.which in ("linkcmp", "linkprof"):
+    elif args.which in ("linkcmp", "linkprof", "ordercmp"):
         # converged L=20 a_k when a config4b record is given, else beta_c(20) throughout
         src = os.path.join(args.inputs or args.out, "config4b_part0.json")
         a20 = load("config4b_part0")["runs"][0]["a"] if os.path.exists(src) else [1.011] * 128
-        rec = link_compare(log, a20) if args.which == "linkcmp" else link_profile(log, a20)
+        if args.which == "linkcmp":
+            rec = link_compare(log, a20)
+        elif args.which == "ordercmp":
+            rec = order_compare(log, a20)
+        else:
+            rec = link_profile(log, a20)
     elif args.which == "config4b" and args.combine:
         import glob
         parts = []
