@@ -33,8 +33,11 @@ def _states(L, n, seed):
     return th, E
 
 
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
 @pytest.mark.parametrize("L", [4, 6])
-def test_muca_sweeps_match_oracle_fp64(llr, L):
+def test_muca_sweeps_match_oracle_fp64(llr, L, order):
+    """Multicanonical sweeps against the oracle's, in both orders of the
+    class passes (the interleaved one runs the fused launches)."""
     import torch
     d, n = 4, 12
     V6 = 6 * L ** 4
@@ -51,8 +54,10 @@ def test_muca_sweeps_match_oracle_fp64(llr, L):
     ctx.bind_state()
     ctx.set_a(0, a)
     ctx.import_state(0, torch.from_numpy(th))
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
     ctx.muca_begin([b])
     oracle.set_muca(cen, a, dE)
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
     tr = th.copy()
     Er = E.copy()
     acc = 0
@@ -67,7 +72,7 @@ def test_muca_sweeps_match_oracle_fp64(llr, L):
         got = ctx.export_state(0).cpu().numpy()
         for t in range(n_sw):
             Er, br = oracle.sweeps(d, L, tr, [b] * n, E_low, E_low + dE, np.arange(n), Er, 1, s0 + t,
-                                   mode=oracle.MODE_MUCA, seed=SEED)
+                                   mode=oracle.MODE_MUCA, seed=SEED, order=o_order)
             acc += sum(bin(int(x) & 0xff).count("1") for x in br[0])
             assert np.max(np.abs(Eg[t] - Er) / np.abs(Er)) < 1e-9, (s0, t)
         dist = circ_dist(got, tr)

@@ -46,15 +46,19 @@ def _setup(llr, L, n, replica):
     return ctx, th, E, E_low, dE, a
 
 
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
 @pytest.mark.parametrize("L", [4, 6])
-def test_observables_match_oracle_fp64(llr, L):
+def test_observables_match_oracle_fp64(llr, L, order):
     d, n = 4, 5
     ctx, th, E, E_low, dE, a = _setup(llr, L, n, replica=False)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
     Eg, Bg = ctx.observables(2, 1, 7)
     ctx.close()
     tr, Er = th.copy(), E.copy()
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
     for m in range(2):
-        Er, _ = oracle.sweeps(d, L, tr, a, E_low, E_low + dE, np.arange(n), Er, 1, 7 + m, seed=SEED)
+        Er, _ = oracle.sweeps(d, L, tr, a, E_low, E_low + dE, np.arange(n), Er, 1, 7 + m, seed=SEED,
+                              order=o_order)
         Eo = np.array([oracle.energy(d, L, tr[k]) for k in range(n)])
         Bo = np.array([oracle.adjoint(d, L, tr[k]) for k in range(n)])
         assert np.max(np.abs(Eg[m] - Eo) / np.abs(Eo)) < 1e-9
