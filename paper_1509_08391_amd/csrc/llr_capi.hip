@@ -325,7 +325,8 @@ static llr_status ensure_link_buffers(llr_ctx* c);
 static int restricted_mode(const llr_ctx* c) { return c->per_link ? LLR_MODE_LINK : LLR_MODE_RESTRICTED; }
 
 // One restricted sweep of the Robbins-Monro loop.  Without per-kernel timing
-// the 18-20 launches of a sweep are captured once per variant into a HIP graph
+// the 18-20 launches of a sweep (10-12 in the interleaved order) are captured
+// once per variant into a HIP graph
 // (kernel nodes only) and replayed; the sweep index lives in device memory, so
 // every replay advances it.
 template <typename T>
