@@ -613,6 +613,7 @@ def batch_profile(log, n=200):
         lats.append((L, 0.58 * V6 + dE * np.arange(64), dE))
     ctx = llr.Context(precision=llr.FP32, device=0)
     ctx.set_params(seed=SEED, replica_exchange=True, recompute_every=10, approach_cap=20000)
+    ctx.set_sweep_order(SWEEP_ORDER)
     for (L, E_low, dE) in lats:
         ctx.add_lattice(L, E_low, dE)
     ctx.bind_state()
@@ -629,7 +630,8 @@ def batch_profile(log, n=200):
     ctx.close()
     log(f"{dt * 1e3:.3f} ms per sweep of 192 chains (L = 12, 16, 20), {upd / dt:.4g} link updates/s, "
         f"tiles {tiles}, approach sweeps {[int(x) for x in ap]}")
-    return dict(ms_per_sweep=dt * 1e3, updates_per_s=upd / dt, tiles=list(tiles), approach_sweeps=list(map(int, ap)))
+    return dict(ms_per_sweep=dt * 1e3, updates_per_s=upd / dt, tiles=list(tiles), approach_sweeps=list(map(int, ap)),
+                sweep_order="interleaved" if SWEEP_ORDER == llr.SWEEP_INTERLEAVED else "grouped")
 
 
 FSS_PARTS = {0: (8, 10, 12, 14), 1: (16, 18)}
