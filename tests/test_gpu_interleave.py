@@ -22,6 +22,9 @@ angle and lets the heatbath decision pick one.
     FP64 and FP32;
   * the tuner times the fused pass without changing the state, and every tile
     choice of the fused pass gives bit-identical sweeps;
+  * switching the order or the restriction between Robbins-Monro iterations
+    drops the captured sweep graphs: graph replays equal eager launches bit
+    for bit across the switches;
   * the order is rejected outside {grouped, interleaved}."""
 import numpy as np
 import pytest
@@ -199,6 +202,45 @@ def test_interleaved_autotune_and_tiles(llr, prec):
     for o in out[1:]:
         for (s0, e0), (s1, e1) in zip(out[0], o):
             assert np.array_equal(s0, s1) and np.array_equal(e0, e1)
+
+
+@pytest.mark.parametrize("switch", ["order", "restriction"])
+def test_mid_run_switch_recaptures_graphs(llr, switch):
+    """Robbins-Monro iterations replayed from captured graphs, with the sweep
+    order (or the restriction) switched between iterations, against the same
+    iterations launched eagerly: a graph captured before the switch must not
+    be replayed after it."""
+    import torch
+    L = 4
+    V6 = 6 * L ** 4
+    dE = 0.025 * V6
+    E_low = 0.55 * V6 + dE * np.arange(6)
+    th = _states_in_intervals(L, E_low, dE, seed=8)
+    out = []
+    for graphs in (True, False):
+        ctx = llr.Context(precision=llr.FP64)
+        ctx.set_params(seed=SEED, n_th=1, n_a=2, n_rm=3, recompute_every=2, replica_exchange=True)
+        ctx.add_lattice(L, E_low, dE)
+        ctx.bind_state()
+        ctx.set_a(0, 1.0)
+        ctx.import_state(0, torch.from_numpy(th))
+        ctx.set_graphs(graphs)
+        ctx.rm_begin()
+        ctx.rm_step(1)
+        if switch == "order":
+            ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+        else:
+            ctx.set_restriction(True)
+        ctx.rm_step(1)
+        if switch == "order":
+            ctx.set_sweep_order(llr.SWEEP_GROUPED)
+        else:
+            ctx.set_restriction(False)
+        ctx.rm_step(1)
+        out.append((ctx.get_history(0), ctx.export_state(0).cpu().numpy(), ctx.get_energy(0)[0]))
+        ctx.close()
+    (h0, s0, e0), (h1, s1, e1) = out
+    assert np.array_equal(h0, h1) and np.array_equal(s0, s1) and np.array_equal(e0, e1)
 
 
 def test_sweep_order_arguments(llr):
