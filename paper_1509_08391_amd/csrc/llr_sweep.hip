@@ -255,15 +255,14 @@ __device__ __forceinline__ void hb_or_new_angle(T c_, T s_, T C, T S, T R, T kap
 
 // Overrelaxation of one link with staple sums (C, S): theta' = -2 phi - theta
 // = arg[(C - i S)^2 e^{-i theta}]; a link with vanishing staples is reflected.
+// (so, co) = (sin, cos) theta, as sincos_rad gives them.
 template <typename T>
-__device__ __forceinline__ T or_angle(T t, T C, T S) {
+__device__ __forceinline__ T or_angle_sc(T t, T so, T co, T C, T S) {
     using M = Math<T>;
     T t_new;
     if (C == T(0) && S == T(0)) {
         t_new = -t;
     } else {
-        T so, co;
-        M::sincos_rad(t, &so, &co);
         const T ar = fms2(C, C, S, S), ai = T(-2) * C * S;   // (C - iS)^2
         const T zr = fma2(ar, co, ai, so);                   // times (cos - i sin)
         const T zi = fms2(ai, co, ar, so);
@@ -271,6 +270,13 @@ __device__ __forceinline__ T or_angle(T t, T C, T S) {
     }
     if (!M::f32 && t_new >= M::pi()) t_new -= T(2) * M::pi();
     return t_new;
+}
+
+template <typename T>
+__device__ __forceinline__ T or_angle(T t, T C, T S) {
+    T so, co;
+    Math<T>::sincos_rad(t, &so, &co);
+    return or_angle_sc(t, so, co, C, S);
 }
 
 // ln W(E) = -ln rho~(E) of the multicanonical weight (Sec. 2.6): in interval
@@ -353,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     }
     if (tid == 0) s_qn[0] = 0;
     T eps_old[LPT], R[LPT], kap[LPT], ch[LPT], sh[LPT];
+    T t_or_old[LPT];   // fused pass: the old angle's overrelaxation, from the sine and cosine at hand
     bool got[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
@@ -360,10 +367,12 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         const int e = r * kBlock + tid;
         got[r] = true;
         ch[r] = T(1); sh[r] = T(0); eps_old[r] = T(0); R[r] = T(0); kap[r] = T(0);
+        t_or_old[r] = T(0);
         if (h < L.V2) {
             T so, co;
             M::sincos_rad(t_old[r], &so, &co);
             eps_old[r] = fms2(C[r], co, S[r], so);
+            if constexpr (VAR == kHbFuseOr) t_or_old[r] = or_angle_sc(t_old[r], so, co, C[r], S[r]);
             R[r] = M::sqrt_(fma2(C[r], C[r], S[r], S[r]));
             kap[r] = (T)acoup * R[r];
             const T ak = kap[r] < T(0) ? -kap[r] : kap[r];
@@ -433,11 +442,10 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
             // the class's overrelaxation follows at once, on the same staples:
             // of the heatbath candidate into the alternate plane, of the old
             // angle in place; the pass's decision picks the plane
-            const T t_or_old = or_angle(t_old[r], C[r], S[r]);
-            T t_or_new = t_or_old;
+            T t_or_new = t_or_old[r];
             if (ok) hb_or_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_or_new, dE);
             st_plane(palt, h, t_or_new);
-            st_plane(pinpl, h, t_or_old);
+            st_plane(pinpl, h, t_or_old[r]);
         } else {
             if (ok) hb_new_angle(c_, s_, C[r], S[r], R[r], kap[r], eps_old[r], t_new, dE);
             st_plane(palt, h, t_new);
