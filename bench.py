@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # order, profiles/k_hb_or_fused_L20x128_fp32_counters.md for the fused pass of
 # the interleaved order); None once the kernel changes until the counters are
 # taken again.
-HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6}
+HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6, ("fp32", 4, "interleaved"): 408.0e6}
 
 
 def cpu_baseline(order, target_s=12.0):
