@@ -160,10 +160,10 @@ def test_one_sweep_fp64_batched_chains_and_lattices(llr):
         col += n
 
 
-def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep):
-    """One FP32-state sweep of one chain by the oracle, pass by pass, returning
-    the set of links whose result is ill-conditioned (sampler margin < 1e-5 or
-    small staple modulus) together with the links sharing a plaquette later."""
+def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWEEP_GROUPED):
+    """One FP32-state sweep of one chain by the oracle, pass by pass (in the
+    given order of the class passes), returning the set of links whose
+    sampler test had a margin below 1e-5."""
     V = L ** d
     flagged = np.zeros((d, V), dtype=bool)
     par = np.array([sum((s // L ** m) % L for m in range(d)) % 2 for s in range(V)])
@@ -173,12 +173,15 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep):
         mu, p = col >> 1, col & 1
         idx = np.nonzero(par == p)[0]
         flagged[mu, idx[mg < 1e-5]] = True
-    for col in range(2 * d):
-        oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
+        if order == oracle.SWEEP_INTERLEAVED:
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
+    if order == oracle.SWEEP_GROUPED:
+        for col in range(2 * d):
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
     return E, flagged
 
 
-def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4):
+def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GROUPED):
     """Per-link linear response of one oracle sweep (FP64): the factor by which
     a 1e-9 random perturbation of the input state is amplified at each output
     link, RMS over n_dir independent perturbations (one random direction alone
@@ -187,17 +190,18 @@ def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4):
     through the same propagation, so this is the link's conditioning."""
     rng = np.random.default_rng(0)
     base = np.ascontiguousarray(th_k[None].copy())
-    oracle.sweeps(d, L, base, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED)
+    oracle.sweeps(d, L, base, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED, order=order)
     acc = np.zeros(th_k.shape)
     for _ in range(n_dir):
         t = np.ascontiguousarray(th_k[None] + rng.normal(0.0, 1e-9, th_k.shape)[None])
-        oracle.sweeps(d, L, t, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED)
+        oracle.sweeps(d, L, t, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED, order=order)
         acc += (circ_dist(base[0], t[0]) / 1e-9) ** 2
     return np.sqrt(acc / n_dir)
 
 
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
 @pytest.mark.parametrize("L", [4, 8])
-def test_one_sweep_fp32_against_fp64_oracle(llr, L):
+def test_one_sweep_fp32_against_fp64_oracle(llr, L, order):
     """One FP32 sweep against the oracle's sweep of the same FP32 state (FP64
     arithmetic, FP32-rounded stored angles, the same 23-bit uniforms).  Each
     pass of the FP32 kernel is within ~1e-6 of the oracle's on the same input
@@ -208,8 +212,11 @@ def test_one_sweep_fp32_against_fp64_oracle(llr, L):
     1e-5 wherever the sweep amplifies by at most 10 (~99 % of links), and
     fewer than 2 % of links above that.  In a chain with a link whose sampler
     test the oracle flags (margin < 1e-5: FP32 may take another attempt),
-    fewer than 1 % of links may exceed the bar."""
+    fewer than 1 % of links may exceed the bar.  In both orders of the class
+    passes (the interleaved one runs the fused launches, whose overrelaxed
+    heatbath angle is computed from the unrounded candidate)."""
     import torch
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
     d, n = 4, 3
     th = random_state(d, L, n, seed=L + 100, u_target=0.6, dtype=np.float32).astype(np.float64)
     n_flag_total = 0
@@ -219,12 +226,13 @@ def test_one_sweep_fp32_against_fp64_oracle(llr, L):
         lo = E0 - 0.45 * width
         ctx = _ctx(llr, llr.FP32, [(L, [lo], width)], a=np.array([1.0]))
         ctx.import_state(0, torch.from_numpy(th[k:k + 1].astype(np.float32)))
+        ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
         bits = ctx.sweeps(1, sweep0=5)
         got = ctx.export_state(0).cpu().numpy().astype(np.float64)
         Eg, _ = ctx.get_energy(0)
-        amp = _amplification(d, L, th[k], lo, lo + width, E0, 5)
+        amp = _amplification(d, L, th[k], lo, lo + width, E0, 5, order=o_order)
         tr = th[k].copy()
-        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, 1.0, lo, lo + width, E0, 5)
+        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, 1.0, lo, lo + width, E0, 5, order=o_order)
         dist = circ_dist(got[0], tr)
         n_flag_total += int(flagged.sum())
         bar = 1e-6 * np.maximum(amp, 10.0)
