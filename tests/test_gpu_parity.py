@@ -590,7 +590,8 @@ def _full_size_states(dtype):
 _SAMPLE = np.array([0, 1, 63, 64, 126, 127])
 
 
-def test_full_size_one_sweep_sampled_chains_fp64(llr):
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     """The benchmark's shape and launch configuration (128 chains of L = 20 in
     one lattice, 640 000 links each; heatbath tiles of 4 and overrelaxation
     tiles of 2 class links per thread; serpentine block order), in FP64: one
@@ -601,13 +602,16 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr):
     L <= 10.  A link whose staple modulus R is small amplifies the ulp-level
     differences of the two sides' sin, cos and atan2 by ~1/R in
     phi = arg(C + iS); with P(R < r) ~ r^2 the largest amplification over N
-    links grows like sqrt(N), about 1e3 here, and measured maxima are ~2e-12.)"""
+    links grows like sqrt(N), about 1e3 here, and measured maxima are ~2e-12.)
+    In both orders of the class passes; the interleaved one, the benchmark's,
+    runs the fused launches."""
     import torch
     d, L = 4, 20
     th, E, E_low, dE, a = _full_size_states(np.float64)
     ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a])
     ctx.set_tiles(4, 2)
     ctx.set_order(True)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
     ctx.import_state(0, torch.from_numpy(th))
     bits = ctx.sweeps(1, sweep0=7)
     got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy()
@@ -615,11 +619,11 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr):
     ctx.close()
     tr = np.ascontiguousarray(th[_SAMPLE])
     Er, br = oracle.sweeps(d, L, tr, a[_SAMPLE], E_low[_SAMPLE], E_low[_SAMPLE] + dE, _SAMPLE, E[_SAMPLE], 1, 7,
-                           seed=SEED)
+                           seed=SEED, order=oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED)
     n_acc = int(sum(bin(int(b) & 0xff).count("1") for b in br[0]))
     assert 0 < n_acc < 8 * _SAMPLE.size          # both outcomes of the interval test occur
     dist = circ_dist(got, tr)
-    print(f"\nL=20 x 128 FP64 sweep, 6 sampled chains: max angle difference {dist.max():.2e}, "
+    print(f"\nL=20 x 128 FP64 sweep ({order}), 6 sampled chains: max angle difference {dist.max():.2e}, "
           f"links above 1e-12: {int(np.sum(dist > 1e-12))} of {dist.size}")
     assert np.mean(dist <= 1e-12) >= 0.99999
     assert dist.max() < 1e-10
