@@ -112,7 +112,7 @@ def test_fused_launch_equals_separate_passes(llr, prec, mode):
     sep.close()
 
 
-@pytest.mark.parametrize("L", [4, 6])
+@pytest.mark.parametrize("L", [2, 4, 6, 10])
 def test_interleaved_sweeps_match_oracle_fp64(llr, L):
     import torch
     d, n = 4, 3
