@@ -35,14 +35,25 @@ SWEEP_GROUPED, SWEEP_INTERLEAVED = 0, 1
 N_PARAMS = 4417
 
 
+_GCC = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
-        subprocess.check_call(cmd)
+        subprocess.check_call(_GCC + [_SRC, "-o", _LIB_PATH + ".tmp", "-lm"])
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
+
+
+def build_variant(path: str, defines) -> "C.CDLL":
+    """A copy of the oracle compiled with extra preprocessor macros (the pins'
+    planted mistakes, e.g. OR_PLANT_RE_SIGN) at `path`; wrappers take it as
+    their `use` argument."""
+    subprocess.check_call(_GCC + [f"-D{m}" for m in defines] + [_SRC, "-o", path, "-lm"])
+    v = C.CDLL(path)
+    _declare(v)
+    return v
 
 
 _lib = None
@@ -100,6 +111,9 @@ def _declare(L):
     L.or_class_pass.restype = i
     L.or_sweeps.argtypes = [i, i, i, _p(d), _p(d), _p(d), _p(d), _p(i), _p(d), i, u32, i, i, i,
                             u64, i, i, _p(i)]
+    L.or_replica_step.argtypes = [i, _p(i), _p(i), _p(d), _p(d), _p(d), _p(d), u64, i, u32, _p(C.c_longlong)]
+    L.or_replica_run.argtypes = [i, i, i, _p(d), _p(d), _p(d), _p(d), _p(d), _p(i), _p(i), i, u32, u64, i, i,
+                                 _p(d), _p(C.c_longlong)]
     L.or_llr_run.argtypes = [C.POINTER(RunParams), _p(d), C.POINTER(RunOut)]
     L.or_llr_run.restype = i
     L.or_rm_step.argtypes = [d, d, d, i, d]
@@ -229,16 +243,17 @@ def class_pass(d, L, theta, hb, colour, mode, a, lo, hi, E, seed, kind=KIND_SWEE
 
 
 def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_RESTRICTED,
-           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False, order=SWEEP_GROUPED):
+           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False, order=SWEEP_GROUPED, use=None):
     """n_sweeps sweeps of every chain of theta (n_chains, d, V), in place.  Returns bits.
-    order (with do_or): SWEEP_GROUPED or SWEEP_INTERLEAVED."""
+    order (with do_or): SWEEP_GROUPED or SWEEP_INTERLEAVED.  use: a library
+    from build_variant instead of the oracle's own."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous
     nch = theta.shape[0]
     a, lo, hi = _f64(a), _f64(lo), _f64(hi)
     itv = np.ascontiguousarray(interval, dtype=np.int32)
     Earr = np.ascontiguousarray(E, dtype=np.float64).copy()
     bits = np.zeros((n_sweeps, nch), dtype=np.int32)
-    lib().or_sweeps(d, L, nch, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
+    (use or lib()).or_sweeps(d, L, nch, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
                     _ptr(hi, C.c_double), _ptr(itv, C.c_int), _ptr(Earr, C.c_double), n_sweeps,
                     sweep0, mode, kind, (2 if order == SWEEP_INTERLEAVED else 1) if do_or else 0, seed,
                     lattice_id, int(f32), _ptr(bits, C.c_int))
@@ -285,6 +300,42 @@ def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=
     if record_bits:
         res["bits"] = bits[: int(ap[0]) + n_rm * (n_th + n_a)]
     return res
+
+
+def replica_step(conf, itv, E, a, lo, hi, seed, t, lattice_id=0, re_acc=None, use=None):
+    """Replica exchange after sweep t (Sec. 2.5) on n intervals: conf
+    (interval -> chain) and itv (chain -> interval), int32 arrays, are updated
+    in place; E per chain; a, lo, hi per interval; re_acc (int64[2], optional)
+    accumulates [proposed, accepted]."""
+    for x in (conf, itv):
+        assert x.dtype == np.int32 and x.flags.c_contiguous
+    E, a, lo, hi = _f64(E), _f64(a), _f64(lo), _f64(hi)
+    if re_acc is not None:
+        assert re_acc.dtype == np.int64
+    (use or lib()).or_replica_step(a.size, _ptr(conf, C.c_int), _ptr(itv, C.c_int), _ptr(E, C.c_double),
+                                   _ptr(a, C.c_double), _ptr(lo, C.c_double), _ptr(hi, C.c_double), seed,
+                                   lattice_id, t, _ptr(re_acc, C.c_longlong))
+
+
+def replica_run(d, L, theta, a, lo, hi, E, conf, itv, n_sweeps, sweep0, seed, lattice_id=0,
+                order=SWEEP_GROUPED, re_acc=None, use=None):
+    """n_sweeps of (restricted sweep of every chain at the coupling of the
+    interval it serves, then replica_step) at fixed a.  theta (n, d, V), E,
+    conf, itv are updated in place.  Returns the energies visited by each
+    interval after every exchange, (n_sweeps, n)."""
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    for x in (conf, itv):
+        assert x.dtype == np.int32 and x.flags.c_contiguous
+    assert E.dtype == np.float64 and E.flags.c_contiguous
+    a, lo, hi = _f64(a), _f64(lo), _f64(hi)
+    n = a.size
+    vis = np.empty((n_sweeps, n))
+    (use or lib()).or_replica_run(d, L, n, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
+                                  _ptr(hi, C.c_double), _ptr(E, C.c_double), _ptr(conf, C.c_int),
+                                  _ptr(itv, C.c_int), n_sweeps, sweep0, seed, lattice_id,
+                                  1 if order == SWEEP_INTERLEAVED else 0, _ptr(vis, C.c_double),
+                                  _ptr(re_acc, C.c_longlong))
+    return vis
 
 
 def rm_step(a, mean, centre, n, w):

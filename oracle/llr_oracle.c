@@ -715,8 +715,11 @@ void or_link_pass(int d, int L, double *theta, int colour, double a, double lo, 
 /* One restricted sweep of one chain.  do_or 0: heatbath over all 2d colours;
  * 1: then overrelaxation over all 2d colours (grouped order); 2: heatbath and
  * overrelaxation of colour 0, then of colour 1, ... (interleaved order).
- * Algorithm 1 asks only for one sweep of the whole system: either order gives
- * every link one heatbath and one overrelaxation update.  bits receives the
+ * Algorithm 1 asks only for one sweep of the whole system.  In the
+ * interleaved order the overrelaxation of colour c reflects, on unchanged
+ * staples, the heatbath draw just made: -2 phi - (X - phi) = -X - phi, again
+ * a von Mises draw, so an accepted heatbath class followed by its
+ * overrelaxation is one update of those links, not two.  bits receives the
  * accept bit of each pass (bit c: heatbath colour c, bit 2d + c:
  * overrelaxation colour c). */
 static int sweep_chain(const geo_t *g, double *th, double *scr, int mode, double a, double lo,
@@ -795,6 +798,87 @@ typedef struct {
     double *sumE_hist;      /* optional: n_rm x n measured means */
     long long *re_acc;      /* optional: replica exchange [proposed, accepted] */
 } or_run_out;
+
+/* Replica exchange after sweep t (Sec. 2.5): the pairs of neighbouring
+ * intervals (k, k+1) with k = t (mod 2).  A pair is eligible when each
+ * configuration lies inside the other's interval, so that the swapped state
+ * has non-zero restricted weight.  In the beta-convention the joint weight of
+ * the chains is prod_k rho(E_k) exp(a_k E_k) 1[E_k in I_k]; exchanging the
+ * configurations of intervals k and k+1 multiplies it by
+ * exp[(a_k - a_{k+1}) (E_{k+1} - E_k)] (the paper prints the exponent for its
+ * exp(-aS) weights), which is the Metropolis ratio of the swap.  The
+ * configurations stay where they are: conf (interval -> chain) and itv
+ * (chain -> interval) are exchanged.  Uniform: first word of Philox at
+ * counter (k, kind 3 << 12 | lattice << 16, t, 0).
+ *
+ * OR_PLANT_RE_SIGN (test builds only) plants the mistake of taking the
+ * printed exponent literally in this convention, exp[(a_k - a_{k+1})(E_k -
+ * E_{k+1})]; the replica-exchange pin must detect it. */
+static void replica_step(int n, int *conf, int *itv, const double *E, const double *a, const double *lo,
+                         const double *hi, const uint32_t key[2], int lattice_id, uint32_t t,
+                         long long *re_acc)
+{
+    for (int k = (int)(t & 1u); k + 1 < n; k += 2) {
+        int A = conf[k], B = conf[k + 1];
+        double EA = E[A], EB = E[B];
+        if (!(EA >= lo[k + 1] && EA <= hi[k + 1] && EB >= lo[k] && EB <= hi[k])) continue;
+        uint32_t ctr[4] = {(uint32_t)k, ctr1_word(0, 0, KIND_REPLICA, lattice_id), t, 0u};
+        uint32_t w[4];
+        or_philox(ctr, key, w);
+        double u = uni01(w[0], 0);
+#ifdef OR_PLANT_RE_SIGN
+        double x = (a[k] - a[k + 1]) * (EA - EB);
+#else
+        double x = (a[k] - a[k + 1]) * (EB - EA);
+#endif
+        if (re_acc) re_acc[0]++;
+        if (x >= 0.0 || u < exp(x)) {
+            conf[k] = B; conf[k + 1] = A;
+            itv[A] = k + 1; itv[B] = k;
+            if (re_acc) re_acc[1]++;
+        }
+    }
+}
+
+/* Exported replica-exchange step for the pins: n intervals with coupling
+ * a[k] and restriction [lo[k], hi[k]]; conf/itv/E per interval and chain as
+ * in the driver; re_acc (optional) accumulates [proposed, accepted]. */
+void or_replica_step(int n, int *conf, int *itv, const double *E, const double *a, const double *lo,
+                     const double *hi, uint64_t seed, int lattice_id, uint32_t t, long long *re_acc)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    replica_step(n, conf, itv, E, a, lo, hi, key, lattice_id, t, re_acc);
+}
+
+/* Exported for the replica-exchange pins: n chains at fixed couplings, one
+ * per interval, n_sweeps times a restricted sweep of every chain (at the
+ * coupling, restriction and counter word 3 of the interval it serves; sweep
+ * index sweep0 + t) followed by replica_step.  E, conf, itv in/out; E_vis
+ * (optional, n_sweeps x n) receives the energy of the chain serving each
+ * interval after the exchange.  Chains run one after another (tiny lattices). */
+void or_replica_run(int d, int L, int n, double *theta, const double *a, const double *lo, const double *hi,
+                    double *E, int *conf, int *itv, int n_sweeps, uint32_t sweep0, uint64_t seed,
+                    int lattice_id, int order, double *E_vis, long long *re_acc)
+{
+    geo_t g;
+    if (geo_init(&g, d, L)) return;
+    long nl = (long)d * g.V;
+    double *scr = (double *)malloc(sizeof(double) * (g.V / 2 + 1));
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int t = 0; t < n_sweeps; ++t) {
+        uint32_t sw = sweep0 + (uint32_t)t;
+        for (int c = 0; c < n; ++c) {
+            int k = itv[c];
+            pass_ctx_t pc = {{key[0], key[1]}, KIND_SWEEP, lattice_id, sw, (uint32_t)k, 0};
+            sweep_chain(&g, theta + c * nl, scr, 0, a[k], lo[k], hi[k], &E[c], &pc, order == 1 ? 2 : 1);
+        }
+        replica_step(n, conf, itv, E, a, lo, hi, key, lattice_id, sw, re_acc);
+        if (E_vis)
+            for (int k = 0; k < n; ++k) E_vis[(long)t * n + k] = E[conf[k]];
+    }
+    free(scr);
+    geo_free(&g);
+}
 
 /* Robbins-Monro step, eq. (kk21) with Algorithm 1's sign (beta-convention):
  * a^(n+1) = a^(n) - 12 (mean - centre) / ((n + 1) w^2), n = 0, 1, ... */
@@ -919,27 +1003,8 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                 if (recompute) o->E[c] = energy(&g, o->theta + c * nl);
                 free(scr);
             }
-            if (p->replica_exchange) {
-                /* pairs (k, k+1) with k = t mod 2 (mod 2); Sec. 2.5 swap
-                 * probability in the beta-convention:
-                 * min(1, exp[(a_k - a_{k+1}) (E_{k+1} - E_k)]) */
-                for (int k = (int)(t_glob & 1u); k + 1 < n; k += 2) {
-                    int A = conf[k], B = conf[k + 1];
-                    double EA = o->E[A], EB = o->E[B];
-                    if (!(EA >= lo[k + 1] && EA <= hi[k + 1] && EB >= lo[k] && EB <= hi[k])) continue;
-                    uint32_t ctr[4] = {(uint32_t)k, ctr1_word(0, 0, KIND_REPLICA, p->lattice_id), t_glob, 0u};
-                    uint32_t w[4];
-                    or_philox(ctr, key, w);
-                    double u = uni01(w[0], 0);
-                    double x = (o->a[k] - o->a[k + 1]) * (EB - EA);
-                    if (o->re_acc) o->re_acc[0]++;
-                    if (x >= 0.0 || u < exp(x)) {
-                        conf[k] = B; conf[k + 1] = A;
-                        itv[A] = k + 1; itv[B] = k;
-                        if (o->re_acc) o->re_acc[1]++;
-                    }
-                }
-            }
+            if (p->replica_exchange)
+                replica_step(n, conf, itv, o->E, o->a, lo, hi, key, p->lattice_id, t_glob, o->re_acc);
             if (j >= p->n_th)
                 for (int k = 0; k < n; ++k) sumE[k] += o->E[conf[k]];
         }

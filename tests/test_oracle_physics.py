@@ -39,20 +39,33 @@ def _astar(lo, hi, NP):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("per_link,order", [(False, oracle.SWEEP_GROUPED), (True, oracle.SWEEP_GROUPED),
-                                            (False, oracle.SWEEP_INTERLEAVED)])
-def test_llr_2d_matches_exact_restricted_root(per_link, order):
+@pytest.mark.parametrize("per_link,order,replica", [(False, oracle.SWEEP_GROUPED, False),
+                                                    (True, oracle.SWEEP_GROUPED, False),
+                                                    (False, oracle.SWEEP_INTERLEAVED, False),
+                                                    (False, oracle.SWEEP_GROUPED, True)])
+def test_llr_2d_matches_exact_restricted_root(per_link, order, replica):
     """Both restrictions of Sec. 2.4 (class-wise rejection and the per-link
-    constraint), and both orders of the class passes in a sweep, drive
-    Algorithm 1 to the same exact root."""
+    constraint), both orders of the class passes in a sweep, and replica
+    exchange between overlapping intervals (Sec. 2.5) drive Algorithm 1 to
+    the same exact root."""
     d, L, w = 2, 8, 8.0
     NP = L * L
-    El = np.array([16.0, 22.0, 28.0])
-    exact = np.array([_astar(e, e + w, NP) for e in El])
-    runs = [oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link,
-                           order=order)["a"]
-            for s in range(3)]
-    A = np.array(runs)
+    if replica:
+        # centres 4 apart, restriction width w = 2 dE = 8: neighbours overlap by half
+        dE = 4.0
+        El = np.array([18.0, 22.0, 26.0, 30.0])
+    else:
+        dE = w
+        El = np.array([16.0, 22.0, 28.0])
+    cen = El + 0.5 * dE
+    exact = np.array([_astar(c - 0.5 * w, c + 0.5 * w, NP) for c in cen])
+    res = [oracle.llr_run(d, L, El, dE, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link,
+                          order=order, replica_exchange=replica, w=w)
+           for s in range(3)]
+    A = np.array([r["a"] for r in res])
+    if replica:
+        re = np.sum([r["re"] for r in res], axis=0)
+        assert re[0] > 1000 and 0.05 < re[1] / re[0] < 0.99, re
     # per-seed spread measured at ~2e-3; mean of 3 seeds within 4e-3
     assert np.all(np.abs(A - exact) < 1.2e-2)
     assert np.all(np.abs(A.mean(0) - exact) < 4e-3)
