@@ -1,6 +1,5 @@
 """The oracle's two orders of a sweep's class passes (Algorithm 1 asks for
-one sweep of the whole system; every link gets one heatbath and one
-overrelaxation update in either) are the compositions of single class passes
+one sweep of the whole system) are the compositions of single class passes
 they are defined as: grouped = heatbath of colours 0..2d-1, then
 overrelaxation of colours 0..2d-1; interleaved = heatbath then
 overrelaxation of colour 0, then of colour 1, ...  Angles and energies are
@@ -42,3 +41,44 @@ def test_sweep_orders_are_their_pass_compositions(d, L, mode):
         assert E_sw[0] == E_cp, order
         out[order] = t_sw[0]
     assert not np.array_equal(out[oracle.SWEEP_GROUPED], out[oracle.SWEEP_INTERLEAVED])
+
+
+def test_overrelaxation_right_after_the_heatbath_of_its_class_is_a_relabelled_draw():
+    """In the interleaved order the overrelaxation of colour c follows the
+    heatbath of colour c on the same staples (links of one colour share no
+    plaquette).  The heatbath writes theta' = X - phi with X ~ vM(a R); the
+    reflection then gives -2 phi - theta' = -X - phi.  Since the von Mises
+    law is symmetric, that is one more heatbath draw, not a second update:
+    an accepted heatbath class followed by its overrelaxation counts as one
+    update, a rejected one as the overrelaxation of the old angles.  Checked
+    link by link (the staples unchanged by the pass, the identity to
+    rounding) and in law (probability integral transforms of -X through each
+    link's von Mises CDF are uniform)."""
+    from scipy import stats
+
+    d, L, a = 4, 4, 1.1
+    V = L ** d
+    pit = []
+    for rep in range(6):
+        th = random_state(d, L, 1, seed=40 + rep, u_target=0.62)[0]
+        for col in range(2 * d):
+            mu, p = col >> 1, col & 1
+            sites = [s for s in range(V) if sum((s // L ** m) % L for m in range(d)) % 2 == p]
+            CS = np.array([oracle.local_field(d, L, th, mu, s) for s in sites])
+            phi = np.arctan2(CS[:, 1], CS[:, 0])
+            kap = a * np.hypot(CS[:, 0], CS[:, 1])
+            E = oracle.energy(d, L, th)
+            acc, E, _, _ = oracle.class_pass(d, L, th, 1, col, oracle.MODE_FREE, a, -1e9, 1e9, E, SEED,
+                                             sweep=100 + rep, interval=col)
+            assert acc
+            CS2 = np.array([oracle.local_field(d, L, th, mu, s) for s in sites])
+            assert np.array_equal(CS, CS2)          # the class's own staples are untouched
+            X = np.angle(np.exp(1j * (th[mu, sites] + phi)))
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_FREE, a, -1e9, 1e9, E, SEED, sweep=100 + rep,
+                              interval=col)
+            Xo = np.angle(np.exp(1j * (th[mu, sites] + phi)))
+            dist = np.abs(np.angle(np.exp(1j * (Xo + X))))
+            assert dist.max() < 1e-12, dist.max()   # -2 phi - (X - phi) = -X - phi
+            pit.append(stats.vonmises.cdf(Xo, kap))
+    pit = np.concatenate(pit)
+    assert stats.kstest(pit, "uniform").pvalue > 1e-3
