@@ -99,7 +99,13 @@ llr_status llr_set_params(llr_ctx *ctx, const llr_params *p);
  * dE > 0 the spacing (Algorithm 1: E_k = E_min + k dE).  Interval k has centre
  * c_k = E_k + dE/2 and restriction [c_k - w/2, c_k + w/2] with w = dE, or
  * (1 + overlap) dE under replica exchange.  lattice_id receives 0, 1, ...
- * At most 8 lattices.  Must precede llr_bind_state. */
+ * At most 8 lattices.  Must precede llr_bind_state.  Edges that are not
+ * evenly spaced (|E_k - E_0 - k dE| > 1e-9 max(|E_0 + k dE|, dE)) are
+ * accepted by the sweeps and the replica exchange, which test each chain
+ * against its own interval (the test hooks centre one interval on each
+ * chain), but the calls that rely on Algorithm 1's spacing refuse them with
+ * LLR_EINVAL: llr_get_ln_rho (trapezium rule on spacing dE) and
+ * llr_muca_begin (the weight's interval lookup floor((E - E_0)/dE)). */
 llr_status llr_add_lattice(llr_ctx *ctx, int L, int n_intervals, const double *E_low, double dE,
                            int *lattice_id);
 
@@ -163,10 +169,10 @@ llr_status llr_rm_step(llr_ctx *ctx, int iterations);
  * null context or another value. */
 llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
 /* Order of the class passes within one sweep (Algorithm 1 fixes only that a
- * sweep evolves the whole system once; each link gets one heatbath and one
- * overrelaxation update either way):
+ * sweep evolves the whole system once):
  *   LLR_SWEEP_GROUPED (default): heatbath of colours 0..7, then
- *     overrelaxation of colours 0..7;
+ *     overrelaxation of colours 0..7; every pass updates every link of its
+ *     class (2 x 4V link updates per sweep);
  *   LLR_SWEEP_INTERLEAVED: for c = 0..7, heatbath of colour c, then the
  *     overrelaxation of colour c.  The class's staples do not change between
  *     the two, so both run in one launch that writes the overrelaxed heatbath
@@ -174,7 +180,11 @@ llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
  *     heatbath picks one (overrelaxation leaves E unchanged).  The result is
  *     that of the two separate passes in this order up to rounding: the
  *     overrelaxed heatbath angle is computed as arg[e^{-iX}(C - iS)] rather
- *     than by reflecting the rounded heatbath angle.
+ *     than by reflecting the rounded heatbath angle.  Reflecting a fresh
+ *     heatbath draw X on the same staples gives -X - phi, itself a von Mises
+ *     draw: an accepted class gets one update per link, not two, and a
+ *     rejected class one overrelaxation of its old angles (with the rejected
+ *     proposal, (2 - acceptance) updates per class link).
  * Applies to the restricted, free and multicanonical sweeps of llr_run /
  * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run;
  * sweeps with the per-link restriction and approach-mode sweeps stay grouped.
@@ -191,6 +201,48 @@ llr_status llr_get_energy(llr_ctx *ctx, int lattice_id, double *E, int *conf);
 /* ln rho at the centres (trapezium recursion, eq. (kk3a)), from the current a
  * (host, n_intervals each). */
 llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double *ln_rho);
+
+/* --- checkpoints -------------------------------------------------------- */
+
+/* Save / resume the state of Algorithm 1 between calls (the iteration over
+ * RM steps n, the sweeps within them and the approach are all resumable):
+ *   - the lattice set (L, n_intervals, dE, E_k) and the parameters;
+ *   - every angle of the bound state (both planes of each colour) and the
+ *     current-plane bits;
+ *   - per chain: E, the interval it serves, the approach couplings, the
+ *     heatbath acceptance counts;
+ *   - per interval: a_k, the chain serving it (replica exchange moves
+ *     labels, not configurations), the running sum of measured energies of
+ *     the open RM iteration, the convergence record and a^(n) so far;
+ *   - the sweep and approach counter words, the RM iteration n, the
+ *     replica-exchange counts, the sweep order, restriction and tiles.
+ * A multicanonical weight (llr_muca_begin) is saved with its flag; the bits
+ * log and the per-kernel timing are not saved.
+ * File layout (little endian): "LLRCKPT1", u32 version 1, u32 precision,
+ * u32 number of lattices, per lattice i32 L, i32 n, f64 dE, f64 E_low[n];
+ * the llr_params fields in declaration order (i32, i32, i32, u64, i32, f64,
+ * i32, f64, i32); tagged sections (u32 tag, u64 bytes, data); the CRC-32
+ * (IEEE 802.3, as zlib's crc32) of all preceding bytes.
+ * llr_checkpoint writes `path` (through `path`.tmp and a rename); the
+ * context must have a bound state.  LLR_EINVAL if the file cannot be
+ * written.
+ * llr_restore loads `path` into a context created with the same precision
+ * and the same lattice set (llr_add_lattice calls with identical L, edges and
+ * dE) whose state is bound; it replaces the parameters by the saved ones.
+ * The next llr_rm_step / llr_approach_continue / llr_sweeps continues exactly
+ * as the saved context would have (same random counters).  LLR_EINVAL, with
+ * nothing written to the device, if the file is missing, truncated,
+ * corrupted (CRC mismatch), of another version, or of another precision or
+ * lattice set.
+ * llr_checkpoint_info reads and validates a file on the host alone (no
+ * device needed): precision, number of lattices, and per lattice L,
+ * n_intervals and dE (host arrays of at least 8), E_low (host, the sum of
+ * n_intervals, lattice after lattice; may be NULL) and the parameters (may be
+ * NULL).  Same errors as llr_restore's file checks. */
+llr_status llr_checkpoint(llr_ctx *ctx, const char *path);
+llr_status llr_restore(llr_ctx *ctx, const char *path);
+llr_status llr_checkpoint_info(const char *path, int *precision, int *n_lattices, int *L, int *n_intervals,
+                               double *dE, double *E_low, llr_params *params);
 
 /* --- test and measurement hooks ----------------------------------------- */
 

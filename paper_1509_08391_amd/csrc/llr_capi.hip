@@ -35,9 +35,21 @@ struct HostLat {
     int L;
     int n;
     double dE;
+    bool even;             // E_low[k] = E_low[0] + k dE (Algorithm 1's interval set)
     std::vector<double> E_low;
     std::vector<double> a0;
 };
+
+// The calls that rely on Algorithm 1's evenly spaced interval set (ln rho by
+// the trapezium rule on spacing dE, the multicanonical weight's interval
+// lookup floor((E - E_0)/dE)) refuse a lattice whose edges deviate from it.
+static bool evenly_spaced(const double* E_low, int n, double dE) {
+    for (int k = 1; k < n; ++k) {
+        const double want = E_low[0] + (double)k * dE;
+        if (!(std::fabs(E_low[k] - want) <= 1e-9 * std::max(std::fabs(want), dE))) return false;
+    }
+    return true;
+}
 
 struct TimingPair {
     hipEvent_t a, b;
@@ -493,6 +505,14 @@ static llr_status approach_impl(llr_ctx* c, long long* sweeps) {
 
 template <typename T> static llr_status autotune_impl(llr_ctx* c);
 
+static llr_status need_even(const llr_ctx* c, const char* what) {
+    for (size_t i = 0; i < c->lats.size(); ++i)
+        if (!c->lats[i].even)
+            return fail(LLR_EINVAL, std::string(what) + " needs evenly spaced interval edges E_k = E_0 + k dE (lattice " +
+                                        std::to_string(i) + ")");
+    return LLR_OK;
+}
+
 static llr_status rm_begin(llr_ctx* c) {
     if (!c->tuned) {
         llr_status st0 = c->precision == LLR_FP32 ? autotune_impl<float>(c) : autotune_impl<double>(c);
@@ -700,6 +720,7 @@ llr_status llr_add_lattice(llr_ctx* c, int L, int n_intervals, const double* E_l
     h.L = L;
     h.n = n_intervals;
     h.dE = dE;
+    h.even = evenly_spaced(E_low, n_intervals, dE);
     h.E_low.assign(E_low, E_low + n_intervals);
     h.a0.assign(n_intervals, 1.0);
     c->lats.push_back(h);
@@ -1004,6 +1025,7 @@ llr_status llr_get_energy(llr_ctx* c, int lat, double* E, int* conf) {
 llr_status llr_get_ln_rho(llr_ctx* c, int lat, double* centres, double* ln_rho) {
     if (!c || !c->laid_out) return fail(LLR_ESTATE, "no state");
     if (lat < 0 || lat >= c->lt.n || !ln_rho) return fail(LLR_EINVAL, "bad argument");
+    if (!c->lats[lat].even) return fail(LLR_EINVAL, "ln rho needs evenly spaced interval edges E_k = E_0 + k dE");
     HIPCHK(hipSetDevice(c->device));
     const HostLat& h = c->lats[lat];
     const int n = h.n;
@@ -1244,6 +1266,7 @@ llr_status llr_muca_begin(llr_ctx* c, const double* b) {
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (!b) return fail(LLR_EINVAL, "null coupling array");
+    if ((st = need_even(c, "the multicanonical weight")) != LLR_OK) return st;
     for (int i = 0; i < c->lt.n; ++i)
         if (!std::isfinite(b[i]) || b[i] < 0) return fail(LLR_EINVAL, "proposal couplings must be finite and >= 0");
     HIPCHK(hipSetDevice(c->device));
@@ -1553,6 +1576,355 @@ llr_status llr_mlp_train(llr_ctx* c, float* w, const float* u, const float* invL
     if (loss_hist && epochs > 0) HIPCHK(hipMemcpyAsync(loss_hist, dloss, 8 * (size_t)epochs, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
+    return LLR_OK;
+}
+
+}  // extern "C"
+
+// ================================================================= checkpoints
+// A checkpoint holds the whole state of Algorithm 1 between two calls: the
+// lattice set (L, n, dE, E_k), the parameters, every angle (both planes of
+// every colour, as bound), the current-plane bits, per chain E, the interval
+// it serves, the approach couplings and the acceptance counters, per interval
+// a_k, the chain serving it, the running sum of measured energies, the
+// convergence record and the history a^(n), and the counters (sweep and
+// approach indices, Robbins-Monro iteration, replica-exchange counts).
+//
+// File layout (little endian): the 8 bytes "LLRCKPT1"; u32 version (1); u32
+// precision; u32 number of lattices; per lattice i32 L, i32 n, f64 dE,
+// f64 E_low[n]; the parameters as listed in llr_params (i32 n_th, n_a, n_rm,
+// u64 seed, i32 replica_exchange, f64 overlap, i32 recompute_every, f64 eps,
+// i32 approach_cap); then named sections, each u32 tag, u64 byte count,
+// bytes; last the u32 CRC-32 (IEEE 802.3 polynomial, reflected 0xEDB88320,
+// initial and final xor 0xFFFFFFFF) of everything before it.
+namespace {
+
+const char kCkMagic[8] = {'L', 'L', 'R', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkVersion = 1;
+
+uint32_t crc32_update(uint32_t crc, const unsigned char* p, size_t n) {
+    static uint32_t table[256];
+    static bool init = false;
+    if (!init) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            table[i] = c;
+        }
+        init = true;
+    }
+    crc = ~crc;
+    for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xffu] ^ (crc >> 8);
+    return ~crc;
+}
+
+// Sections of the file, in the order they are written.
+enum CkTag : uint32_t {
+    kTagState = 1, kTagCur, kTagE, kTagItv, kTagB, kTagEta, kTagSprev, kTagHbProp, kTagHbAcc, kTagA, kTagConf,
+    kTagSumE, kTagConvIter, kTagConvSweeps, kTagAHist, kTagLinkFix, kTagLinkArc, kTagLatDone, kTagMuLnRho, kTagMuB,
+    kTagScalars, kTagHost
+};
+
+struct CkWriter {
+    std::vector<unsigned char> buf;
+    void put(const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        buf.insert(buf.end(), c, c + n);
+    }
+    template <typename V> void val(V v) { put(&v, sizeof(V)); }
+};
+
+struct CkReader {
+    const unsigned char* p;
+    size_t n, off = 0;
+    bool get(void* dst, size_t k) {
+        if (k > n - off) return false;
+        memcpy(dst, p + off, k);
+        off += k;
+        return true;
+    }
+    template <typename V> bool val(V* v) { return get(v, sizeof(V)); }
+};
+
+struct CkLattice {
+    int L, n;
+    double dE;
+    std::vector<double> E_low;
+};
+
+struct CkHeader {
+    uint32_t precision = 0;
+    std::vector<CkLattice> lats;
+    llr_params prm{};
+    size_t body = 0;   // offset of the first section
+};
+
+// Reads the whole file, checks magic, version, size and CRC, and parses the
+// header.  Host only.
+llr_status ck_load(const char* path, std::vector<unsigned char>& data, CkHeader& h) {
+    if (!path) return fail(LLR_EINVAL, "null path");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(LLR_EINVAL, std::string("cannot open checkpoint ") + path);
+    data.clear();
+    unsigned char tmp[1 << 16];
+    size_t got;
+    while ((got = fread(tmp, 1, sizeof(tmp), f)) > 0) data.insert(data.end(), tmp, tmp + got);
+    fclose(f);
+    if (data.size() < sizeof(kCkMagic) + 4 + 4 || memcmp(data.data(), kCkMagic, sizeof(kCkMagic)) != 0)
+        return fail(LLR_EINVAL, "not an LLR checkpoint (magic)");
+    uint32_t crc_file;
+    memcpy(&crc_file, data.data() + data.size() - 4, 4);
+    if (crc32_update(0, data.data(), data.size() - 4) != crc_file)
+        return fail(LLR_EINVAL, "checkpoint corrupted or truncated (CRC-32 mismatch)");
+    CkReader r{data.data(), data.size() - 4};
+    r.off = sizeof(kCkMagic);
+    uint32_t ver = 0, nl = 0;
+    if (!r.val(&ver) || ver != kCkVersion) return fail(LLR_EINVAL, "unsupported checkpoint version");
+    if (!r.val(&h.precision) || (h.precision != LLR_FP64 && h.precision != LLR_FP32))
+        return fail(LLR_EINVAL, "bad precision in checkpoint");
+    if (!r.val(&nl) || nl < 1 || nl > (uint32_t)kMaxLat) return fail(LLR_EINVAL, "bad lattice count in checkpoint");
+    h.lats.assign(nl, CkLattice{});
+    for (auto& l : h.lats) {
+        if (!r.val(&l.L) || !r.val(&l.n) || !r.val(&l.dE)) return fail(LLR_EINVAL, "checkpoint header truncated");
+        if (l.L < 2 || l.L > 32 || (l.L & 1) || l.n < 1 || l.n > 4096 || !(l.dE > 0))
+            return fail(LLR_EINVAL, "bad lattice in checkpoint");
+        l.E_low.resize(l.n);
+        if (!r.get(l.E_low.data(), 8 * (size_t)l.n)) return fail(LLR_EINVAL, "checkpoint header truncated");
+    }
+    llr_params& p = h.prm;
+    if (!r.val(&p.n_th) || !r.val(&p.n_a) || !r.val(&p.n_rm) || !r.val(&p.seed) || !r.val(&p.replica_exchange) ||
+        !r.val(&p.overlap) || !r.val(&p.recompute_every) || !r.val(&p.eps) || !r.val(&p.approach_cap))
+        return fail(LLR_EINVAL, "checkpoint header truncated");
+    h.body = r.off;
+    return LLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+llr_status llr_checkpoint_info(const char* path, int* precision, int* n_lattices, int* L, int* n_intervals,
+                               double* dE, double* E_low, llr_params* params) {
+    std::vector<unsigned char> data;
+    CkHeader h;
+    llr_status st = ck_load(path, data, h);
+    if (st != LLR_OK) return st;
+    if (precision) *precision = (int)h.precision;
+    if (n_lattices) *n_lattices = (int)h.lats.size();
+    size_t off = 0;
+    for (size_t i = 0; i < h.lats.size(); ++i) {
+        if (L) L[i] = h.lats[i].L;
+        if (n_intervals) n_intervals[i] = h.lats[i].n;
+        if (dE) dE[i] = h.lats[i].dE;
+        if (E_low) memcpy(E_low + off, h.lats[i].E_low.data(), 8 * (size_t)h.lats[i].n);
+        off += (size_t)h.lats[i].n;
+    }
+    if (params) *params = h.prm;
+    return LLR_OK;
+}
+
+llr_status llr_checkpoint(llr_ctx* c, const char* path) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    if (!path) return fail(LLR_EINVAL, "null path");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = c->lt.n_chains;
+    const DevState& s = c->ds;
+    CkWriter w;
+    w.put(kCkMagic, sizeof(kCkMagic));
+    w.val(kCkVersion);
+    w.val((uint32_t)c->precision);
+    w.val((uint32_t)c->lats.size());
+    for (const auto& hl : c->lats) {
+        w.val(hl.L);
+        w.val(hl.n);
+        w.val(hl.dE);
+        w.put(hl.E_low.data(), 8 * (size_t)hl.n);
+    }
+    const llr_params& p = c->prm;
+    w.val(p.n_th); w.val(p.n_a); w.val(p.n_rm); w.val(p.seed); w.val(p.replica_exchange); w.val(p.overlap);
+    w.val(p.recompute_every); w.val(p.eps); w.val(p.approach_cap);
+    auto dev = [&](uint32_t tag, const void* d, size_t bytes) -> llr_status {
+        w.val(tag);
+        w.val((uint64_t)bytes);
+        const size_t at = w.buf.size();
+        w.buf.resize(at + bytes);
+        if (bytes) HIPCHK(hipMemcpy(w.buf.data() + at, d, bytes, hipMemcpyDeviceToHost));
+        return LLR_OK;
+    };
+#define CKD(tag, ptr, bytes) \
+    if ((st = dev(tag, ptr, bytes)) != LLR_OK) return st;
+    CKD(kTagState, c->state, c->state_bytes)
+    CKD(kTagCur, s.cur, 8 * (size_t)n)
+    CKD(kTagE, s.E, 8 * (size_t)n)
+    CKD(kTagItv, s.itv, 4 * (size_t)n)
+    CKD(kTagB, s.b, 8 * 8 * (size_t)n)
+    CKD(kTagEta, s.eta, 8 * 8 * (size_t)n)
+    CKD(kTagSprev, s.sprev, 4 * 8 * (size_t)n)
+    CKD(kTagHbProp, s.hb_prop, 8 * (size_t)n)
+    CKD(kTagHbAcc, s.hb_acc, 8 * (size_t)n)
+    CKD(kTagA, s.a, 8 * (size_t)n)
+    CKD(kTagConf, s.conf, 4 * (size_t)n)
+    CKD(kTagSumE, s.sumE, 8 * (size_t)n)
+    CKD(kTagConvIter, s.conv_iter, 4 * (size_t)n)
+    CKD(kTagConvSweeps, s.conv_sweeps, 8 * (size_t)n)
+    CKD(kTagAHist, s.a_hist, s.a_hist ? 8 * (size_t)(p.n_rm + 1) * n : 0)
+    CKD(kTagLinkFix, s.link_fix, 8 * (size_t)n)
+    CKD(kTagLinkArc, s.link_arc, 8 * (size_t)n)
+    CKD(kTagLatDone, s.lat_done, 4 * (size_t)kMaxLat)
+    CKD(kTagMuLnRho, s.mu_lnrho, 8 * (size_t)n)
+    CKD(kTagMuB, s.mu_b, 8 * (size_t)kMaxLat)
+#undef CKD
+    // device scalars: sweep index, approach index, RM iteration, replica counts
+    uint32_t sc[2];
+    int rmi = 0;
+    unsigned long long re[2];
+    HIPCHK(hipMemcpy(&sc[0], s.sweep_ctr, 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&sc[1], s.approach_ctr, 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&rmi, s.rm_iter, 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(re, s.re_cnt, 16, hipMemcpyDeviceToHost));
+    w.val((uint32_t)kTagScalars);
+    w.val((uint64_t)(8 + 4 + 16));
+    w.put(sc, 8); w.val(rmi); w.put(re, 16);
+    // host state of the driver
+    CkWriter hw;
+    hw.val(c->rm_done); hw.val((int)c->rm_open); hw.val((int)c->ap_open); hw.val((int)c->have_energy);
+    hw.val((int)c->interleave); hw.val((int)c->per_link); hw.val((int)c->muca_ready); hw.val((int)c->tuned);
+    hw.val(c->lt.hb_lpt); hw.val(c->lt.or_lpt); hw.val(c->lt.serpentine);
+    for (size_t i = 0; i < c->lats.size(); ++i) {
+        hw.val(i < c->approach_sweeps.size() ? c->approach_sweeps[i] : 0ll);
+        hw.val(i < c->ap_done.size() ? c->ap_done[i] : 0);
+        hw.put(c->lats[i].a0.data(), 8 * (size_t)c->lats[i].n);
+    }
+    w.val((uint32_t)kTagHost);
+    w.val((uint64_t)hw.buf.size());
+    w.put(hw.buf.data(), hw.buf.size());
+    const uint32_t crc = crc32_update(0, w.buf.data(), w.buf.size());
+    w.val(crc);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return fail(LLR_EINVAL, std::string("cannot write ") + tmp);
+    const size_t put = fwrite(w.buf.data(), 1, w.buf.size(), f);
+    const int cl = fclose(f);
+    if (put != w.buf.size() || cl != 0 || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return fail(LLR_EINVAL, std::string("cannot write ") + path);
+    }
+    return LLR_OK;
+}
+
+llr_status llr_restore(llr_ctx* c, const char* path) {
+    llr_status st = need_state(c);
+    if (st != LLR_OK) return st;
+    std::vector<unsigned char> data;
+    CkHeader h;
+    if ((st = ck_load(path, data, h)) != LLR_OK) return st;
+    if ((int)h.precision != c->precision) return fail(LLR_EINVAL, "checkpoint precision differs from the context's");
+    if (h.lats.size() != c->lats.size()) return fail(LLR_EINVAL, "checkpoint lattice set differs from the context's");
+    for (size_t i = 0; i < h.lats.size(); ++i) {
+        const auto& a = h.lats[i];
+        const auto& b = c->lats[i];
+        if (a.L != b.L || a.n != b.n || a.dE != b.dE || memcmp(a.E_low.data(), b.E_low.data(), 8 * (size_t)a.n) != 0)
+            return fail(LLR_EINVAL, "checkpoint lattice set differs from the context's");
+    }
+    const int n = c->lt.n_chains;
+    const llr_params& p = h.prm;
+    // parse and size-check every section before anything is written to the device
+    struct Sec { uint32_t tag; uint64_t bytes; const unsigned char* at; };
+    std::vector<Sec> secs;
+    CkReader r{data.data(), data.size() - 4};
+    r.off = h.body;
+    while (r.off < r.n) {
+        Sec x{};
+        if (!r.val(&x.tag) || !r.val(&x.bytes) || x.bytes > r.n - r.off) return fail(LLR_EINVAL, "checkpoint section truncated");
+        x.at = r.p + r.off;
+        r.off += (size_t)x.bytes;
+        secs.push_back(x);
+    }
+    auto find = [&](uint32_t tag) -> const Sec* {
+        for (const auto& x : secs)
+            if (x.tag == tag) return &x;
+        return nullptr;
+    };
+    struct Want { uint32_t tag; size_t bytes; };
+    const Want want[] = {
+        {kTagState, c->state_bytes}, {kTagCur, 8 * (size_t)n}, {kTagE, 8 * (size_t)n}, {kTagItv, 4 * (size_t)n},
+        {kTagB, 64 * (size_t)n}, {kTagEta, 64 * (size_t)n}, {kTagSprev, 32 * (size_t)n}, {kTagHbProp, 8 * (size_t)n},
+        {kTagHbAcc, 8 * (size_t)n}, {kTagA, 8 * (size_t)n}, {kTagConf, 4 * (size_t)n}, {kTagSumE, 8 * (size_t)n},
+        {kTagConvIter, 4 * (size_t)n}, {kTagConvSweeps, 8 * (size_t)n}, {kTagLinkFix, 8 * (size_t)n},
+        {kTagLinkArc, 8 * (size_t)n}, {kTagLatDone, 4 * (size_t)kMaxLat}, {kTagMuLnRho, 8 * (size_t)n},
+        {kTagMuB, 8 * (size_t)kMaxLat}, {kTagScalars, 28}};
+    for (const auto& x : want) {
+        const Sec* q = find(x.tag);
+        if (!q || q->bytes != x.bytes) return fail(LLR_EINVAL, "checkpoint section missing or of the wrong size");
+    }
+    const Sec* ah = find(kTagAHist);
+    if (!ah || (ah->bytes != 0 && ah->bytes != 8 * (size_t)(p.n_rm + 1) * n))
+        return fail(LLR_EINVAL, "checkpoint history of the wrong size");
+    const Sec* hs = find(kTagHost);
+    size_t host_bytes = 4 * 11;
+    for (const auto& l : h.lats) host_bytes += 8 + 4 + 8 * (size_t)l.n;
+    if (!hs || hs->bytes != host_bytes) return fail(LLR_EINVAL, "checkpoint driver state of the wrong size");
+    CkReader hr{hs->at, (size_t)hs->bytes};
+    int rm_done, rm_open, ap_open, have_e, inter, per_link, muca, tuned, hbl, orl, serp;
+    hr.val(&rm_done); hr.val(&rm_open); hr.val(&ap_open); hr.val(&have_e); hr.val(&inter); hr.val(&per_link);
+    hr.val(&muca); hr.val(&tuned); hr.val(&hbl); hr.val(&orl); hr.val(&serp);
+    auto ok_lpt = [](int v) { return v == 1 || v == 2 || v == 4; };
+    if (!ok_lpt(hbl) || !ok_lpt(orl) || rm_done < 0 || rm_done > p.n_rm)
+        return fail(LLR_EINVAL, "bad driver state in checkpoint");
+    // parameters (and with them the restriction widths), then the device state
+    if ((st = llr_set_params(c, &p)) != LLR_OK) return st;
+    HIPCHK(hipSetDevice(c->device));
+    if ((st = upload_intervals(c)) != LLR_OK) return st;
+    const DevState& s = c->ds;
+    auto up = [&](uint32_t tag, void* d) -> llr_status {
+        const Sec* q = find(tag);
+        if (q->bytes) HIPCHK(hipMemcpy(d, q->at, (size_t)q->bytes, hipMemcpyHostToDevice));
+        return LLR_OK;
+    };
+#define CKU(tag, ptr) \
+    if ((st = up(tag, ptr)) != LLR_OK) return st;
+    CKU(kTagState, c->state) CKU(kTagCur, s.cur) CKU(kTagE, s.E) CKU(kTagItv, s.itv) CKU(kTagB, s.b)
+    CKU(kTagEta, s.eta) CKU(kTagSprev, s.sprev) CKU(kTagHbProp, s.hb_prop) CKU(kTagHbAcc, s.hb_acc) CKU(kTagA, s.a)
+    CKU(kTagConf, s.conf) CKU(kTagSumE, s.sumE) CKU(kTagConvIter, s.conv_iter) CKU(kTagConvSweeps, s.conv_sweeps)
+    CKU(kTagLinkFix, s.link_fix) CKU(kTagLinkArc, s.link_arc) CKU(kTagLatDone, s.lat_done) CKU(kTagMuLnRho, s.mu_lnrho)
+    CKU(kTagMuB, s.mu_b)
+#undef CKU
+    if (c->ds.a_hist) {
+        HIPCHK(hipFree(c->ds.a_hist));
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void*)c->ds.a_hist), c->allocs.end());
+        c->ds.a_hist = nullptr;
+    }
+    if (ah->bytes) {
+        if ((st = dalloc(c, &c->ds.a_hist, (size_t)(p.n_rm + 1) * n)) != LLR_OK) return st;
+        HIPCHK(hipMemcpy(c->ds.a_hist, ah->at, (size_t)ah->bytes, hipMemcpyHostToDevice));
+    }
+    const Sec* sc = find(kTagScalars);
+    HIPCHK(hipMemcpy(s.sweep_ctr, sc->at, 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.approach_ctr, sc->at + 4, 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.rm_iter, sc->at + 8, 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.re_cnt, sc->at + 12, 16, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(s.bits, 0, 2 * (size_t)(n + 2)));
+    HIPCHK(hipDeviceSynchronize());
+    c->rm_done = rm_done;
+    c->rm_open = rm_open != 0;
+    c->ap_open = ap_open != 0;
+    c->have_energy = have_e != 0;
+    c->interleave = inter != 0;
+    c->per_link = per_link != 0;
+    c->muca_ready = muca != 0;
+    set_tiles(c->lt, hbl, orl);
+    c->tuned = tuned != 0;
+    c->lt.serpentine = serp;
+    c->approach_sweeps.assign(c->lats.size(), 0);
+    c->ap_done.assign(c->lats.size(), 0);
+    for (size_t i = 0; i < c->lats.size(); ++i) {
+        hr.val(&c->approach_sweeps[i]);
+        hr.val(&c->ap_done[i]);
+        hr.get(c->lats[i].a0.data(), 8 * (size_t)c->lats[i].n);
+    }
+    drop_graphs(c);
     return LLR_OK;
 }
 

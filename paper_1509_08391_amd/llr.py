@@ -71,6 +71,10 @@ _SIGS = {
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
     "llr_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong)],
     "llr_link_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong)],
+    "llr_checkpoint": [C.c_void_p, C.c_char_p],
+    "llr_restore": [C.c_void_p, C.c_char_p],
+    "llr_checkpoint_info": [C.c_char_p, _p(C.c_int), _p(C.c_int), _p(C.c_int), _p(C.c_int), _p(C.c_double),
+                            _p(C.c_double), _p(Params)],
     "llr_set_timing": [C.c_void_p, C.c_int],
     "llr_get_timing": [C.c_void_p, _p(C.c_double), _p(C.c_longlong), _p(C.c_double), _p(C.c_longlong),
                        _p(C.c_double), _p(C.c_longlong)],
@@ -325,6 +329,32 @@ class Context:
         _check(lib().llr_stats(self.h, _ptr(hp, C.c_longlong), _ptr(ha, C.c_longlong), C.byref(rp), C.byref(ra)))
         return hp, ha, rp.value, ra.value
 
+    # ---- checkpoints
+    def checkpoint(self, path):
+        """Save the whole state of Algorithm 1 (angles, bits, E, a_k, counters,
+        chain <-> interval labels, history) to path."""
+        _check(lib().llr_checkpoint(self.h, os.fsencode(path)))
+
+    def restore(self, path):
+        """Load a checkpoint written for the same precision and lattice set
+        into this context (state bound)."""
+        _check(lib().llr_restore(self.h, os.fsencode(path)))
+        self.params = checkpoint_info(path)["params"]
+
+    @classmethod
+    def from_checkpoint(cls, path, device=0, stream=None):
+        """A new context with the checkpoint's precision, lattices and
+        parameters, its state allocated, bound and restored."""
+        info = checkpoint_info(path)
+        ctx = cls(precision=info["precision"], device=device, stream=stream)
+        _check(lib().llr_set_params(ctx.h, C.byref(info["params"])))
+        ctx.params = info["params"]
+        for L, E_low, dE in info["lattices"]:
+            ctx.add_lattice(L, E_low, dE)
+        ctx.bind_state()
+        ctx.restore(path)
+        return ctx
+
     def link_stats(self):
         """Per chain: links re-drawn under the per-link constraint and, of
         those, draws of the arc sampler (cumulative)."""
@@ -465,6 +495,25 @@ class Context:
         _check(lib().llr_mlp_train(self.h, _ptr(w, C.c_float), _ptr(u, C.c_float), _ptr(invL, C.c_float),
                                    _ptr(a, C.c_double), u.size, epochs, lr, int(bf16), _ptr(hist, C.c_double)))
         return w, hist[:epochs]
+
+
+def checkpoint_info(path):
+    """Validate a checkpoint on the host (no device needed) and return its
+    precision, lattices [(L, E_low, dE)] and parameters."""
+    prec, nl = C.c_int(), C.c_int()
+    Ls = np.zeros(8, dtype=np.int32)
+    ns = np.zeros(8, dtype=np.int32)
+    dEs = np.zeros(8)
+    prm = Params()
+    _check(lib().llr_checkpoint_info(os.fsencode(path), C.byref(prec), C.byref(nl), _ptr(Ls, C.c_int),
+                                     _ptr(ns, C.c_int), _ptr(dEs, C.c_double), None, C.byref(prm)))
+    E_low = np.zeros(int(ns[: nl.value].sum()))
+    _check(lib().llr_checkpoint_info(os.fsencode(path), None, None, None, None, None, _ptr(E_low, C.c_double), None))
+    lats, off = [], 0
+    for i in range(nl.value):
+        lats.append((int(Ls[i]), E_low[off: off + ns[i]].copy(), float(dEs[i])))
+        off += int(ns[i])
+    return {"precision": prec.value, "lattices": lats, "params": prm}
 
 
 def fss_fit(L, y, sigma, powers):

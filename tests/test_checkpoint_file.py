@@ -1,0 +1,82 @@
+"""Checkpoint files on the host (no device): a file written to the documented
+layout is read back by llr_checkpoint_info; a truncated, corrupted, foreign or
+missing file is rejected with LLR_EINVAL before any device work."""
+import ctypes as C
+import os
+import struct
+import zlib
+
+import numpy as np
+import pytest
+
+from paper_1509_08391_amd import llr
+
+EINVAL = -1
+
+
+def _file(lats, prm, sections=(), version=1, precision=1, magic=b"LLRCKPT1"):
+    b = bytearray(magic)
+    b += struct.pack("<III", version, precision, len(lats))
+    for L, E_low, dE in lats:
+        b += struct.pack("<iid", L, len(E_low), dE)
+        b += np.asarray(E_low, dtype="<f8").tobytes()
+    b += struct.pack("<iiiQidid i".replace(" ", ""), *prm)
+    for tag, data in sections:
+        b += struct.pack("<IQ", tag, len(data)) + data
+    b += struct.pack("<I", zlib.crc32(bytes(b)) & 0xFFFFFFFF)
+    return bytes(b)
+
+
+LATS = [(4, [600.0, 640.0, 680.0], 40.0), (6, [3000.0, 3100.0], 100.0)]
+PRM = (5, 7, 3, 1509083910, 1, 1.0, 10, 1e-4, 200)
+
+
+def _info(path):
+    return llr.checkpoint_info(str(path))
+
+
+def _status(path):
+    lib = llr.lib()
+    prec, nl = C.c_int(), C.c_int()
+    return lib.llr_checkpoint_info(os.fsencode(str(path)), C.byref(prec), C.byref(nl), None, None, None, None, None)
+
+
+def test_documented_layout_reads_back(tmp_path):
+    p = tmp_path / "ok.ckpt"
+    p.write_bytes(_file(LATS, PRM, sections=[(1, b"\0" * 16)]))
+    info = _info(p)
+    assert info["precision"] == llr.FP32
+    assert [(L, list(E), dE) for L, E, dE in info["lattices"]] == [(L, list(E), dE) for L, E, dE in LATS]
+    prm = info["params"]
+    assert (prm.n_th, prm.n_a, prm.n_rm, prm.seed, prm.replica_exchange, prm.overlap, prm.recompute_every,
+            prm.eps, prm.approach_cap) == PRM
+
+
+def test_truncated_corrupted_foreign_and_missing_files_are_rejected(tmp_path):
+    good = _file(LATS, PRM, sections=[(1, b"\1" * 64)])
+    cases = {
+        "truncated_tail": good[:-7],
+        "truncated_header": good[:20],
+        "empty": b"",
+        "flipped_bit": good[:40] + bytes([good[40] ^ 0x10]) + good[41:],
+        "flipped_crc": good[:-1] + bytes([good[-1] ^ 1]),
+        "magic": _file(LATS, PRM, magic=b"LLRCKPT2"),
+        "version": _file(LATS, PRM, version=2),
+        "precision": _file(LATS, PRM, precision=7),
+        "odd_L": _file([(5, [1.0], 1.0)], PRM),
+        "no_lattices": _file([], PRM),
+    }
+    for name, data in cases.items():
+        p = tmp_path / f"{name}.ckpt"
+        p.write_bytes(data)
+        assert _status(p) == EINVAL, name
+        with pytest.raises(llr.LLRError):
+            _info(p)
+    assert _status(tmp_path / "does_not_exist.ckpt") == EINVAL
+
+
+def test_restore_without_context_is_rejected(tmp_path):
+    p = tmp_path / "ok.ckpt"
+    p.write_bytes(_file(LATS, PRM))
+    assert llr.lib().llr_restore(None, os.fsencode(str(p))) == EINVAL
+    assert llr.lib().llr_checkpoint(None, os.fsencode(str(p))) == EINVAL
