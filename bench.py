@@ -12,11 +12,16 @@ One step = one Robbins-Monro iteration of all 128 intervals: 2500 sweeps (8
 heatbath + 8 overrelaxation class passes of all chains, recompute, replica
 exchange, measurement), the a_k update, and the FP64 reconstruction of
 beta_c and the C_V peak on beta in [1.008, 1.012].  One link update = one
-heatbath or one overrelaxation of one link; a sweep is 2 x 4V updates.
+heatbath or one overrelaxation of one link.
 
---order: interleaved (default; heatbath then overrelaxation per colour, one
-fused launch per colour) or grouped (heatbath of every colour, then
-overrelaxation of every colour, 16 launches); the same updates either way.
+--order: grouped (default; heatbath of every colour, then overrelaxation of
+every colour, 16 launches per sweep: 2 x 4V updates per sweep) or interleaved
+(heatbath then overrelaxation per colour, one fused launch per colour).  In
+the interleaved order the overrelaxation reflects the heatbath draw just made
+on the same staples, which is again a von Mises draw: an accepted heatbath
+class gives its links one update, a rejected one gives the rejected proposal
+and one overrelaxation.  Its count is (2 - acceptance) x V/2 per class pass,
+with the heatbath class acceptance measured over the timed steps.
 """
 import argparse
 import json
@@ -79,7 +84,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--order", choices=["interleaved", "grouped"], default="interleaved")
+    ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped")
     ap.add_argument("--n-th", type=int, default=500)
     ap.add_argument("--n-a", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -144,6 +149,7 @@ def main():
         ctx.rm_step(1)
         print(f"# warmup step {w} done", file=sys.stderr, flush=True)
     ctx.set_timing(True)
+    hp0, ha0, _, _ = ctx.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -159,7 +165,13 @@ def main():
 
     nsw = args.n_th + args.n_a
     dt = t1 - t0
-    updates = 2.0 * 4 * V * N_INT * nsw * args.steps
+    hb_acc_timed = float((ha - ha0).sum() / max((hp - hp0).sum(), 1))
+    if args.order == "grouped":
+        updates = 2.0 * 4 * V * N_INT * nsw * args.steps
+    else:
+        # 8 fused passes per sweep of V/2 class links each: 1 update per link
+        # of an accepted class, 2 (proposal + overrelaxation) of a rejected one
+        updates = (2.0 - hb_acc_timed) * 8 * (V // 2) * N_INT * nsw * args.steps
     value = updates / dt
     esz = 4 if prec == llr.FP32 else 8
     # algorithmic bytes of one heatbath pass: the pass reads the whole lattice
@@ -199,7 +211,7 @@ def main():
                                else "heatbath + overrelaxation class pass (k_hb, fused)",
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
                      "overrelaxation_avg_launch_us": or_avg_s * 1e6},
-        "acceptance": {"heatbath_class": float(ha.sum() / max(hp.sum(), 1)),
+        "acceptance": {"heatbath_class": hb_acc_timed,
                        "replica_exchange": float(ra / max(rp, 1))},
         "approach_sweeps": int(ap_sweeps[0]),
     }
