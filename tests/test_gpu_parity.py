@@ -329,7 +329,15 @@ def test_approach_parity_fp64(llr):
 
 def test_driver_mixed_lattices_fp64(llr):
     """L=4 and L=6 chains batched in one launch; each lattice against its own
-    oracle run (lattice id in the Philox counter)."""
+    oracle run (lattice id in the Philox counter): 4 sweeps, two RM
+    iterations.  a_k within 1e-7, the single-lattice driver run's bar
+    (measured 5e-13 and 2e-13).  Angles: with the random numbers fixed the
+    sweep map amplifies the two sides' last-bit differences (~3e-14 after
+    one sweep) by ~5x per sweep, and by ~1/R at links with a small staple
+    modulus R, so after four sweeps most links agree to ~1e-12 and a few
+    have grown further.  Measured: L=4 median 1e-12, max 5e-10; L=6 median
+    7e-13, 99 % 8e-10, 99.9 % 4.5e-9, max 6.6e-7 (115 of 15552 links above
+    1e-9).  Bars: median 1e-11, 99 % of links 1e-8, every link 1e-5."""
     import torch
     d = 4
     lats = []
@@ -346,8 +354,14 @@ def test_driver_mixed_lattices_fp64(llr):
         r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=0, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
                            lattice_id=i, theta=th, approach_cap=0)
         a, it, sw = ctx.get_a(i)
-        assert np.max(np.abs(a - r["a"])) < 1e-5
-        assert np.max(circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"])) < 1e-5
+        da = np.max(np.abs(a - r["a"]))
+        dist = circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"]).ravel()
+        q = np.quantile(dist, [0.5, 0.99, 0.999, 0.9999, 1.0])
+        print(f"\nmixed lattices, L={L}: max |a - a_oracle| {da:.2e}; angle differences: median {q[0]:.1e}, "
+              f"99% {q[1]:.1e}, 99.9% {q[2]:.1e}, 99.99% {q[3]:.1e}, max {q[4]:.1e}; "
+              f"links above 1e-9: {int(np.sum(dist > 1e-9))} of {dist.size}")
+        assert da < 1e-7
+        assert q[0] < 1e-11 and q[1] < 1e-8 and q[4] < 1e-5, q
 
 
 @pytest.mark.slow
@@ -355,33 +369,102 @@ def test_full_run_config0_statistical_fp64_and_fp32(llr):
     """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
     dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start).  Beyond
     ~15 sweeps the two implementations follow different trajectories, so the
-    final a_k are compared as distributions over 4 seeds: means agree within
-    4 combined standard errors, for the FP64 and the FP32 GPU path."""
+    final a_k are compared as distributions over 64 independent runs per side
+    (8 seeds x 8 lattice ids; the GPU runs the 8 lattices of a seed in one
+    context, the oracle each (seed, lattice id) alone): means agree within 4
+    combined standard errors, for the FP64 and the FP32 GPU path.  The
+    single-run spread of a_k here is ~3e-3, so the combined standard error,
+    the resolution of this comparison, is ~5e-4 per interval."""
+    from concurrent.futures import ThreadPoolExecutor
     L, d = 4, 4
     V6 = 6 * L ** 4
     dE = 0.025 * V6
     E_low = 0.5 * V6 + dE * np.arange(8)
-    seeds = [SEED + 17 * i for i in range(4)]
+    seeds = [SEED + 17 * i for i in range(8)]
+    n_lat = 8
     res = {}
     for prec in ("FP64", "FP32"):
         A = []
         for sd in seeds:
-            ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)], seed=sd, n_th=100, n_a=100, n_rm=20,
+            ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)] * n_lat, seed=sd, n_th=100, n_a=100, n_rm=20,
                        approach_cap=20000)
             ctx.hot_start()
             ctx.approach()
             ctx.run()
-            A.append(ctx.get_a(0)[0])
+            A.extend(ctx.get_a(i)[0] for i in range(n_lat))
             ctx.close()
         res[prec] = np.array(A)
-    O = np.array([oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd,
-                                 approach_cap=20000)["a"] for sd in seeds])
+
+    def orun(job):
+        sd, lid = job
+        return oracle.llr_run(d, L, E_low, dE, 1.0, n_th=100, n_a=100, n_rm=20, seed=sd, lattice_id=lid,
+                              approach_cap=20000)["a"]
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        O = np.array(list(ex.map(orun, [(sd, lid) for sd in seeds for lid in range(n_lat)])))
     for prec in ("FP64", "FP32"):
         G = res[prec]
-        se = np.sqrt(G.var(0, ddof=1) / len(seeds) + O.var(0, ddof=1) / len(seeds))
-        se = np.maximum(se, 2e-4)
-        z = np.abs(G.mean(0) - O.mean(0)) / se
-        assert np.all(z < 4.0), (prec, z, G.mean(0) - O.mean(0))
+        se = np.sqrt(G.var(0, ddof=1) / G.shape[0] + O.var(0, ddof=1) / O.shape[0])
+        diff = G.mean(0) - O.mean(0)
+        z = np.abs(diff) / se
+        print(f"\nconfig0 {prec}, 64 + 64 runs: max |mean a_GPU - mean a_oracle| {np.abs(diff).max():.2e}, "
+              f"combined standard error {se.min():.1e}-{se.max():.1e}, max z {z.max():.2f}, "
+              f"mean difference over intervals {diff.mean():+.1e} +- {np.sqrt(np.sum(se ** 2)) / se.size:.1e}")
+        assert np.all(z < 4.0), (prec, z, diff)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_negative_coupling_heatbath(llr, prec):
+    """Heatbath passes at negative couplings a_k < 0 (kappa = a R < 0: the
+    conditional peaks at theta = -phi + pi, X ~ vM(|kappa|) shifted by pi),
+    free mode so every class is written, one class at a time from the same
+    state on both sides.  FP64: every class link within 1e-12 of the oracle.
+    FP32 against the oracle's FP32-state pass (23-bit uniforms): class links
+    within 1e-5 except those whose sampler test the oracle flags (margin
+    below 1e-5)."""
+    import torch
+    d, L, n = 4, 6, 3
+    V = L ** d
+    f32 = prec == "FP32"
+    dt = np.float32 if f32 else np.float64
+    th = random_state(d, L, n, seed=321, u_target=0.6, dtype=dt).astype(np.float64)
+    a = np.array([-0.4, -1.0, -2.5])
+    E0 = np.array([oracle.energy(d, L, th[k]) for k in range(n)])
+    order = np.argsort(E0)
+    th, E0 = np.ascontiguousarray(th[order]), E0[order]
+    dE = 1000.0                                  # free mode: the intervals only label the chains
+    E_low = E0.min() - 0.5 * dE + dE * np.arange(n)
+    ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)], a=[a])
+    ctx.import_state(0, torch.from_numpy(th.astype(dt)))
+    par = np.zeros(V, dtype=np.int64)
+    for m in range(d):
+        par += (np.arange(V) // L ** m) % L
+    par &= 1
+    cur = th.copy()
+    n_flag = 0
+    for col in range(8):
+        ctx.class_pass(1, col, mode=llr.MODE_FREE, sweep_index=13)
+        got = ctx.export_state(0).cpu().numpy().astype(np.float64)
+        mu, idx = col >> 1, np.nonzero(par == (col & 1))[0]
+        for k in range(n):
+            tr = cur[k].copy()
+            Ek = oracle.energy(d, L, tr)
+            acc, _, _, mg = oracle.class_pass(d, L, tr, 1, col, oracle.MODE_FREE, a[k], -1e9, 1e9, Ek, SEED,
+                                              sweep=13, interval=k, f32=f32, want_margin=True)
+            assert acc
+            dist = circ_dist(got[k][mu, idx], tr[mu, idx])
+            if f32:
+                flag = mg < 1e-5
+                n_flag += int(flag.sum())
+                assert dist[~flag].max() < 1e-5, (col, k, dist[~flag].max())
+            else:
+                assert dist.max() < 1e-12, (col, k, dist.max())
+            # the rest of the chain is untouched
+            others = np.ones((d, V), dtype=bool)
+            others[mu, idx] = False
+            assert np.array_equal(got[k][others], cur[k][others])
+        cur = got
+    assert n_flag <= 3
 
 
 def test_reconstruction_and_beta_c(llr):
@@ -506,6 +589,24 @@ def test_invalid_arguments_are_rejected(llr):
         ctx.run()                               # state not bound
     with pytest.raises(llr.LLRError):
         ctx.set_params(n_a=0)
+    ctx.close()
+    # edges off Algorithm 1's E_k = E_0 + k dE: the sweeps take them, ln rho
+    # and the multicanonical weight (which rely on the spacing) refuse them
+    for edges, ok in (([600.0, 640.0, 680.0], True), ([600.0, 640.0, 690.0], False)):
+        ctx = llr.Context(precision=llr.FP64)
+        ctx.add_lattice(4, edges, 40.0)
+        ctx.bind_state()
+        ctx.hot_start()
+        if ok:
+            ctx.get_ln_rho(0)
+            ctx.muca_begin([1.0])
+        else:
+            with pytest.raises(llr.LLRError):
+                ctx.get_ln_rho(0)
+            with pytest.raises(llr.LLRError):
+                ctx.muca_begin([1.0])
+        ctx.sweeps(1, mode=llr.MODE_FREE)
+        ctx.close()
 
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
