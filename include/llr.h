@@ -426,6 +426,16 @@ llr_status llr_muca_reweight(llr_ctx *ctx, const double *E, long m, const double
 llr_status llr_mlp_init(llr_ctx *ctx, uint64_t seed, float *weights);
 llr_status llr_mlp_predict(llr_ctx *ctx, const float *weights, const float *u, const float *inv_L,
                            int n, int bf16, double *a_out);
+/* Warm start of Algorithm 1 from the network (Sec. 2.4: initial a_i close to
+ * the result shorten the Robbins-Monro iteration): predicts a_k at the
+ * centres c_k of lattice lattice_id (u = c_k/(6V), 1/L) and sets them as
+ * a_k^(0) (llr_set_a).  Plain Robbins-Monro stays the fallback: a prediction
+ * that is not finite or lies outside [a_min, a_max] (the caller passes the
+ * range of the a_k the network was trained on, with any margin) is replaced
+ * by a^(0) = 1, the cold start.  a_out (host, n_intervals, optional)
+ * receives the a_k^(0) set; n_fallback (optional) the number replaced. */
+llr_status llr_mlp_warm_start(llr_ctx *ctx, int lattice_id, const float *weights, int bf16, double a_min,
+                              double a_max, double *a_out, int *n_fallback);
 /* Mean squared error on a and its gradient (host, 4417). */
 llr_status llr_mlp_loss_grad(llr_ctx *ctx, const float *weights, const float *u,
                              const float *inv_L, const double *a, int n, int bf16, float *grad,

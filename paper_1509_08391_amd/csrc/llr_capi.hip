@@ -1534,6 +1534,31 @@ llr_status llr_mlp_predict(llr_ctx* c, const float* w, const float* u, const flo
     return LLR_OK;
 }
 
+llr_status llr_mlp_warm_start(llr_ctx* c, int lat, const float* w, int bf16, double a_min, double a_max,
+                              double* a_out, int* n_fallback) {
+    if (!c || !w) return fail(LLR_EINVAL, "bad argument");
+    if (lat < 0 || lat >= (int)c->lats.size()) return fail(LLR_EINVAL, "no such lattice");
+    if (!(a_max >= a_min) || !std::isfinite(a_min) || !std::isfinite(a_max))
+        return fail(LLR_EINVAL, "need finite a_min <= a_max");
+    const HostLat& hl = c->lats[lat];
+    const double six_v = 6.0 * (double)hl.L * hl.L * hl.L * hl.L;
+    std::vector<float> u(hl.n), il(hl.n, (float)(1.0 / hl.L));
+    for (int k = 0; k < hl.n; ++k) u[k] = (float)((hl.E_low[k] + 0.5 * hl.dE) / six_v);
+    std::vector<double> a(hl.n);
+    llr_status st = llr_mlp_predict(c, w, u.data(), il.data(), hl.n, bf16, a.data());
+    if (st != LLR_OK) return st;
+    int nf = 0;
+    for (int k = 0; k < hl.n; ++k)
+        if (!std::isfinite(a[k]) || a[k] < a_min || a[k] > a_max) {
+            a[k] = 1.0;
+            ++nf;
+        }
+    if ((st = llr_set_a(c, lat, a.data())) != LLR_OK) return st;
+    if (a_out) memcpy(a_out, a.data(), 8 * (size_t)hl.n);
+    if (n_fallback) *n_fallback = nf;
+    return LLR_OK;
+}
+
 llr_status llr_mlp_loss_grad(llr_ctx* c, const float* w, const float* u, const float* invL, const double* a, int n,
                              int bf16, float* grad, double* loss) {
     if (!c || !w || !u || !invL || !a || !grad || !loss || n < 1 || n > 4096) return fail(LLR_EINVAL, "bad argument");

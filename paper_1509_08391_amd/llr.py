@@ -104,6 +104,8 @@ _SIGS = {
     "llr_mlp_init": [C.c_void_p, C.c_uint64, _p(C.c_float)],
     "llr_mlp_predict": [C.c_void_p, _p(C.c_float), _p(C.c_float), _p(C.c_float), C.c_int, C.c_int,
                         _p(C.c_double)],
+    "llr_mlp_warm_start": [C.c_void_p, C.c_int, _p(C.c_float), C.c_int, C.c_double, C.c_double, _p(C.c_double),
+                           _p(C.c_int)],
     "llr_mlp_loss_grad": [C.c_void_p, _p(C.c_float), _p(C.c_float), _p(C.c_float), _p(C.c_double), C.c_int,
                           C.c_int, _p(C.c_float), _p(C.c_double)],
     "llr_mlp_train": [C.c_void_p, _p(C.c_float), _p(C.c_float), _p(C.c_float), _p(C.c_double), C.c_int, C.c_int,
@@ -479,6 +481,18 @@ class Context:
         _check(lib().llr_mlp_predict(self.h, _ptr(w, C.c_float), _ptr(u, C.c_float), _ptr(invL, C.c_float), u.size,
                                      int(bf16), _ptr(a, C.c_double)))
         return a
+
+    def mlp_warm_start(self, lattice_id, w, a_min, a_max, bf16=True):
+        """Set lattice_id's a_k^(0) from the network, with the cold start
+        a^(0) = 1 wherever the prediction is non-finite or outside
+        [a_min, a_max].  Returns (a_k^(0), number of fallbacks)."""
+        w = _arr(w, np.float32)
+        n = self.lattices[lattice_id][1]
+        a = np.empty(n)
+        nf = C.c_int()
+        _check(lib().llr_mlp_warm_start(self.h, lattice_id, _ptr(w, C.c_float), int(bf16), a_min, a_max,
+                                        _ptr(a, C.c_double), C.byref(nf)))
+        return a, nf.value
 
     def mlp_loss_grad(self, w, u, invL, a, bf16=False):
         w, u, invL, a = _arr(w, np.float32), _arr(u, np.float32), _arr(invL, np.float32), _arr(a, np.float64)
