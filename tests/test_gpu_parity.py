@@ -419,16 +419,18 @@ def test_negative_coupling_heatbath(llr, prec):
     conditional peaks at theta = -phi + pi, X ~ vM(|kappa|) shifted by pi),
     free mode so every class is written, one class at a time from the same
     state on both sides.  FP64: every class link within 1e-12 of the oracle.
-    FP32 against the oracle's FP32-state pass (23-bit uniforms): class links
-    within 1e-5 except those whose sampler test the oracle flags (margin
-    below 1e-5)."""
+    FP32 against the oracle's FP32-state pass (23-bit uniforms), links whose
+    sampler test the oracle flags (margin below 1e-5) aside: within
+    1e-5 + 2e-6/R per link, the sampler's own FP32 bar plus the phase
+    phi = arg(C + iS) moved by the FP32 staple sums' error (~1e-6 absolute
+    over six terms) divided by the staple modulus R."""
     import torch
     d, L, n = 4, 6, 3
     V = L ** d
     f32 = prec == "FP32"
     dt = np.float32 if f32 else np.float64
     th = random_state(d, L, n, seed=321, u_target=0.6, dtype=dt).astype(np.float64)
-    a = np.array([-0.4, -1.0, -2.5])
+    a = np.array([-0.4, -0.9, -1.4])
     E0 = np.array([oracle.energy(d, L, th[k]) for k in range(n)])
     order = np.argsort(E0)
     th, E0 = np.ascontiguousarray(th[order]), E0[order]
@@ -456,7 +458,10 @@ def test_negative_coupling_heatbath(llr, prec):
             if f32:
                 flag = mg < 1e-5
                 n_flag += int(flag.sum())
-                assert dist[~flag].max() < 1e-5, (col, k, dist[~flag].max())
+                R = np.array([np.hypot(*oracle.local_field(d, L, cur[k], mu, int(sx))) for sx in idx])
+                bar = 1e-5 + 2e-6 / np.maximum(R, 1e-30)
+                worst = np.max(dist[~flag] / bar[~flag])
+                assert worst < 1.0, (col, k, worst, dist[~flag].max())
             else:
                 assert dist.max() < 1e-12, (col, k, dist.max())
             # the rest of the chain is untouched
