@@ -327,6 +327,22 @@ llr_status llr_beta_c(llr_ctx *ctx, const double *centres, const double *a, int 
                       double six_v, double blo, double bhi, double h, double tol,
                       double *beta_c, double *cv_peak);
 
+/* llr_beta_c for callers that cannot allocate device memory (code running
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, with the device copies
+ * of centres and a, ln rho, the grid of Var(E) and the result held in one
+ * fixed library array of 1 MiB per GPU (created with the library, resolved by
+ * llr_create for its device, never freed before the process ends) instead of
+ * the context's growing staging buffer.  The call allocates nothing.
+ * Requires 8 (3 n + ng + 8) <= 2^20 bytes, ng = round((bhi - blo)/h) (e.g.
+ * n = 128 with ng up to 130 000), else LLR_EINVAL.  Every call on one GPU
+ * uses that GPU's array: calls that overlap on one GPU (several host threads
+ * or streams) race and must be serialised by the caller; the array keeps the
+ * last call's contents, which nothing reads. */
+llr_status llr_beta_c_noalloc(llr_ctx *ctx, const double *centres, const double *a, int n, double s,
+                              double six_v, double blo, double bhi, double h, double tol,
+                              double *beta_c, double *cv_peak);
+
 /* --- analysis of repeated runs (Sec. 2.4 N_B repetitions, Sec. 3.4) ------ */
 
 /* ln P_beta(E) at m energies E (host), P_beta(E) = rho~(E) e^{beta E} / Z with

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,29 @@ static llr_status fail(llr_status st, const std::string& msg) {
         if (e_ != hipSuccess)                                                                 \
             return fail(LLR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
     } while (0)
+
+// Device memory for llr_beta_c_noalloc, for callers that cannot allocate:
+// one fixed array per GPU, held until the process ends.  Host code never
+// uses the array's name as an address: llr_create resolves each device's
+// copy with hipGetSymbolAddress (that device current) and keeps the pointer.
+constexpr size_t kNoAllocBytes = (size_t)1 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve this device's copy of scratch once (the device must be current).
+static llr_status scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(LLR_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LLR_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LLR_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return LLR_OK;
+}
 
 struct HostLat {
     int L;
@@ -89,20 +113,20 @@ struct llr_ctx {
     std::vector<hipEvent_t> pool;
     double t_ms[3] = {0, 0, 0};
     long long t_n[3] = {0, 0, 0};
-    // scratch for host <-> device staging of small arrays
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
+    // device staging of small host arrays (grown on demand)
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
 };
 
 static size_t elem_size(const llr_ctx* c) { return c->precision == LLR_FP32 ? 4 : 8; }
 
-static llr_status ensure_scratch(llr_ctx* c, size_t bytes) {
-    if (c->scratch_bytes >= bytes) return LLR_OK;
-    if (c->scratch) HIPCHK(hipFree(c->scratch));
-    c->scratch = nullptr;
-    c->scratch_bytes = 0;
-    HIPCHK(hipMalloc(&c->scratch, bytes));
-    c->scratch_bytes = bytes;
+static llr_status ensure_stage(llr_ctx* c, size_t bytes) {
+    if (c->stage_bytes >= bytes) return LLR_OK;
+    if (c->stage) HIPCHK(hipFree(c->stage));
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    HIPCHK(hipMalloc(&c->stage, bytes));
+    c->stage_bytes = bytes;
     return LLR_OK;
 }
 
@@ -661,6 +685,8 @@ llr_status llr_create(llr_ctx** out, int hip_device, void* hip_stream, int preci
     if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
         return fail(LLR_EDEVICE, "no such HIP device");
     HIPCHK(hipSetDevice(hip_device));
+    const llr_status sst = scratch_setup(hip_device);
+    if (sst != LLR_OK) return sst;
     llr_ctx* c = new llr_ctx();
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
@@ -687,7 +713,7 @@ void llr_destroy(llr_ctx* c) {
     for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
     for (void* p : c->allocs) hipFree(p);
-    if (c->scratch) hipFree(c->scratch);
+    if (c->stage) hipFree(c->stage);
     delete c;
 }
 
@@ -1029,9 +1055,9 @@ llr_status llr_get_ln_rho(llr_ctx* c, int lat, double* centres, double* ln_rho) 
     HIPCHK(hipSetDevice(c->device));
     const HostLat& h = c->lats[lat];
     const int n = h.n;
-    llr_status st = ensure_scratch(c, 16 * (size_t)n + 64);
+    llr_status st = ensure_stage(c, 16 * (size_t)n + 64);
     if (st != LLR_OK) return st;
-    double* d = (double*)c->scratch;
+    double* d = (double*)c->stage;
     launch_recon(nullptr, c->ds.a + c->lt.l[lat].chain0, n, h.dE, 1.0, nullptr, 0, d, nullptr, nullptr, c->stream);
     HIPCHK(hipMemcpyAsync(ln_rho, d, 8 * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1135,9 +1161,9 @@ llr_status llr_test_philox(llr_ctx* c, long n, const uint32_t* ctr, uint64_t see
     if (!c || !ctr || !out || n < 0) return fail(LLR_EINVAL, "bad argument");
     if (n == 0) return LLR_OK;
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 32 * (size_t)n);
+    llr_status st = ensure_stage(c, 32 * (size_t)n);
     if (st != LLR_OK) return st;
-    uint4* d = (uint4*)c->scratch;
+    uint4* d = (uint4*)c->stage;
     HIPCHK(hipMemcpyAsync(d, ctr, 16 * (size_t)n, hipMemcpyHostToDevice, c->stream));
     launch_test_philox(n, d, (uint32_t)seed, (uint32_t)(seed >> 32), d + n, c->stream);
     HIPCHK(hipMemcpyAsync(out, d + n, 16 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
@@ -1151,9 +1177,9 @@ llr_status llr_test_vonmises(llr_ctx* c, long n, double kappa, uint64_t seed, ui
     if (!c || !X || !attempts || n < 0 || !(kappa >= 0)) return fail(LLR_EINVAL, "bad argument");
     if (n == 0) return LLR_OK;
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 12 * (size_t)n + 64);
+    llr_status st = ensure_stage(c, 12 * (size_t)n + 64);
     if (st != LLR_OK) return st;
-    double* dX = (double*)c->scratch;
+    double* dX = (double*)c->stage;
     int* dA = (int*)(dX + n);
     if (c->precision == LLR_FP32)
         launch_test_vonmises<float>(n, kappa, (uint32_t)seed, (uint32_t)(seed >> 32), c1, c2, c3, dX, dA, c->stream);
@@ -1171,9 +1197,9 @@ llr_status llr_reconstruct(llr_ctx* c, const double* centres, const double* a, i
     if (!c || !centres || !a || n < 1 || nb < 0 || !(s > 0) || !(six_v > 0)) return fail(LLR_EINVAL, "bad argument");
     if (nb > 0 && (!beta || !u_mean || !cv)) return fail(LLR_EINVAL, "bad beta arrays");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 3 * nb) + 64);
+    llr_status st = ensure_stage(c, 8 * (size_t)(3 * n + 3 * nb) + 64);
     if (st != LLR_OK) return st;
-    double* dc = (double*)c->scratch;
+    double* dc = (double*)c->stage;
     double* da = dc + n;
     double* dl = da + n;
     double* db = dl + n;
@@ -1201,14 +1227,44 @@ llr_status llr_beta_c(llr_ctx* c, const double* centres, const double* a, int n,
     const long ng = (long)std::floor((bhi - blo) / h + 0.5);
     if (ng > 10000000) return fail(LLR_EINVAL, "beta grid too fine");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + ng + 8) + 64);
+    llr_status st = ensure_stage(c, 8 * (size_t)(3 * n + ng + 8) + 64);
     if (st != LLR_OK) return st;
-    double* dc = (double*)c->scratch;
+    double* dc = (double*)c->stage;
     double* da = dc + n;
     double* out = da + n;
     double* scr = out + 4;
     HIPCHK(hipMemcpyAsync(dc, centres, 8 * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(da, a, 8 * n, hipMemcpyHostToDevice, c->stream));
+    launch_beta_c(dc, da, n, s, six_v, blo, bhi, h, tol, scr, out, c->stream);
+    double r[2];
+    HIPCHK(hipMemcpyAsync(r, out, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    *beta_c = r[0];
+    *cv_peak = r[1];
+    return LLR_OK;
+}
+
+llr_status llr_beta_c_noalloc(llr_ctx* c, const double* centres, const double* a, int n, double s, double six_v,
+                              double blo, double bhi, double h, double tol, double* beta_c, double* cv_peak) {
+    if (!c || !centres || !a || n < 1 || !(s > 0) || !(six_v > 0) || !(bhi > blo) || !(h > 0) || !(tol > 0) ||
+        !beta_c || !cv_peak)
+        return fail(LLR_EINVAL, "bad argument");
+    const double ngd = std::floor((bhi - blo) / h + 0.5);
+    // centres, a, the (beta_c, peak) pair, ln rho and the grid of ng + 1 variances
+    const double need = 8.0 * (3.0 * (double)n + ngd + 8.0);
+    if (!(need <= (double)kNoAllocBytes))
+        return fail(LLR_EINVAL, "llr_beta_c_noalloc: 8 (3 n + ng + 8) = " + std::to_string((long long)need) +
+                                    " bytes exceed its fixed 1 MiB device buffer");
+    void* base = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_ptr[c->device] : nullptr;
+    if (!base) return fail(LLR_ESTATE, "no fixed device buffer for this context's device");
+    HIPCHK(hipSetDevice(c->device));
+    double* dc = (double*)base;
+    double* da = dc + n;
+    double* out = da + n;
+    double* scr = out + 4;
+    HIPCHK(hipMemcpyAsync(dc, centres, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(da, a, 8 * (size_t)n, hipMemcpyHostToDevice, c->stream));
     launch_beta_c(dc, da, n, s, six_v, blo, bhi, h, tol, scr, out, c->stream);
     double r[2];
     HIPCHK(hipMemcpyAsync(r, out, 16, hipMemcpyDeviceToHost, c->stream));
@@ -1241,9 +1297,9 @@ llr_status llr_obs_reconstruct(llr_ctx* c, const double* centres, const double* 
     if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
     HIPCHK(hipSetDevice(c->device));
     const size_t mn = (size_t)m * n;
-    llr_status st = ensure_scratch(c, 8 * (2 * mn + 3 * (size_t)n + 2 * (size_t)nb) + 64);
+    llr_status st = ensure_stage(c, 8 * (2 * mn + 3 * (size_t)n + 2 * (size_t)nb) + 64);
     if (st != LLR_OK) return st;
-    double* dE = (double*)c->scratch;
+    double* dE = (double*)c->stage;
     double* dB = dE + mn;
     double* dc = dB + mn;
     double* da = dc + n;
@@ -1301,9 +1357,9 @@ llr_status llr_muca_reweight(llr_ctx* c, const double* E, long m, const double* 
         return fail(LLR_EINVAL, "bad argument");
     if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 8 * ((size_t)m + 3 * (size_t)n + 3 * (size_t)nb) + 64);
+    llr_status st = ensure_stage(c, 8 * ((size_t)m + 3 * (size_t)n + 3 * (size_t)nb) + 64);
     if (st != LLR_OK) return st;
-    double* dE = (double*)c->scratch;
+    double* dE = (double*)c->stage;
     double* dc = dE + m;
     double* da = dc + n;
     double* dL = da + n;
@@ -1329,9 +1385,9 @@ llr_status llr_prob_density(llr_ctx* c, const double* centres, const double* a, 
         return fail(LLR_EINVAL, "bad argument");
     if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 2 * m + 4) + 64);
+    llr_status st = ensure_stage(c, 8 * (size_t)(3 * n + 2 * m + 4) + 64);
     if (st != LLR_OK) return st;
-    double* dc = (double*)c->scratch;
+    double* dc = (double*)c->stage;
     double* da = dc + n;
     double* dE = da + n;
     double* dp = dE + m;
@@ -1353,9 +1409,9 @@ llr_status llr_prob_peaks(llr_ctx* c, const double* centres, const double* a, in
         return fail(LLR_EINVAL, "bad argument");
     if (!uniform_centres(centres, n, s)) return fail(LLR_EINVAL, "centres must be spaced by s");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 8 * (size_t)(3 * n + 2 * max_peaks + 8) + 64);
+    llr_status st = ensure_stage(c, 8 * (size_t)(3 * n + 2 * max_peaks + 8) + 64);
     if (st != LLR_OK) return st;
-    double* dc = (double*)c->scratch;
+    double* dc = (double*)c->stage;
     double* da = dc + n;
     double* dEp = da + n;
     double* dlp = dEp + max_peaks;
@@ -1387,9 +1443,9 @@ llr_status llr_bootstrap(llr_ctx* c, const double* centres, const double* a_runs
     if (ng > 1000000 || (double)n_boot * (double)(ng + 1) > 6.5e7) return fail(LLR_EINVAL, "beta grid too fine");
     HIPCHK(hipSetDevice(c->device));
     const size_t nd = (size_t)n * (1 + (size_t)n_runs + 2 * (size_t)n_boot) + (size_t)n_boot * (ng + 1 + 2) + 8;
-    llr_status st = ensure_scratch(c, 8 * nd + 64);
+    llr_status st = ensure_stage(c, 8 * nd + 64);
     if (st != LLR_OK) return st;
-    double* dc = (double*)c->scratch;
+    double* dc = (double*)c->stage;
     double* druns = dc + n;
     double* dbar = druns + (size_t)n_runs * n;
     double* dout = dbar + (size_t)n_boot * n;
@@ -1492,10 +1548,10 @@ llr_status llr_fss_fit(const double* x, const double* y, const double* sigma, in
 llr_status llr_mlp_init(llr_ctx* c, uint64_t seed, float* weights) {
     if (!c || !weights) return fail(LLR_EINVAL, "bad argument");
     HIPCHK(hipSetDevice(c->device));
-    llr_status st = ensure_scratch(c, 4 * kMlpNP);
+    llr_status st = ensure_stage(c, 4 * kMlpNP);
     if (st != LLR_OK) return st;
-    launch_mlp_init(seed, (float*)c->scratch, c->stream);
-    HIPCHK(hipMemcpyAsync(weights, c->scratch, 4 * kMlpNP, hipMemcpyDeviceToHost, c->stream));
+    launch_mlp_init(seed, (float*)c->stage, c->stream);
+    HIPCHK(hipMemcpyAsync(weights, c->stage, 4 * kMlpNP, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     return LLR_OK;
@@ -1504,9 +1560,9 @@ llr_status llr_mlp_init(llr_ctx* c, uint64_t seed, float* weights) {
 static llr_status stage_inputs(llr_ctx* c, const float* w, const float* u, const float* invL, const double* a, int n,
                                float** dw, float** du, float** dl, double** dA, size_t extra) {
     const size_t need = 4 * (size_t)kMlpNP + 8 * (size_t)n + 8 * (size_t)n + extra + 256;
-    llr_status st = ensure_scratch(c, need);
+    llr_status st = ensure_stage(c, need);
     if (st != LLR_OK) return st;
-    char* p = (char*)c->scratch;
+    char* p = (char*)c->stage;
     *dw = (float*)p; p += 4 * (size_t)kMlpNP; p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
     *du = (float*)p; p += 4 * (size_t)n;
     *dl = (float*)p; p += 4 * (size_t)n; p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);

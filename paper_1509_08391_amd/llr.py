@@ -85,6 +85,8 @@ _SIGS = {
                         _p(C.c_double), C.c_int, _p(C.c_double), _p(C.c_double), _p(C.c_double)],
     "llr_beta_c": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double, C.c_double,
                    C.c_double, C.c_double, C.c_double, _p(C.c_double), _p(C.c_double)],
+    "llr_beta_c_noalloc": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double,
+                           C.c_double, C.c_double, C.c_double, C.c_double, _p(C.c_double), _p(C.c_double)],
     "llr_prob_density": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double,
                          _p(C.c_double), C.c_int, _p(C.c_double)],
     "llr_prob_peaks": [C.c_void_p, _p(C.c_double), _p(C.c_double), C.c_int, C.c_double, C.c_double, C.c_int,
@@ -401,6 +403,15 @@ class Context:
         bc, pk = C.c_double(), C.c_double()
         _check(lib().llr_beta_c(self.h, _ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, six_v, blo, bhi, h,
                                 tol, C.byref(bc), C.byref(pk)))
+        return bc.value, pk.value
+
+    def beta_c_noalloc(self, centres, a, s, six_v, blo, bhi, h=1e-5, tol=1e-9):
+        """beta_c through the allocation-free entry point (fixed 1 MiB device
+        buffer per GPU; see llr_beta_c_noalloc)."""
+        c, a = _arr(centres, np.float64), _arr(a, np.float64)
+        bc, pk = C.c_double(), C.c_double()
+        _check(lib().llr_beta_c_noalloc(self.h, _ptr(c, C.c_double), _ptr(a, C.c_double), a.size, s, six_v, blo, bhi,
+                                        h, tol, C.byref(bc), C.byref(pk)))
         return bc.value, pk.value
 
     def prob_density(self, centres, a, s, beta, E):
