@@ -22,6 +22,17 @@ on the same staples, which is again a von Mises draw: an accepted heatbath
 class gives its links one update, a rejected one gives the rejected proposal
 and one overrelaxation.  Its count is (2 - acceptance) x V/2 per class pass,
 with the heatbath class acceptance measured over the timed steps.
+
+The metric's second half (rm_sweeps_plain_vs_mlp in the JSON line): Robbins-
+Monro sweeps to the stopping rule |a^(n+1) - a^(n)| < 1e-4 on the same
+interval set, from a^(0) = 1 and from the warm start of the network trained
+in this run by the library's kernels on converged a_k of L = 8, 12, 16
+(paper_1509_08391_amd/warmstart/), and the time to accuracy against the
+long-run reference slopes stored there; --m2-iters-plain and --m2-iters-mlp iterations.
+
+cpu_baseline: the CPU oracle (FP64, OpenMP over chains) timed on restricted
+sweeps of L=20 chains inside intervals of the benchmark's width, on all host
+cores and on one.
 """
 import argparse
 import json
@@ -48,33 +59,135 @@ PEAK_HBM_GBS = 8000.0
 HB_TRAFFIC = {("fp32", 4, "grouped"): 374.0e6, ("fp32", 4, "interleaved"): 408.0e6}
 
 
-def cpu_baseline(order, target_s=12.0):
+WARMSTART = os.path.join(ROOT, "paper_1509_08391_amd", "warmstart")
+
+
+def _a_ref():
+    with open(os.path.join(WARMSTART, "aref_L20.json")) as f:
+        return json.load(f)
+
+
+def cpu_baseline(order, target_s=10.0):
     """The oracle (plain FP64 C, OpenMP over chains) on a bounded sample of the
-    same workload: one L=20 chain per thread from the oracle's hot start,
-    sweeps (heatbath + overrelaxation, in the given order) until ~target_s
-    seconds of CPU work."""
+    same workload: restricted sweeps (8 heatbath + 8 overrelaxation passes)
+    of L=20 chains whose energies lie inside their intervals.  The states come
+    from the seeded input generator (plaquette densities spread over the
+    intervals' range u in [0.60, 0.664]); each chain is restricted to an
+    interval of the benchmark's width 2 dE centred on its energy, at the
+    reference a_k of the interval nearest that energy; one untimed sweep
+    first.  All cores: one chain per thread; one core: a single chain."""
     import oracle
+    from tests.inputs import random_state
     oracle.build(force=False)
     threads = oracle.num_threads()
-    nch = threads
-    th = oracle.hot_start(4, L, nch, SEED)
-    E = np.array([oracle.energy(4, L, th[i]) for i in range(nch)])
-    a = np.full(nch, 1.0)
-    lo, hi = np.full(nch, -1e9), np.full(nch, 1e9)
-    done = 0
+    V6 = 6 * L ** 4
+    dE = 0.0005 * V6
+    ref = _a_ref()
+    cen = np.array(ref["E_low"]) + 0.5 * dE
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
+
+    def run(nch, budget):
+        th = np.ascontiguousarray(np.concatenate(
+            [random_state(4, L, 1, seed=SEED + k, u_target=0.60 + 0.064 * (k + 0.5) / nch) for k in range(nch)]))
+        E = np.array([oracle.energy(4, L, th[k]) for k in range(nch)])
+        a = np.interp(E, cen, ref["a_ref"])
+        lo, hi = E - dE, E + dE
+        itv = np.arange(nch)
+        E, _ = oracle.sweeps(4, L, th, a, lo, hi, itv, E, 1, 0, seed=SEED, order=o_order)
+        done = 0
+        t0 = time.perf_counter()
+        while True:
+            E, bits = oracle.sweeps(4, L, th, a, lo, hi, itv, E, 1, 1 + done, seed=SEED, order=o_order)
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        dt = time.perf_counter() - t0
+        assert np.all((E >= lo) & (E <= hi))
+        return 2.0 * 4 * L ** 4 * nch * done / dt, done, dt
+
+    v_all, n_all, t_all = run(threads, target_s)
+    v_one, n_one, t_one = run(1, 0.5 * target_s)
+    return {"value": v_all, "unit": "link updates/s", "cores": threads, "kind": "oracle",
+            "one_core": v_one,
+            "sample": f"restricted sweeps (8 heatbath + 8 overrelaxation passes, {order}) of L=20 chains inside "
+                      f"intervals of width 2 dE = {2 * dE:.0f} at the reference a_k: {n_all} sweep(s) of {threads} "
+                      f"chains, one per thread, in {t_all:.1f} s (all cores); {n_one} sweep(s) of one chain in "
+                      f"{t_one:.1f} s (one core, {v_one:.3e} updates/s)"}
+
+
+def rm_convergence(llr, n_plain, n_mlp):
+    """The metric's second half: Robbins-Monro sweeps to |a^(n+1) - a^(n)| <
+    1e-4 (the stopping rule of Sec. 2.4) on the full-pipeline interval set,
+    from the cold start a^(0) = 1 and from the warm start of the network
+    trained here with the library's kernels on the converged a_k of L = 8, 12,
+    16 (warmstart/train_ak.json; predictions that are non-finite or outside
+    the trained range fall back to a^(0) = 1).  Same seed, same GPU, N_RM =
+    n_plain and n_mlp.  Also the time to accuracy against the long-run reference
+    slopes (warmstart/aref_L20.json): the sweeps after which every a_k^(n)
+    stays within tol of a_ref for all later n of the run."""
+    with open(os.path.join(WARMSTART, "train_ak.json")) as f:
+        pts = np.array(json.load(f)["points"])
+    ref = _a_ref()
+    a_ref = np.array(ref["a_ref"])
+    u, il, a_tr = pts[:, 0], pts[:, 1], pts[:, 2]
+    V6 = 6 * L ** 4
+    dE = 0.0005 * V6
+    E_low = 0.60 * V6 + dE * np.arange(N_INT)
     t0 = time.perf_counter()
-    while True:
-        E, _ = oracle.sweeps(4, L, th, a, lo, hi, np.arange(nch), E, 1, done, mode=oracle.MODE_RESTRICTED,
-                             seed=SEED, order=oracle.SWEEP_INTERLEAVED if order == "interleaved"
-                             else oracle.SWEEP_GROUPED)
-        done += 1
-        if time.perf_counter() - t0 > target_s:
-            break
-    dt = time.perf_counter() - t0
-    upd = 2.0 * 4 * L ** 4 * nch * done
-    return {"value": upd / dt, "unit": "link updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} restricted sweep(s) (8 heatbath + 8 overrelaxation passes, {order}) of {nch} "
-                      f"L=20 chains, one per thread, from the oracle's hot start; {dt:.1f} s"}
+    c0 = llr.Context(precision=llr.FP32, device=0)
+    w, hist = c0.mlp_train(c0.mlp_init(SEED), u, il, a_tr, epochs=4000, lr=3e-3, bf16=True)
+    fit_rms = float(np.sqrt(np.mean((c0.mlp_predict(w, u, il, bf16=True) - a_tr) ** 2)))
+    c0.close()
+    t_train = time.perf_counter() - t0
+    margin = 0.1 * (a_tr.max() - a_tr.min())
+    nsw = 2500
+    out = {"n_rm": {"plain": n_plain, "mlp": n_mlp}, "eps": 1e-4, "training_points": int(len(pts)), "train_s": t_train,
+           "fit_rms": fit_rms, "a_ref_uncertainty_max": 2 * float(np.max(ref["half_difference"]))}
+    for name, n_iter in (("plain", n_plain), ("mlp", n_mlp)):
+        ctx = llr.Context(precision=llr.FP32, device=0)
+        ctx.set_params(n_th=500, n_a=2000, n_rm=n_iter, seed=SEED, replica_exchange=True, overlap=1.0,
+                       recompute_every=10, eps=1e-4, approach_cap=20000)
+        ctx.add_lattice(L, E_low, dE)
+        ctx.bind_state()
+        nf = 0
+        if name == "mlp":
+            a0, nf = ctx.mlp_warm_start(0, w, a_tr.min() - margin, a_tr.max() + margin)
+            out["mlp_error_vs_a_ref"] = {"max": float(np.max(np.abs(a0 - a_ref))),
+                                         "rms": float(np.sqrt(np.mean((a0 - a_ref) ** 2))), "fallbacks": int(nf)}
+        else:
+            a0 = np.full(N_INT, 1.0)
+            ctx.set_a(0, a0)
+        t1 = time.perf_counter()
+        ctx.hot_start()
+        ap = int(ctx.approach()[0])
+        ctx.rm_begin()
+        for it in range(n_iter):
+            ctx.rm_step(1)
+            if it % 5 == 4:
+                print(f"# {name} start: RM iteration {it + 1}/{n_iter}, {time.perf_counter() - t1:.0f} s",
+                      file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t1
+        a_fin, conv, conv_sw = ctx.get_a(0)
+        hist = ctx.get_history(0)
+        ctx.close()
+        ok = conv >= 0
+        r = {"approach_sweeps": ap, "wall_s": wall,
+             "intervals_converged": int(ok.sum()),
+             "sweeps_to_stop_total": int(conv_sw[ok].sum()),
+             "sweeps_to_stop_slowest": int(conv_sw[ok].max()) if ok.any() else None,
+             "mean_iteration_of_stop": float(conv[ok].mean()) if ok.any() else None,
+             "final_error_vs_a_ref": {"max": float(np.max(np.abs(a_fin - a_ref))),
+                                      "rms": float(np.sqrt(np.mean((a_fin - a_ref) ** 2)))}}
+        for tol in (1e-3, 3e-4):
+            bad = np.abs(hist - a_ref[None, :]) >= tol          # rows n = 0..n_iter
+            last_bad = np.where(bad.any(axis=1))[0]
+            n_ok = 0 if last_bad.size == 0 else int(last_bad[-1]) + 1
+            r[f"sweeps_to_within_{tol:g}_of_a_ref"] = ap + n_ok * nsw if n_ok <= n_iter else None
+        out[name] = r
+    p, m = out["plain"], out["mlp"]
+    if p["sweeps_to_stop_total"] and m["sweeps_to_stop_total"]:
+        out["stop_sweeps_ratio_plain_over_mlp"] = p["sweeps_to_stop_total"] / m["sweeps_to_stop_total"]
+    return out
 
 
 def main():
@@ -84,6 +197,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--m2-iters-plain", type=int, default=40,
+                    help="Robbins-Monro iterations of the convergence run from a^(0) = 1")
+    ap.add_argument("--m2-iters-mlp", type=int, default=20,
+                    help="Robbins-Monro iterations of the convergence run from the network's warm start")
+    ap.add_argument("--no-m2", action="store_true", help="skip the plain-vs-network convergence runs")
     ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped")
     ap.add_argument("--n-th", type=int, default=500)
     ap.add_argument("--n-a", type=int, default=2000)
@@ -186,7 +304,7 @@ def main():
     achieved = bytes_per_hb_launch / hb_avg_s / 1e9 if hb_avg_s > 0 else 0.0
     or_avg_s = tm["or_ms"] / max(tm["or_n"], 1) / 1e3
     out = {
-        "metric": "link updates/s at 20^4x128 intervals",
+        "metric": "link updates/s at 20^4x128 intervals; RM sweeps to |da_k|<1e-4, plain vs MLP",
         "value": value,
         "unit": "link updates/s",
         "n_gpus": 1,
@@ -215,6 +333,9 @@ def main():
                        "replica_exchange": float(ra / max(rp, 1))},
         "approach_sweeps": int(ap_sweeps[0]),
     }
+    ctx.close()
+    if not args.no_m2 and args.precision == "fp32":
+        out["rm_sweeps_plain_vs_mlp"] = rm_convergence(llr, args.m2_iters_plain, args.m2_iters_mlp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.order)
     print(json.dumps(out))

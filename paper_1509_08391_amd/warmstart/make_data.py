@@ -15,9 +15,11 @@ is this library's own output:
     their mean is the reference against which the benchmark times both
     starts, their difference its uncertainty.
 
-All runs FP32 angles with FP64 energies, grouped sweep order, seed 1509083910
-(+1 for the second reference run).  Usage (on a GPU):
-    python -m paper_1509_08391_amd.warmstart.make_data
+All runs FP32 angles with FP64 energies, grouped sweep order.  The training
+runs use seed 1509083910; the reference runs seeds 1509083910 + 101 and
++ 102, so that they share no random numbers with the benchmark's runs (seed
+1509083910).  Usage (on a GPU), --reference-only to keep train_ak.json:
+    python -m paper_1509_08391_amd.warmstart.make_data [--reference-only]
 """
 import json
 import os
@@ -36,6 +38,7 @@ from paper_1509_08391_amd import llr  # noqa: E402
 
 SEED = 1509083910
 EPOCHS, LR = 4000, 3e-3
+REF_SEEDS = (SEED + 101, SEED + 102)
 
 
 def log(msg):
@@ -78,9 +81,9 @@ def train(pts):
 def reference(w, a_lo, a_hi, n_rm=60):
     L, E_low, dE = ex.config4_intervals()
     runs = []
-    for k in range(2):
+    for k, seed in enumerate(REF_SEEDS):
         ctx = llr.Context(precision=llr.FP32, device=0)
-        ctx.set_params(n_th=500, n_a=2000, n_rm=n_rm, seed=SEED + k, replica_exchange=True, overlap=1.0,
+        ctx.set_params(n_th=500, n_a=2000, n_rm=n_rm, seed=seed, replica_exchange=True, overlap=1.0,
                        recompute_every=10, eps=1e-4, approach_cap=20000)
         ctx.add_lattice(L, E_low, dE)
         ctx.bind_state()
@@ -94,7 +97,7 @@ def reference(w, a_lo, a_hi, n_rm=60):
             if it % 10 == 9:
                 log(f"reference run {k}: RM iteration {it + 1}/{n_rm}, {time.perf_counter() - t0:.0f} s")
         a, conv, _ = ctx.get_a(0)
-        runs.append(dict(seed=SEED + k, a=a.tolist(), a0=a0.tolist(), fallbacks=nf,
+        runs.append(dict(seed=seed, a=a.tolist(), a0=a0.tolist(), fallbacks=nf,
                          a_hist_last11=ctx.get_history(0)[-11:].tolist()))
         ctx.close()
     A = np.array([r["a"] for r in runs])
@@ -103,15 +106,21 @@ def reference(w, a_lo, a_hi, n_rm=60):
 
 
 def main():
-    pts, metas = training_points()
+    path = os.path.join(HERE, "train_ak.json")
+    if "--reference-only" in sys.argv[1:]:
+        with open(path) as f:
+            pts = [tuple(p) for p in json.load(f)["points"]]
+        w, rms = train(pts)
+    else:
+        pts, metas = training_points()
+        w, rms = train(pts)
+        with open(path, "w") as f:
+            json.dump(dict(points=pts, seed=SEED, epochs=EPOCHS, lr=LR, fit_rms=rms,
+                           runs=[{k: m[k] for k in ("precision", "n_th", "n_a", "n_rm", "replica", "sweep_order")}
+                                 for m in metas],
+                           made_by="python -m paper_1509_08391_amd.warmstart.make_data"), f, indent=1)
     a = np.array([p[2] for p in pts])
-    w, rms = train(pts)
     log(f"{len(pts)} training points, a in [{a.min():.5f}, {a.max():.5f}], fit rms {rms:.2e}")
-    with open(os.path.join(HERE, "train_ak.json"), "w") as f:
-        json.dump(dict(points=pts, seed=SEED, epochs=EPOCHS, lr=LR, fit_rms=rms,
-                       runs=[{k: m[k] for k in ("precision", "n_th", "n_a", "n_rm", "replica", "sweep_order")}
-                             for m in metas],
-                       made_by="python -m paper_1509_08391_amd.warmstart.make_data"), f, indent=1)
     margin = 0.1 * (a.max() - a.min())
     ref = reference(w, a.min() - margin, a.max() + margin)
     hd = np.array(ref["half_difference"])
