@@ -183,8 +183,10 @@ static void set_tiles(LatTable& lt, int hb_lpt, int or_lpt) {
     int hb0 = 0, or0 = 0;
     for (int i = 0; i < lt.n; ++i) {
         LatDev& d = lt.l[i];
-        d.hb_bpc = (int)((d.V2 + (uint32_t)(kBlock * hb_lpt) - 1) / (uint32_t)(kBlock * hb_lpt));
-        d.or_bpc = (int)((d.V2 + (uint32_t)(kBlock * or_lpt) - 1) / (uint32_t)(kBlock * or_lpt));
+        // column tiles: npt position tiles of the (x0h, x1, x2) slab times
+        // ceil(L / LPT) groups of consecutive x3
+        d.hb_bpc = d.npt * ((d.L + hb_lpt - 1) / hb_lpt);
+        d.or_bpc = d.npt * ((d.L + or_lpt - 1) / or_lpt);
         d.hb_block0 = hb0;
         d.or_block0 = or0;
         hb0 += d.n_chains * d.hb_bpc;
@@ -209,6 +211,8 @@ static llr_status layout(llr_ctx* c) {
         d.hL = h.L / 2;
         const long long V = (long long)h.L * h.L * h.L * h.L;
         d.V2 = (uint32_t)(V / 2);
+        d.P = d.V2 / (uint32_t)h.L;
+        d.npt = (int)((d.P + kBlock - 1) / kBlock);
         d.mL = magic((uint32_t)h.L);
         d.mhL = magic((uint32_t)(h.L / 2));
         d.n_chains = h.n;

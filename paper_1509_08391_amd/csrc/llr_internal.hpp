@@ -17,8 +17,10 @@ struct LatDev {
     uint32_t mL, mhL;      // ceil(2^32 / L), ceil(2^32 / (L/2))
     int n_chains;          // = number of intervals
     int chain0;            // first global chain index (= first global interval index)
-    int hb_bpc, hb_block0; // heatbath pass: blocks per chain (V/2 / (256 LPT), rounded up), first block
+    int hb_bpc, hb_block0; // heatbath pass: blocks per chain (npt x ceil(L / LPT)), first block
     int or_bpc, or_block0; // overrelaxation pass: the same
+    uint32_t P;            // positions in the (x0h, x1, x2) slab: hL L^2 = V/(2L); h = pos + P x3
+    int npt;               // position tiles of kBlock per slab, ceil(P / kBlock)
     int ebpc;              // blocks per chain in the site kernels (2 x V/2 / 256, rounded up)
     int hstr[4];           // half-index stride of a step along nu = 1..3: (L/2) L^(nu-1); [0] unused
     int hwrap[4];          // (L - 1) hstr[nu]: the periodic jump across the boundary

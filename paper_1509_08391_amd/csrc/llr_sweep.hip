@@ -48,6 +48,44 @@ __device__ __forceinline__ void decode_half(const LatDev& L, uint32_t h, int p, 
     x[3] = (int)r3;
     x[0] = 2 * x0h + ((p + x[1] + x[2] + x[3]) & 1);
 }
+// Column tiles of the class passes.  The half index is h = pos + P x3 with
+// pos = x0h + hL (x1 + L x2) the position in the (x0h, x1, x2) slab and
+// P = hL L^2 its size, and the class's sites at one position and
+// consecutive x3 alternate between x0 = 2 x0h and 2 x0h + 1 (the parity of
+// x1 + x2 + x3 flips).  A tile is kBlock positions by LPT consecutive x3:
+// thread tid owns position pos = pt kBlock + tid and x3 = xg LPT + r,
+// r = 0..LPT-1, so its links share x0h, x1, x2 and the offsets along
+// x1, x2, while x3 and its offsets are uniform over the wavefront.
+struct ColTile {
+    uint32_t pos;   // position in the slab (valid if < P)
+    int x0h, x1, x2;
+    int x3_0;       // x3 of the thread's first link
+};
+template <int LPT>
+__device__ __forceinline__ ColTile col_tile(const LatDev& L, int tile, int tid) {
+    ColTile t;
+    const int xg = tile / L.npt;
+    const int pt = tile - xg * L.npt;
+    t.pos = (uint32_t)pt * kBlock + (uint32_t)tid;
+    t.x3_0 = xg * LPT;
+    const uint32_t r1 = L.hL == 1 ? t.pos : fdiv(t.pos, L.mhL);
+    t.x0h = (int)(t.pos - r1 * (uint32_t)L.hL);
+    const uint32_t r2 = fdiv(r1, L.mL);
+    t.x1 = (int)(r1 - r2 * (uint32_t)L.L);
+    t.x2 = (int)r2;
+    return t;
+}
+// coordinates and half index of link r of the thread's column (in the
+// lattice iff pos < P and x3 < L)
+__device__ __forceinline__ bool col_link(const LatDev& L, const ColTile& t, int r, int p, int x[4], uint32_t& h) {
+    const int x3 = t.x3_0 + r;
+    x[1] = t.x1;
+    x[2] = t.x2;
+    x[3] = x3;
+    x[0] = 2 * t.x0h + ((p + t.x1 + t.x2 + x3) & 1);
+    h = t.pos + L.P * (uint32_t)x3;
+    return t.pos < L.P && x3 < L.L;
+}
 __device__ __forceinline__ uint32_t half_of(const LatDev& L, int y0, int y1, int y2, int y3) {
     return (uint32_t)((y0 >> 1) + L.hL * (y1 + L.L * (y2 + L.L * y3)));
 }
@@ -106,8 +144,6 @@ __device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_
     const int q = p ^ 1;
     const T* pmu_q = plane_ptr(chain, curw, 2 * MU + q, L.V2);
     const uint32_t h_pmu = h + up[MU];
-    C = T(0);
-    S = T(0);
 #pragma unroll
     for (int NU = 0; NU < 4; ++NU) {
         if (NU == MU) continue;
@@ -127,8 +163,13 @@ __device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_
         T s1, c1, s2, c2;
         M::sincos_rad(sf, &s1, &c1);
         M::sincos_rad(sb, &s2, &c2);
-        C += c1 + c2;
-        S += s1 + s2;
+        if (NU == (MU == 0 ? 1 : 0)) {   // the first direction seeds the sums
+            C = c1 + c2;
+            S = s1 + s2;
+        } else {
+            C += c1 + c2;
+            S += s1 + s2;
+        }
     }
 }
 
@@ -176,11 +217,22 @@ __device__ __forceinline__ void vm_constants(T ak, T& q, T& rm1, T& kg2) {
         const T tau = T(1) + M::sqrt_(T(1) + T(4) * ak * ak);
         const T D = tau + M::sqrt_(T(2) * tau);
         const T dm = D - T(2) * ak, dp = D + T(2) * ak;
-        const T r1 = M::div_(T(1), T(4) * ak * D);
-        rm1 = dm * dm * r1;
-        const T gg = dm * dp * r1;
-        kg2 = ak * gg * gg;
-        q = M::div_(dm, dp);
+        if constexpr (M::f32) {
+            // 1/(4 ak D) and 1/dp from one reciprocal of their product
+            const T fd = T(4) * ak * D;
+            const T t = M::div_(T(1), fd * dp);
+            const T r1 = dp * t;
+            rm1 = dm * dm * r1;
+            const T gg = dm * dp * r1;
+            kg2 = ak * gg * gg;
+            q = dm * (fd * t);
+        } else {
+            const T r1 = M::div_(T(1), T(4) * ak * D);
+            rm1 = dm * dm * r1;
+            const T gg = dm * dp * r1;
+            kg2 = ak * gg * gg;
+            q = M::div_(dm, dp);
+        }
     }
 }
 
@@ -194,7 +246,12 @@ __device__ __forceinline__ bool vm_attempt(uint32_t wa, uint32_t wb, T q, T rm1,
     const T U2 = M::unif(wb);
     const T cc = M::div_(kg2, M::fma_(T(2) * c_, c_, rm1));   // kappa (r^2 - 1)/(r + z)
     bool acc = M::fma_(cc, T(2) - cc, -U2) > T(0);
-    if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
+    if constexpr (M::f32) {
+        // ln(c/U2) + 1 - c >= 0 as c >= U2 e^(c - 1): one transcendental
+        if (!acc) acc = cc >= U2 * __builtin_amdgcn_exp2f(M::fma_(cc, 1.44269504088896341f, -1.44269504088896341f));
+    } else {
+        if (!acc) acc = M::log_(M::div_(cc, U2)) + T(1) - cc >= T(0);
+    }
     if (acc) { ch = c_; sh = q * s_; }
     return acc;
 }
@@ -299,7 +356,7 @@ __device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, d
 // theta' is formed as arg[(cos(pi V1/2) + i q sin(pi V1/2))^2 (C - i S)], and
 // the new local action is R cos X.
 //
-// Each thread owns LPT class links of a tile of kBlock * LPT links (all their
+// Each thread owns the LPT class links of its column in a tile (all their
 // loads are issued before the arithmetic).  Sampler schedule: every link
 // tries attempts 0 and 1 (one Philox call); the few links that reject both
 // are queued in LDS and later rounds give each queued link its next two
@@ -308,16 +365,14 @@ __device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, d
 // accepted attempt in order.
 // ---------------------------------------------------------------------------
 template <typename T, int MU, int LPT, int VAR>
-__global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
-                                               int kind, uint32_t k0, uint32_t k1, int reverse) {
+__device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th, const DevState& s, int parity,
+                                         int mode, int kind, uint32_t k0, uint32_t k1, int b) {
     using M = Math<T>;
     constexpr int NT = kBlock * LPT;
     __shared__ T s_q[NT], s_rm1[NT], s_kg2[NT], s_ch[NT], s_sh[NT];
     __shared__ unsigned char s_res[NT];
     __shared__ short s_queue[2][NT];
     __shared__ int s_qn[2];
-    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int b = reverse ? (int)gridDim.x - 1 - b0 : b0;
     int li = 0;
 #pragma unroll 1
     while (li + 1 < lt.n && b >= lt.l[li + 1].hb_block0) ++li;
@@ -343,18 +398,19 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     // state as it is and writes both angles into the non-current plane
     T* pinpl = mode == kModeTune ? chain + (size_t)((own ^ 1) * 8 + colour) * L.V2 : pcur;
     T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
-    const uint32_t hbase = (uint32_t)tile * NT;
+    const ColTile ct = col_tile<LPT>(L, tile, tid);
 
     T C[LPT], S[LPT], t_old[LPT];
+    uint32_t hl[LPT];
+    bool in[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
-        const uint32_t h = hbase + r * kBlock + tid;
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
-        if (h < L.V2) {
-            int x[4];
-            decode_half(L, h, parity, x);
-            staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
-            t_old[r] = ld_plane(pown, h);
+        int x[4];
+        in[r] = col_link(L, ct, r, parity, x, hl[r]);
+        if (in[r]) {
+            staples<T, MU>(L, chain, curw, x, parity, hl[r], C[r], S[r]);
+            t_old[r] = ld_plane(pown, hl[r]);
         }
     }
     if (tid == 0) s_qn[0] = 0;
@@ -363,12 +419,12 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     bool got[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
-        const uint32_t h = hbase + r * kBlock + tid;
+        const uint32_t h = hl[r];
         const int e = r * kBlock + tid;
         got[r] = true;
         ch[r] = T(1); sh[r] = T(0); eps_old[r] = T(0); R[r] = T(0); kap[r] = T(0);
         t_or_old[r] = T(0);
-        if (h < L.V2) {
+        if (in[r]) {
             T so, co;
             M::sincos_rad(t_old[r], &so, &co);
             eps_old[r] = fms2(C[r], co, S[r], so);
@@ -406,7 +462,10 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         __syncthreads();
         for (int i = tid; i < n; i += kBlock) {
             const int e = s_queue[cq][i];
-            const uint4 w = philox10(make_uint4(hbase + e, c1base | (uint32_t)m, sweep, c3), k0, k1);
+            // queue entry e = r kBlock + tid: link r of thread tid
+            const uint32_t he = ct.pos - (uint32_t)tid + (uint32_t)(e & (kBlock - 1)) +
+                                L.P * (uint32_t)(ct.x3_0 + e / kBlock);
+            const uint4 w = philox10(make_uint4(he, c1base | (uint32_t)m, sweep, c3), k0, k1);
             const T qe = s_q[e], rme = s_rm1[e], kge = s_kg2[e];
             T che = T(1), she = T(0);
             bool acc = vm_attempt(w.x, w.y, qe, rme, kge, che, she);
@@ -426,8 +485,8 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
     int fx32 = 0;   // FP32: the thread's class links at 2^-25 (|dE| <= 12 per link, LPT <= 4)
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
-        const uint32_t h = hbase + r * kBlock + tid;
-        if (h >= L.V2) continue;
+        const uint32_t h = hl[r];
+        if (!in[r]) continue;
         const int e = r * kBlock + tid;
         bool ok = got[r];
         T c_ = ch[r], s_ = sh[r];
@@ -506,6 +565,13 @@ __global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, 
         }
         atomicExch(s.acc + g, 0ull);
     }
+}
+
+template <typename T, int MU, int LPT, int VAR>
+__global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
+                                               int kind, uint32_t k0, uint32_t k1, int reverse) {
+    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    hb_block<T, MU, LPT, VAR>(lt, th, s, parity, mode, kind, k0, k1, reverse ? (int)gridDim.x - 1 - b0 : b0);
 }
 
 // ---------------------------------------------------------------------------
@@ -802,12 +868,10 @@ __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict
 // LPT class links per thread.
 // ---------------------------------------------------------------------------
 template <typename T, int MU, int LPT>
-__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity, int to_alt,
-                                               int reverse) {
+__device__ __forceinline__ void or_block(const LatTable& lt, T* __restrict__ th, const DevState& s, int parity,
+                                         int to_alt, int b) {
     using M = Math<T>;
     constexpr int NT = kBlock * LPT;
-    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int b = reverse ? (int)gridDim.x - 1 - b0 : b0;
     int li = 0;
 #pragma unroll 1
     while (li + 1 < lt.n && b >= lt.l[li + 1].or_block0) ++li;
@@ -822,25 +886,32 @@ __global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, 
     T* pown = plane_ptr(chain, curw, colour, L.V2);
     // timing runs of the tuner write to the non-current plane (state unchanged)
     T* pout = to_alt ? chain + (size_t)(((((curw >> (8 * colour)) & 1ull) ^ 1ull) * 8ull) + colour) * L.V2 : pown;
-    const uint32_t hbase = (uint32_t)tile * NT;
+    const ColTile ct = col_tile<LPT>(L, tile, (int)threadIdx.x);
     T C[LPT], S[LPT], t_old[LPT];
+    uint32_t hl[LPT];
+    bool in[LPT];
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
-        const uint32_t h = hbase + r * kBlock + threadIdx.x;
         C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
-        if (h < L.V2) {
-            int x[4];
-            decode_half(L, h, parity, x);
-            staples<T, MU>(L, chain, curw, x, parity, h, C[r], S[r]);
-            t_old[r] = ld_plane(pown, h);
+        int x[4];
+        in[r] = col_link(L, ct, r, parity, x, hl[r]);
+        if (in[r]) {
+            staples<T, MU>(L, chain, curw, x, parity, hl[r], C[r], S[r]);
+            t_old[r] = ld_plane(pown, hl[r]);
         }
     }
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
-        const uint32_t h = hbase + r * kBlock + threadIdx.x;
-        if (h >= L.V2) continue;
-        st_plane(pout, h, or_angle(t_old[r], C[r], S[r]));
+        if (!in[r]) continue;
+        st_plane(pout, hl[r], or_angle(t_old[r], C[r], S[r]));
     }
+}
+
+template <typename T, int MU, int LPT>
+__global__ __launch_bounds__(kBlock) void k_or(LatTable lt, T* __restrict__ th, DevState s, int parity, int to_alt,
+                                               int reverse) {
+    const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    or_block<T, MU, LPT>(lt, th, s, parity, to_alt, reverse ? (int)gridDim.x - 1 - b0 : b0);
 }
 
 // ---------------------------------------------------------------------------
