@@ -57,7 +57,9 @@ __device__ __forceinline__ void decode_half(const LatDev& L, uint32_t h, int p, 
 // r = 0..LPT-1, so its links share x0h, x1, x2 and the offsets along
 // x1, x2, while x3 and its offsets are uniform over the wavefront.
 struct ColTile {
-    uint32_t pos;   // position in the slab (valid if < P)
+    uint32_t pos;   // position in the slab; a lane past the slab's end gets 0
+    uint32_t pos0;  // the tile's first position, pt kBlock
+    bool in_slab;   // the lane's position lies in the slab (pt kBlock + tid < P)
     int x0h, x1, x2;
     int x3_0;       // x3 of the thread's first link
 };
@@ -66,7 +68,12 @@ __device__ __forceinline__ ColTile col_tile(const LatDev& L, int tile, int tid) 
     ColTile t;
     const int xg = tile / L.npt;
     const int pt = tile - xg * L.npt;
-    t.pos = (uint32_t)pt * kBlock + (uint32_t)tid;
+    t.pos0 = (uint32_t)pt * kBlock;
+    const uint32_t pos = t.pos0 + (uint32_t)tid;
+    t.in_slab = pos < L.P;
+    // a lane past the slab computes (and discards) the links of position 0,
+    // so that its coordinates, neighbour offsets and addresses stay in range
+    t.pos = t.in_slab ? pos : 0u;
     t.x3_0 = xg * LPT;
     const uint32_t r1 = L.hL == 1 ? t.pos : fdiv(t.pos, L.mhL);
     t.x0h = (int)(t.pos - r1 * (uint32_t)L.hL);
@@ -74,17 +81,6 @@ __device__ __forceinline__ ColTile col_tile(const LatDev& L, int tile, int tid) 
     t.x1 = (int)(r1 - r2 * (uint32_t)L.L);
     t.x2 = (int)r2;
     return t;
-}
-// coordinates and half index of link r of the thread's column (in the
-// lattice iff pos < P and x3 < L)
-__device__ __forceinline__ bool col_link(const LatDev& L, const ColTile& t, int r, int p, int x[4], uint32_t& h) {
-    const int x3 = t.x3_0 + r;
-    x[1] = t.x1;
-    x[2] = t.x2;
-    x[3] = x3;
-    x[0] = 2 * t.x0h + ((p + t.x1 + t.x2 + x3) & 1);
-    h = t.pos + L.P * (uint32_t)x3;
-    return t.pos < L.P && x3 < L.L;
 }
 __device__ __forceinline__ uint32_t half_of(const LatDev& L, int y0, int y1, int y2, int y3) {
     return (uint32_t)((y0 >> 1) + L.hL * (y1 + L.L * (y2 + L.L * y3)));
@@ -130,34 +126,72 @@ __device__ __forceinline__ void neighbour_offsets(const LatDev& L, const int x[4
     }
 }
 
+// Neighbour offsets of a thread's column (see col_tile), split into a
+// per-lane part along x0, x1, x2 and a wavefront-uniform part along x3:
+//   v_up[d], v_dn[d] (d < 3): half-index offsets of x +- d within the slab,
+//   for the thread's links with x0 = 2 x0h + b[k], k = r & 1 (the parity of
+//   x0 alternates along the column); v_up[3] = v_dn[3] = 0;
+//   the offsets along x3 and the link's own shift P x3 are uniform and are
+//   added to the plane's base address.
+struct ColNbr {
+    int up0[2], dn0[2];   // along x0 for the column's even / odd links
+    int up1, dn1, up2, dn2;
+};
+__device__ __forceinline__ ColNbr col_nbr(const LatDev& L, const ColTile& t, int p) {
+    ColNbr n;
+    const int b0 = (p + t.x1 + t.x2 + t.x3_0) & 1;   // x0 = 2 x0h + b0 for the even links
+    const int uo = t.x0h == L.hL - 1 ? 1 - L.hL : 1;  // x0 odd: the partner site 2 x0h + 2 (periodic)
+    const int de = t.x0h == 0 ? L.hL - 1 : -1;        // x0 even: the partner site 2 x0h - 1 (periodic)
+    n.up0[0] = b0 ? uo : 0;
+    n.dn0[0] = b0 ? 0 : de;
+    n.up0[1] = b0 ? 0 : uo;
+    n.dn0[1] = b0 ? de : 0;
+    n.up1 = t.x1 == L.L - 1 ? -L.hwrap[1] : L.hstr[1];
+    n.dn1 = t.x1 == 0 ? L.hwrap[1] : -L.hstr[1];
+    n.up2 = t.x2 == L.L - 1 ? -L.hwrap[2] : L.hstr[2];
+    n.dn2 = t.x2 == 0 ? L.hwrap[2] : -L.hstr[2];
+    return n;
+}
+
 // Local field of link (MU, x): staples of the 2 x 3 plaquettes containing it,
 // each oriented so that theta_MU(x) enters with a plus sign:
 //   forward  s_f = th_nu(x+mu) - th_mu(x+nu) - th_nu(x)
 //   backward s_b = th_nu(x-nu) - th_nu(x+mu-nu) - th_mu(x-nu)
-// C + i S = sum of e^{i s}.
-template <typename T, int MU>
-__device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_t curw, const int x[4], int p,
-                                        uint32_t h, T& C, T& S) {
+// C + i S = sum of e^{i s}.  The link sits at slab position pos (per lane) and
+// x3 = x3 (uniform); K = x3 parity relative to the column's first link selects
+// the x0 offsets.  Every neighbour's half index is pos + (per-lane offset
+// along x0..x2) + (uniform: P x3 and the offset along x3).
+// UB: the uniform part of every index goes into the plane's base address (a
+// scalar 64-bit add per plane and link: the cheaper form when scalar
+// registers are free); otherwise it is added to the per-lane 32-bit index.
+template <bool UB, typename T>
+__device__ __forceinline__ T ld_col(const T* plane, int uni, uint32_t lane) {
+    if constexpr (UB) return ld_plane(plane + uni, lane);
+    else return ld_plane(plane, lane + (uint32_t)uni);
+}
+
+template <typename T, int MU, int K, bool UB>
+__device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_t curw, int p, uint32_t pos,
+                                        const ColNbr& nb, int x3, T& C, T& S) {
     using M = Math<T>;
-    int up[4], dn[4];
-    neighbour_offsets(L, x, up, dn);
+    const int vu[4] = {nb.up0[K], nb.up1, nb.up2, 0};
+    const int vd[4] = {nb.dn0[K], nb.dn1, nb.dn2, 0};
+    const int sh = (int)L.P * x3;   // the link's own x3, uniform
+    const int su[4] = {sh, sh, sh, sh + (x3 == L.L - 1 ? -L.hwrap[3] : L.hstr[3])};
+    const int sd[4] = {0, 0, 0, x3 == 0 ? L.hwrap[3] : -L.hstr[3]};
     const int q = p ^ 1;
     const T* pmu_q = plane_ptr(chain, curw, 2 * MU + q, L.V2);
-    const uint32_t h_pmu = h + up[MU];
 #pragma unroll
     for (int NU = 0; NU < 4; ++NU) {
         if (NU == MU) continue;
         const T* pnu_p = plane_ptr(chain, curw, 2 * NU + p, L.V2);
         const T* pnu_q = plane_ptr(chain, curw, 2 * NU + q, L.V2);
-        const uint32_t h_pnu = h + up[NU];
-        const uint32_t h_mnu = h + dn[NU];
-        const uint32_t h_pmu_mnu = h + up[MU] + dn[NU];
-        const T t_nu_pmu = ld_plane(pnu_q, h_pmu);
-        const T t_mu_pnu = ld_plane(pmu_q, h_pnu);
-        const T t_nu_x = ld_plane(pnu_p, h);
-        const T t_nu_pmu_mnu = ld_plane(pnu_p, h_pmu_mnu);
-        const T t_mu_mnu = ld_plane(pmu_q, h_mnu);
-        const T t_nu_mnu = ld_plane(pnu_q, h_mnu);
+        const T t_nu_pmu = ld_col<UB>(pnu_q, su[MU], pos + vu[MU]);
+        const T t_mu_pnu = ld_col<UB>(pmu_q, su[NU], pos + vu[NU]);
+        const T t_nu_x = ld_col<UB>(pnu_p, sh, pos);
+        const T t_nu_pmu_mnu = ld_col<UB>(pnu_p, su[MU] + sd[NU], pos + (vu[MU] + vd[NU]));
+        const T t_mu_mnu = ld_col<UB>(pmu_q, sh + sd[NU], pos + vd[NU]);
+        const T t_nu_mnu = ld_col<UB>(pnu_q, sh + sd[NU], pos + vd[NU]);
         const T sf = t_nu_pmu - t_mu_pnu - t_nu_x;
         const T sb = t_nu_mnu - t_nu_pmu_mnu - t_mu_mnu;
         T s1, c1, s2, c2;
@@ -169,6 +203,27 @@ __device__ __forceinline__ void staples(const LatDev& L, const T* chain, uint64_
         } else {
             C += c1 + c2;
             S += s1 + s2;
+        }
+    }
+}
+
+// Staples and old angle of the LPT links of the thread's column; hl, in: the
+// links' half indices and whether they lie in the lattice (pos < P, and
+// x3 < L, uniform over the wavefront).
+template <typename T, int MU, int LPT, bool UB>
+__device__ __forceinline__ void col_staples(const LatDev& L, const T* chain, uint64_t curw, int p, const ColTile& ct,
+                                            const ColNbr& nb, uint32_t pos, const T* pown, T* C, T* S, T* t_old,
+                                            uint32_t* hl, bool* in) {
+#pragma unroll
+    for (int r = 0; r < LPT; ++r) {
+        const int x3 = ct.x3_0 + r;
+        C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
+        hl[r] = pos + L.P * (uint32_t)x3;
+        in[r] = ct.in_slab && x3 < L.L;
+        if (x3 < L.L) {
+            if (r & 1) staples<T, MU, 1, UB>(L, chain, curw, p, pos, nb, x3, C[r], S[r]);
+            else staples<T, MU, 0, UB>(L, chain, curw, p, pos, nb, x3, C[r], S[r]);
+            t_old[r] = ld_col<UB>(pown, (int)L.P * x3, pos);
         }
     }
 }
@@ -399,20 +454,13 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
     T* pinpl = mode == kModeTune ? chain + (size_t)((own ^ 1) * 8 + colour) * L.V2 : pcur;
     T* palt = chain + (size_t)((own ^ 1) * 8 + colour) * L.V2;
     const ColTile ct = col_tile<LPT>(L, tile, tid);
+    const ColNbr nb = col_nbr(L, ct, parity);
+    const uint32_t pos = ct.pos;
 
     T C[LPT], S[LPT], t_old[LPT];
     uint32_t hl[LPT];
     bool in[LPT];
-#pragma unroll
-    for (int r = 0; r < LPT; ++r) {
-        C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
-        int x[4];
-        in[r] = col_link(L, ct, r, parity, x, hl[r]);
-        if (in[r]) {
-            staples<T, MU>(L, chain, curw, x, parity, hl[r], C[r], S[r]);
-            t_old[r] = ld_plane(pown, hl[r]);
-        }
-    }
+    col_staples<T, MU, LPT, false>(L, chain, curw, parity, ct, nb, pos, pown, C, S, t_old, hl, in);
     if (tid == 0) s_qn[0] = 0;
     T eps_old[LPT], R[LPT], kap[LPT], ch[LPT], sh[LPT];
     T t_or_old[LPT];   // fused pass: the old angle's overrelaxation, from the sine and cosine at hand
@@ -463,8 +511,7 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
         for (int i = tid; i < n; i += kBlock) {
             const int e = s_queue[cq][i];
             // queue entry e = r kBlock + tid: link r of thread tid
-            const uint32_t he = ct.pos - (uint32_t)tid + (uint32_t)(e & (kBlock - 1)) +
-                                L.P * (uint32_t)(ct.x3_0 + e / kBlock);
+            const uint32_t he = ct.pos0 + (uint32_t)(e & (kBlock - 1)) + L.P * (uint32_t)(ct.x3_0 + e / kBlock);
             const uint4 w = philox10(make_uint4(he, c1base | (uint32_t)m, sweep, c3), k0, k1);
             const T qe = s_q[e], rme = s_rm1[e], kge = s_kg2[e];
             T che = T(1), she = T(0);
@@ -887,19 +934,12 @@ __device__ __forceinline__ void or_block(const LatTable& lt, T* __restrict__ th,
     // timing runs of the tuner write to the non-current plane (state unchanged)
     T* pout = to_alt ? chain + (size_t)(((((curw >> (8 * colour)) & 1ull) ^ 1ull) * 8ull) + colour) * L.V2 : pown;
     const ColTile ct = col_tile<LPT>(L, tile, (int)threadIdx.x);
+    const ColNbr nb = col_nbr(L, ct, parity);
+    const uint32_t pos = ct.pos;
     T C[LPT], S[LPT], t_old[LPT];
     uint32_t hl[LPT];
     bool in[LPT];
-#pragma unroll
-    for (int r = 0; r < LPT; ++r) {
-        C[r] = T(0); S[r] = T(0); t_old[r] = T(0);
-        int x[4];
-        in[r] = col_link(L, ct, r, parity, x, hl[r]);
-        if (in[r]) {
-            staples<T, MU>(L, chain, curw, x, parity, hl[r], C[r], S[r]);
-            t_old[r] = ld_plane(pown, hl[r]);
-        }
-    }
+    col_staples<T, MU, LPT, true>(L, chain, curw, parity, ct, nb, pos, pown, C, S, t_old, hl, in);
 #pragma unroll
     for (int r = 0; r < LPT; ++r) {
         if (!in[r]) continue;
