@@ -95,6 +95,19 @@ SEED = 1509083910
 SWEEP_ORDER = llr.SWEEP_GROUPED
 
 
+def _updates_per_class_link(ctx, before):
+    """Link updates per class link and class pass since the stats() snapshot
+    `before`: 2 in the grouped order (one heatbath, one overrelaxation); in
+    the interleaved order the overrelaxation right after an accepted heatbath
+    of its class is a relabelled draw, so 1 for an accepted class and 2 (the
+    rejected proposal and one overrelaxation) for a rejected one."""
+    if SWEEP_ORDER != llr.SWEEP_INTERLEAVED:
+        return 2.0
+    hp, ha, _, _ = ctx.stats()
+    passes = float((hp - before[0]).sum())
+    return 2.0 - (float((ha - before[1]).sum()) / passes if passes > 0 else 0.0)
+
+
 def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None, eps=1e-4):
     """lattices: list of (L, E_low, dE).  a0: list of per-lattice arrays or None."""
     ctx = llr.Context(precision=prec, device=0)
@@ -117,6 +130,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
     t_ap = time.perf_counter() - t0
     tiles = ctx.autotune()
     ctx.rm_begin()
+    st0 = ctx.stats()
     t1 = time.perf_counter()
     t_log = t1
     for it in range(n_rm):
@@ -126,6 +140,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
             log(f"RM iteration {it + 1}/{n_rm}, {now - t1:.1f} s")
             t_log = now
     t_rm = time.perf_counter() - t1
+    per_link = _updates_per_class_link(ctx, st0)
     out = []
     for i, (L, E_low, dE) in enumerate(lattices):
         a, conv, sw = ctx.get_a(i)
@@ -136,7 +151,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
                         E=E.tolist()))
     hp, ha, rp, ra = ctx.stats()
     nsw = n_th + n_a
-    upd = sum(2 * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lattices) * nsw * n_rm
+    upd = sum(per_link * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lattices) * nsw * n_rm
     meta = dict(precision="fp32" if prec == llr.FP32 else "fp64", n_th=n_th, n_a=n_a, n_rm=n_rm, replica=replica,
                 sweep_order="interleaved" if SWEEP_ORDER == llr.SWEEP_INTERLEAVED else "grouped",
                 seed=seed, seconds_approach=t_ap, seconds_rm=t_rm, updates_per_s=upd / t_rm, tiles=list(tiles),
@@ -623,10 +638,11 @@ def batch_profile(log, n=200):
     ap = ctx.approach()
     tiles = ctx.autotune()
     ctx.sweeps(10, sweep0=1 << 20, mode=llr.MODE_RESTRICTED, want_bits=False)
+    st0 = ctx.stats()
     t0 = time.perf_counter()
     ctx.sweeps(n, sweep0=(1 << 20) + 16, mode=llr.MODE_RESTRICTED, want_bits=False)
     dt = (time.perf_counter() - t0) / n
-    upd = sum(2 * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lats)
+    upd = sum(_updates_per_class_link(ctx, st0) * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lats)
     ctx.close()
     log(f"{dt * 1e3:.3f} ms per sweep of 192 chains (L = 12, 16, 20), {upd / dt:.4g} link updates/s, "
         f"tiles {tiles}, approach sweeps {[int(x) for x in ap]}")
