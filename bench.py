@@ -30,6 +30,12 @@ in this run by the library's kernels on converged a_k of L = 8, 12, 16
 (paper_1509_08391_amd/warmstart/), and the time to accuracy against the
 long-run reference slopes stored there; --m2-iters-plain and --m2-iters-mlp iterations.
 
+The timed steps run with per-kernel HIP-event timing (which launches the
+sweeps eagerly); one more step after them replays the captured sweep graphs,
+the library's default path, and is reported as graph_replay.  health: chains
+flagged by the recompute's health tests and the largest drift of the
+incremental energy seen at a recompute.
+
 cpu_baseline: the CPU oracle (FP64, OpenMP over chains) timed on restricted
 sweeps of L=20 chains inside intervals of the benchmark's width, on all host
 cores and on one.
@@ -237,7 +243,7 @@ def main():
     dE = 0.0005 * V6
     E_low = 0.60 * V6 + dE * np.arange(N_INT)
     prec = llr.FP32 if args.precision == "fp32" else llr.FP64
-    n_rm = args.warmup + args.steps
+    n_rm = args.warmup + args.steps + 1   # + one step replayed from HIP graphs after the timed region
     ctx = llr.Context(precision=prec, device=0)
     ctx.set_params(n_th=args.n_th, n_a=args.n_a, n_rm=n_rm, seed=SEED, replica_exchange=True, overlap=1.0,
                    recompute_every=10, eps=1e-4, approach_cap=20000)
@@ -280,6 +286,17 @@ def main():
     tm = ctx.get_timing()
     hp, ha, rp, ra = ctx.stats()
     ctx.set_timing(False)
+    # the same work with the sweeps replayed from the captured HIP graphs (the
+    # library's default path; per-kernel event timing launches them eagerly)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    ctx.rm_step(1)
+    a, _, _ = ctx.get_a(0)
+    ctx.beta_c(centres, a, dE, V6, 1.008, 1.012, h=1e-5, tol=1e-9)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - tg0
+    rates = ctx.rates()
+    health_flags, drift = ctx.health()
 
     nsw = args.n_th + args.n_a
     dt = t1 - t0
@@ -329,9 +346,12 @@ def main():
                                else "heatbath + overrelaxation class pass (k_hb, fused)",
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
                      "overrelaxation_avg_launch_us": or_avg_s * 1e6},
-        "acceptance": {"heatbath_class": hb_acc_timed,
+        "acceptance": {"heatbath_class": hb_acc_timed, "overrelaxation": rates["or_acceptance"],
                        "replica_exchange": float(ra / max(rp, 1))},
         "approach_sweeps": int(ap_sweeps[0]),
+        "graph_replay": {"ms_per_step": t_graph * 1e3, "link_updates_per_s": updates / args.steps / t_graph},
+        "health": {"chains_flagged": int(np.count_nonzero(health_flags)),
+                   "max_recompute_drift": float(drift.max())},
     }
     ctx.close()
     if not args.no_m2 and args.precision == "fp32":

@@ -63,7 +63,7 @@ enum {
     LLR_EDEVICE = -3,           /* HIP runtime error */
     LLR_ESTATE = -4,            /* call out of order (e.g. state not bound) */
     LLR_EAPPROACH = -5,         /* approach cap reached before every chain entered its interval */
-    LLR_ENUMERIC = -6           /* non-finite value detected */
+    LLR_ENUMERIC = -6           /* non-finite value or failed health test (llr_health) */
 };
 
 enum { LLR_FP64 = 0, LLR_FP32 = 1 }; /* precision of link angles and local arithmetic;
@@ -210,15 +210,16 @@ llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double 
  *   - every angle of the bound state (both planes of each colour) and the
  *     current-plane bits;
  *   - per chain: E, the interval it serves, the approach couplings, the
- *     heatbath acceptance counts;
+ *     heatbath acceptance counts (plain and fused passes);
  *   - per interval: a_k, the chain serving it (replica exchange moves
  *     labels, not configurations), the running sum of measured energies of
  *     the open RM iteration, the convergence record and a^(n) so far;
  *   - the sweep and approach counter words, the RM iteration n, the
- *     replica-exchange counts, the sweep order, restriction and tiles.
+ *     replica-exchange counts, the sweep order, restriction and tiles, and
+ *     the counts and time of llr_get_rates.
  * A multicanonical weight (llr_muca_begin) is saved with its flag; the bits
- * log and the per-kernel timing are not saved.
- * File layout (little endian): "LLRCKPT1", u32 version 1, u32 precision,
+ * log, the per-kernel timing and the health flags (cleared) are not saved.
+ * File layout (little endian): "LLRCKPT1", u32 version 2, u32 precision,
  * u32 number of lattices, per lattice i32 L, i32 n, f64 dE, f64 E_low[n];
  * the llr_params fields in declaration order (i32, i32, i32, u64, i32, f64,
  * i32, f64, i32); tagged sections (u32 tag, u64 bytes, data); the CRC-32
@@ -298,6 +299,46 @@ llr_status llr_get_bits_log(llr_ctx *ctx, uint16_t *bits, long long *rows);
  * heatbath proposals/accepts; replica-exchange proposals/accepts (scalars). */
 llr_status llr_stats(llr_ctx *ctx, long long *hb_prop, long long *hb_acc, long long *re_prop,
                      long long *re_acc);
+
+/* Work done and rates since creation, summed over every chain.  A link update
+ * is one heatbath or one overrelaxation of one link (Algorithm 1 counts
+ * sweeps of the whole lattice; the local moves inside a sweep are this
+ * library's, the paper names none).  A heatbath class pass (approach passes
+ * included) updates the V/2 links of its class, accepted or not, since a
+ * rejected class is a valid move that keeps its links; an overrelaxation
+ * class pass updates V/2 links, except in the interleaved order after an
+ * accepted heatbath of the same class, where it reflects the fresh heatbath
+ * draw on unchanged staples: that is again a draw from the same conditional,
+ * so those passes are counted as relabelled, not as updates.  The
+ * overrelaxation keeps each link's local action, hence E, and is never
+ * rejected: or_acceptance is 1.  seconds is host wall time inside the calls
+ * that run sweeps (llr_run, llr_rm_step, llr_approach*, llr_sweeps,
+ * llr_class_pass, llr_muca_sweeps, llr_observables), each of which returns
+ * after the device has finished. */
+typedef struct {
+    long long sweeps;              /* full sweeps (llr_run, llr_rm_step, llr_sweeps, ...); approach not included */
+    long long hb_class_passes;     /* per chain, summed over chains */
+    long long hb_class_accepts;
+    long long or_class_passes;     /* per chain, summed over chains (fused ones included) */
+    long long or_class_relabelled; /* fused overrelaxation passes after an accepted heatbath class */
+    long long re_proposals, re_accepts;
+    double link_updates;
+    double seconds;
+    double link_updates_per_s;     /* link_updates / seconds */
+    double hb_acceptance, or_acceptance, re_acceptance;
+} llr_rates;
+llr_status llr_get_rates(llr_ctx *ctx, llr_rates *out);
+
+/* Runtime health of the chains, from the tests the FP64 energy recompute
+ * applies before it replaces a chain's incremental E:
+ * flags (host, one per chain, may be NULL) are sticky bits set since the last
+ * clear: 1 a link angle is not finite, 2 |E incremental - E recomputed|
+ * exceeded the drift bound (1e-5 x 6V with FP32 angles, 1e-9 x 6V in FP64),
+ * 4 in restricted sweeps the recomputed E lay outside the chain's restriction
+ * by more than that bound.  drift (host, per chain, may be NULL): the largest
+ * drift seen.  clear != 0 resets both.  Every call that runs sweeps returns
+ * LLR_ENUMERIC, after its work, while a flag is set. */
+llr_status llr_health(llr_ctx *ctx, uint32_t *flags, double *drift, int clear);
 /* Kernel timing with HIP events on the context stream: on/off, and the
  * summed duration (ms) and count of heatbath-pass, overrelaxation-pass and
  * energy launches since enabling.  The 8 heatbath (and the 8

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -116,6 +117,23 @@ struct llr_ctx {
     // device staging of small host arrays (grown on demand)
     void* stage = nullptr;
     size_t stage_bytes = 0;
+    // link-update accounting (llr_get_rates): class passes applied to every
+    // chain, counted as they are enqueued or replayed
+    bool capturing = false;        // a sweep is being captured into a graph, not run
+    long long sweeps_run = 0;      // full sweeps (any mode) since creation
+    long long or_passes = 0;       // plain overrelaxation class passes
+    long long fused_passes = 0;    // fused heatbath + overrelaxation class passes
+    double run_seconds = 0.0;      // host wall time inside the calls that run sweeps
+};
+
+// Wall time of one sweep-running call (each ends with a stream synchronisation).
+struct RunClock {
+    llr_ctx* c;
+    std::chrono::steady_clock::time_point t0;
+    explicit RunClock(llr_ctx* cc) : c(cc), t0(std::chrono::steady_clock::now()) {}
+    ~RunClock() {
+        if (c) c->run_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
 };
 
 static size_t elem_size(const llr_ctx* c) { return c->precision == LLR_FP32 ? 4 : 8; }
@@ -251,7 +269,8 @@ static llr_status layout(llr_ctx* c) {
 #define AL(field, cnt) \
     if ((st = dalloc(c, &s.field, (cnt))) != LLR_OK) return st;
     AL(E, n) AL(acc, n) AL(eacc, n) AL(oacc, n) AL(obs, n) AL(cur, 8 * n) AL(itv, n) AL(b, 8 * n) AL(eta, 8 * n)
-    AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(a, n) AL(lo, n) AL(hi, n)
+    AL(sprev, 8 * n) AL(bits, n + 2) AL(bits_last, n + 2) AL(hb_prop, n) AL(hb_acc, n) AL(fu_acc, n) AL(health, n)
+    AL(drift, n) AL(a, n) AL(lo, n) AL(hi, n)
     AL(cen, n) AL(w, n) AL(sumE, n) AL(conf, n) AL(conv_iter, n) AL(conv_sweeps, n) AL(mu_lnrho, n)
     AL(mu_b, kMaxLat) AL(link_fix, n) AL(link_arc, n)
     AL(lat_done, kMaxLat) AL(lat_outside, kMaxLat) AL(lat_approach, kMaxLat) AL(sweep_ctr, 1)
@@ -320,6 +339,28 @@ struct TimeScope {
     }
 };
 
+// ---------------------------------------------------------------- health
+// The energy recompute's sticky per-chain flags (kHealth*): LLR_ENUMERIC with
+// the first flagged chain named, the flags left set until llr_health clears
+// them.  Called at the end of the calls that run sweeps.
+static llr_status health_check(llr_ctx* c) {
+    const int n = c->lt.n_chains;
+    std::vector<uint32_t> f(n);
+    std::vector<double> d(n);
+    HIPCHK(hipMemcpy(f.data(), c->ds.health, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    for (int g = 0; g < n; ++g) {
+        if (!f[g]) continue;
+        HIPCHK(hipMemcpy(d.data(), c->ds.drift, 8 * (size_t)n, hipMemcpyDeviceToHost));
+        char msg[256];
+        snprintf(msg, sizeof msg, "chain %d failed a health test at an energy recompute:%s%s%s (largest drift %.3e)", g,
+                 (f[g] & kHealthNonFinite) ? " non-finite angle" : "",
+                 (f[g] & kHealthDrift) ? " incremental E drifted beyond the bound" : "",
+                 (f[g] & kHealthOutside) ? " E outside its restriction" : "", d[g]);
+        return fail(LLR_ENUMERIC, msg);
+    }
+    return LLR_OK;
+}
+
 // ---------------------------------------------------------------- sweep drivers
 template <typename T>
 static void enqueue_hb_pass(llr_ctx* c, int colour, int mode, int kind) {
@@ -331,15 +372,26 @@ static void enqueue_or_pass(llr_ctx* c, int colour) {
     launch_or_pass<T>(c->lt, (T*)c->state, c->ds, colour, 0, c->stream);
 }
 template <typename T>
-static void enqueue_energy(llr_ctx* c) {
+static void enqueue_energy(llr_ctx* c, int check = kCheckDrift) {
     TimeScope ts(c, 2);
-    launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream);
+    launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream, false, check);
+}
+
+// the overrelaxation class passes one sweep applies to every chain: 8
+// plain ones, or 8 fused into the heatbath passes
+static void note_sweep(llr_ctx* c, bool fused) {
+    if (c->capturing) return;
+    c->sweeps_run += 1;
+    if (fused) c->fused_passes += 8;
+    else c->or_passes += 8;
 }
 
 // one restricted sweep of all chains, then recompute / replica exchange / measurement
 template <typename T>
 static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bool measure) {
-    if (c->interleave && (mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_MUCA)) {
+    const bool fused = c->interleave && (mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_MUCA);
+    note_sweep(c, fused);
+    if (fused) {
         TimeScope ts(c, 0, 8);
         for (int col = 0; col < 8; ++col)
             launch_hb_or_pass<T>(c->lt, (T*)c->state, c->ds, col, mode, (uint32_t)c->prm.seed,
@@ -354,7 +406,8 @@ static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bo
             for (int col = 0; col < 8; ++col) enqueue_or_pass<T>(c, col);
         }
     }
-    if (recompute) enqueue_energy<T>(c);
+    if (recompute)
+        enqueue_energy<T>(c, kCheckDrift | (mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_LINK ? kCheckInterval : 0));
     if (replica) launch_replica(c->lt, c->ds, (uint32_t)c->prm.seed, (uint32_t)(c->prm.seed >> 32), c->stream);
     launch_end_sweep(c->lt, c->ds, measure ? 1 : 0, 0, 1, c->stream);
 }
@@ -389,7 +442,9 @@ static llr_status launch_sweep(llr_ctx* c, bool recompute, bool replica, bool me
         c->stream = c->cap_stream;
         hipError_t e0 = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e0 == hipSuccess) {
+            c->capturing = true;
             enqueue_sweep<T>(c, restricted_mode(c), recompute, replica, measure);
+            c->capturing = false;
             e0 = hipStreamEndCapture(c->stream, &g);
         }
         c->stream = user;
@@ -401,6 +456,7 @@ static llr_status launch_sweep(llr_ctx* c, bool recompute, bool replica, bool me
         c->sweep_graph[key] = ex;
     }
     HIPCHK(hipGraphLaunch(c->sweep_graph[key], c->stream));
+    note_sweep(c, c->interleave && restricted_mode(c) == LLR_MODE_RESTRICTED);
     return LLR_OK;
 }
 
@@ -516,7 +572,7 @@ static llr_status approach_continue_impl(llr_ctx* c, long long max_sweeps, int* 
     }
     HIPCHK(hipGetLastError());
     if (all_done) *all_done = all ? 1 : 0;
-    return LLR_OK;
+    return health_check(c);
 }
 
 template <typename T>
@@ -590,7 +646,7 @@ static llr_status rm_step_impl(llr_ctx* c, int iters) {
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     if (c->timing) harvest(c);
-    return LLR_OK;
+    return health_check(c);
 }
 
 static llr_status rm_converged(llr_ctx* c) {
@@ -625,7 +681,7 @@ static llr_status sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, int mo
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     if (c->timing) harvest(c);
-    return LLR_OK;
+    return health_check(c);
 }
 
 template <typename T>
@@ -642,7 +698,7 @@ static llr_status muca_sweeps_impl(llr_ctx* c, int n_sweeps, long long sweep0, d
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     if (c->timing) harvest(c);
-    return LLR_OK;
+    return health_check(c);
 }
 
 template <typename T>
@@ -661,7 +717,7 @@ static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sw
             enqueue_sweep<T>(c, restricted_mode(c), false, c->prm.replica_exchange != 0, false);
         {
             TimeScope ts(c, 2);
-            launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream, true);
+            launch_energy<T>(c->lt, (const T*)c->state, c->ds, c->stream, true, kCheckDrift | kCheckInterval);
         }
         HIPCHK(hipMemcpyAsync(E.data(), c->ds.E, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(B.data(), c->ds.obs, 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
@@ -674,7 +730,7 @@ static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sw
     }
     HIPCHK(hipGetLastError());
     if (c->timing) harvest(c);
-    return LLR_OK;
+    return health_check(c);
 }
 
 // ================================================================= C ABI
@@ -808,10 +864,10 @@ llr_status llr_hot_start(llr_ctx* c) {
     const uint32_t k0 = (uint32_t)c->prm.seed, k1 = (uint32_t)(c->prm.seed >> 32);
     if (c->precision == LLR_FP32) {
         launch_hot_start<float>(c->lt, (float*)c->state, c->ds, k0, k1, c->stream);
-        enqueue_energy<float>(c);
+        enqueue_energy<float>(c, 0);
     } else {
         launch_hot_start<double>(c->lt, (double*)c->state, c->ds, k0, k1, c->stream);
-        enqueue_energy<double>(c);
+        enqueue_energy<double>(c, 0);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
@@ -826,10 +882,10 @@ llr_status llr_import_state(llr_ctx* c, int lat, const void* dev) {
     HIPCHK(hipSetDevice(c->device));
     if (c->precision == LLR_FP32) {
         launch_import<float>(c->lt, lat, (float*)c->state, c->ds, (const float*)dev, c->stream);
-        enqueue_energy<float>(c);
+        enqueue_energy<float>(c, 0);
     } else {
         launch_import<double>(c->lt, lat, (double*)c->state, c->ds, (const double*)dev, c->stream);
-        enqueue_energy<double>(c);
+        enqueue_energy<double>(c, 0);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
@@ -852,6 +908,7 @@ llr_status llr_export_state(llr_ctx* c, int lat, void* dev) {
 }
 
 llr_status llr_approach(llr_ctx* c, long long* sweeps) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     HIPCHK(hipSetDevice(c->device));
@@ -866,6 +923,7 @@ llr_status llr_approach_begin(llr_ctx* c) {
 }
 
 llr_status llr_approach_continue(llr_ctx* c, long long max_sweeps, long long* sweeps, int* all_done) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (max_sweeps < 0) return fail(LLR_EINVAL, "max_sweeps < 0");
@@ -877,6 +935,7 @@ llr_status llr_approach_continue(llr_ctx* c, long long max_sweeps, long long* sw
 }
 
 llr_status llr_run(llr_ctx* c) {
+    RunClock clk(c);
     if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
@@ -893,6 +952,7 @@ llr_status llr_rm_begin(llr_ctx* c) {
 }
 
 llr_status llr_rm_step(llr_ctx* c, int iterations) {
+    RunClock clk(c);
     if (c) c->muca_ready = false;   // the multicanonical weights follow a_k
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
@@ -966,6 +1026,7 @@ static llr_status ensure_link_buffers(llr_ctx* c) {
 static bool sweep_mode_ok(int mode) { return mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_LINK; }
 
 llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint16_t* bits) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (n_sweeps < 0 || !(sweep_mode_ok(mode) || mode == LLR_MODE_APPROACH))
@@ -977,6 +1038,7 @@ llr_status llr_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, int mode, uint
 }
 
 llr_status llr_class_pass(llr_ctx* c, int heatbath, int colour, int mode, long long sweep_index) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (colour < 0 || colour > 7 || !(sweep_mode_ok(mode) || mode == LLR_MODE_APPROACH))
@@ -992,6 +1054,7 @@ llr_status llr_class_pass(llr_ctx* c, int heatbath, int colour, int mode, long l
         if (heatbath) enqueue_hb_pass<double>(c, colour, mode, kSweep);
         else enqueue_or_pass<double>(c, colour);
     }
+    if (!heatbath) c->or_passes += 1;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
     return LLR_OK;
@@ -1005,7 +1068,7 @@ llr_status llr_recompute_energy(llr_ctx* c) {
     else enqueue_energy<double>(c);
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
-    return LLR_OK;
+    return health_check(c);
 }
 
 llr_status llr_get_a(llr_ctx* c, int lat, double* a, int* conv_iter, long long* conv_sweeps) {
@@ -1113,6 +1176,65 @@ llr_status llr_stats(llr_ctx* c, long long* hb_prop, long long* hb_acc, long lon
     HIPCHK(hipMemcpy(re, c->ds.re_cnt, 16, hipMemcpyDeviceToHost));
     if (re_prop) *re_prop = (long long)re[0];
     if (re_acc) *re_acc = (long long)re[1];
+    return LLR_OK;
+}
+
+llr_status llr_get_rates(llr_ctx* c, llr_rates* out) {
+    if (!c || !out) return fail(LLR_EINVAL, "null argument");
+    if (!c->laid_out) return fail(LLR_ESTATE, "no state");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = c->lt.n_chains;
+    std::vector<unsigned long long> hp(n), ha(n), fa(n), re(2);
+    HIPCHK(hipMemcpy(hp.data(), c->ds.hb_prop, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ha.data(), c->ds.hb_acc, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fa.data(), c->ds.fu_acc, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(re.data(), c->ds.re_cnt, 16, hipMemcpyDeviceToHost));
+    llr_rates r{};
+    r.sweeps = c->sweeps_run;
+    double links = 0.0;   // link updates
+    long long fused_acc = 0;
+    for (int i = 0; i < c->lt.n; ++i) {
+        const LatDev& L = c->lt.l[i];
+        const double half = (double)L.V2;   // class links of one chain in one class pass
+        for (int k = 0; k < L.n_chains; ++k) {
+            const int g = L.chain0 + k;
+            r.hb_class_passes += (long long)hp[g];
+            r.hb_class_accepts += (long long)ha[g];
+            fused_acc += (long long)fa[g];
+            // every heatbath class pass updates its V/2 links; every
+            // overrelaxation class pass too, except the one fused after an
+            // accepted heatbath of its class (a relabelled draw)
+            links += half * ((double)hp[g] + (double)(c->or_passes + c->fused_passes) - (double)fa[g]);
+        }
+    }
+    r.or_class_passes = (c->or_passes + c->fused_passes) * (long long)n;
+    r.or_class_relabelled = fused_acc;
+    r.re_proposals = (long long)re[0];
+    r.re_accepts = (long long)re[1];
+    r.link_updates = links;
+    r.seconds = c->run_seconds;
+    r.link_updates_per_s = c->run_seconds > 0 ? links / c->run_seconds : 0.0;
+    r.hb_acceptance = r.hb_class_passes ? (double)r.hb_class_accepts / (double)r.hb_class_passes : 0.0;
+    r.or_acceptance = 1.0;
+    r.re_acceptance = r.re_proposals ? (double)r.re_accepts / (double)r.re_proposals : 0.0;
+    *out = r;
+    return LLR_OK;
+}
+
+llr_status llr_health(llr_ctx* c, uint32_t* flags, double* drift, int clear) {
+    if (!c) return fail(LLR_EINVAL, "null context");
+    if (!c->laid_out) return fail(LLR_ESTATE, "no state");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int n = c->lt.n_chains;
+    if (flags) HIPCHK(hipMemcpy(flags, c->ds.health, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    if (drift) HIPCHK(hipMemcpy(drift, c->ds.drift, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    if (clear) {
+        HIPCHK(hipMemsetAsync(c->ds.health, 0, 4 * (size_t)n, c->stream));
+        HIPCHK(hipMemsetAsync(c->ds.drift, 0, 8 * (size_t)n, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
     return LLR_OK;
 }
 
@@ -1286,6 +1408,7 @@ static bool uniform_centres(const double* c, int n, double s) {
 }
 
 llr_status llr_observables(llr_ctx* c, int n_meas, int gap, long long sweep0, double* E, double* B) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (n_meas < 1 || gap < 1 || !E || !B) return fail(LLR_EINVAL, "bad argument");
@@ -1345,6 +1468,7 @@ llr_status llr_muca_begin(llr_ctx* c, const double* b) {
 }
 
 llr_status llr_muca_sweeps(llr_ctx* c, int n_sweeps, long long sweep0, double* E_hist) {
+    RunClock clk(c);
     llr_status st = need_state(c);
     if (st != LLR_OK) return st;
     if (!c->muca_ready) return fail(LLR_ESTATE, "call llr_muca_begin first");
@@ -1675,7 +1799,7 @@ llr_status llr_mlp_train(llr_ctx* c, float* w, const float* u, const float* invL
 // convergence record and the history a^(n), and the counters (sweep and
 // approach indices, Robbins-Monro iteration, replica-exchange counts).
 //
-// File layout (little endian): the 8 bytes "LLRCKPT1"; u32 version (1); u32
+// File layout (little endian): the 8 bytes "LLRCKPT1"; u32 version (2); u32
 // precision; u32 number of lattices; per lattice i32 L, i32 n, f64 dE,
 // f64 E_low[n]; the parameters as listed in llr_params (i32 n_th, n_a, n_rm,
 // u64 seed, i32 replica_exchange, f64 overlap, i32 recompute_every, f64 eps,
@@ -1685,7 +1809,7 @@ llr_status llr_mlp_train(llr_ctx* c, float* w, const float* u, const float* invL
 namespace {
 
 const char kCkMagic[8] = {'L', 'L', 'R', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kCkVersion = 1;
+constexpr uint32_t kCkVersion = 2;
 
 uint32_t crc32_update(uint32_t crc, const unsigned char* p, size_t n) {
     static uint32_t table[256];
@@ -1707,7 +1831,7 @@ uint32_t crc32_update(uint32_t crc, const unsigned char* p, size_t n) {
 enum CkTag : uint32_t {
     kTagState = 1, kTagCur, kTagE, kTagItv, kTagB, kTagEta, kTagSprev, kTagHbProp, kTagHbAcc, kTagA, kTagConf,
     kTagSumE, kTagConvIter, kTagConvSweeps, kTagAHist, kTagLinkFix, kTagLinkArc, kTagLatDone, kTagMuLnRho, kTagMuB,
-    kTagScalars, kTagHost
+    kTagScalars, kTagHost, kTagFuAcc, kTagRates
 };
 
 struct CkWriter {
@@ -1860,6 +1984,7 @@ llr_status llr_checkpoint(llr_ctx* c, const char* path) {
     CKD(kTagLatDone, s.lat_done, 4 * (size_t)kMaxLat)
     CKD(kTagMuLnRho, s.mu_lnrho, 8 * (size_t)n)
     CKD(kTagMuB, s.mu_b, 8 * (size_t)kMaxLat)
+    CKD(kTagFuAcc, s.fu_acc, 8 * (size_t)n)
 #undef CKD
     // device scalars: sweep index, approach index, RM iteration, replica counts
     uint32_t sc[2];
@@ -1885,6 +2010,10 @@ llr_status llr_checkpoint(llr_ctx* c, const char* path) {
     w.val((uint32_t)kTagHost);
     w.val((uint64_t)hw.buf.size());
     w.put(hw.buf.data(), hw.buf.size());
+    // link-update accounting of llr_get_rates
+    w.val((uint32_t)kTagRates);
+    w.val((uint64_t)32);
+    w.val(c->sweeps_run); w.val(c->or_passes); w.val(c->fused_passes); w.val(c->run_seconds);
     const uint32_t crc = crc32_update(0, w.buf.data(), w.buf.size());
     w.val(crc);
     const std::string tmp = std::string(path) + ".tmp";
@@ -1939,7 +2068,7 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
         {kTagHbAcc, 8 * (size_t)n}, {kTagA, 8 * (size_t)n}, {kTagConf, 4 * (size_t)n}, {kTagSumE, 8 * (size_t)n},
         {kTagConvIter, 4 * (size_t)n}, {kTagConvSweeps, 8 * (size_t)n}, {kTagLinkFix, 8 * (size_t)n},
         {kTagLinkArc, 8 * (size_t)n}, {kTagLatDone, 4 * (size_t)kMaxLat}, {kTagMuLnRho, 8 * (size_t)n},
-        {kTagMuB, 8 * (size_t)kMaxLat}, {kTagScalars, 28}};
+        {kTagMuB, 8 * (size_t)kMaxLat}, {kTagScalars, 28}, {kTagFuAcc, 8 * (size_t)n}, {kTagRates, 32}};
     for (const auto& x : want) {
         const Sec* q = find(x.tag);
         if (!q || q->bytes != x.bytes) return fail(LLR_EINVAL, "checkpoint section missing or of the wrong size");
@@ -1974,7 +2103,7 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     CKU(kTagEta, s.eta) CKU(kTagSprev, s.sprev) CKU(kTagHbProp, s.hb_prop) CKU(kTagHbAcc, s.hb_acc) CKU(kTagA, s.a)
     CKU(kTagConf, s.conf) CKU(kTagSumE, s.sumE) CKU(kTagConvIter, s.conv_iter) CKU(kTagConvSweeps, s.conv_sweeps)
     CKU(kTagLinkFix, s.link_fix) CKU(kTagLinkArc, s.link_arc) CKU(kTagLatDone, s.lat_done) CKU(kTagMuLnRho, s.mu_lnrho)
-    CKU(kTagMuB, s.mu_b)
+    CKU(kTagMuB, s.mu_b) CKU(kTagFuAcc, s.fu_acc)
 #undef CKU
     if (c->ds.a_hist) {
         HIPCHK(hipFree(c->ds.a_hist));
@@ -1991,7 +2120,13 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     HIPCHK(hipMemcpy(s.rm_iter, sc->at + 8, 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(s.re_cnt, sc->at + 12, 16, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(s.bits, 0, 2 * (size_t)(n + 2)));
+    HIPCHK(hipMemset(s.health, 0, 4 * (size_t)n));
+    HIPCHK(hipMemset(s.drift, 0, 8 * (size_t)n));
     HIPCHK(hipDeviceSynchronize());
+    {
+        CkReader rr{find(kTagRates)->at, 32};
+        rr.val(&c->sweeps_run); rr.val(&c->or_passes); rr.val(&c->fused_passes); rr.val(&c->run_seconds);
+    }
     c->rm_done = rm_done;
     c->rm_open = rm_open != 0;
     c->ap_open = ap_open != 0;

@@ -61,6 +61,9 @@ struct DevState {
     uint16_t* bits_last;   // accept bits of the last finished sweep
     unsigned long long* hb_prop;
     unsigned long long* hb_acc;
+    unsigned long long* fu_acc;   // fused heatbath + overrelaxation passes whose heatbath class was accepted
+    uint32_t* health;      // kHealth* flags raised by the energy recompute (sticky until read and cleared)
+    double* drift;         // largest |E incremental - E recomputed| seen at a recompute
     // per interval (global index = chain0 of the lattice + local index)
     double* a;             // Robbins-Monro coupling
     double* lo;            // restriction [lo, hi]
@@ -94,6 +97,14 @@ struct DevState {
     long long bits_rows_max;
 };
 
+// Health tests of the FP64 energy recompute.  The incremental E of a chain
+// and the recomputed one differ by the rounding of the per-link Delta E (and,
+// in FP32, of the overrelaxed angles, whose energy change is not tracked);
+// the drift bound is 1e-5 x 6V in FP32 and 1e-9 x 6V in FP64, far above that
+// rounding.  An angle that is not finite makes its plaquettes not finite.
+enum { kHealthNonFinite = 1, kHealthDrift = 2, kHealthOutside = 4 };
+enum { kCheckDrift = 1, kCheckInterval = 2 };
+
 struct RunCfg {
     uint32_t k0, k1;       // Philox key
     int n_a;
@@ -111,8 +122,9 @@ template <typename T> void launch_or_pass(const LatTable& lt, T* th, DevState s,
 // overrelaxation of the same class, in one launch
 template <typename T> void launch_hb_or_pass(const LatTable& lt, T* th, DevState s, int colour, int mode,
                                              uint32_t k0, uint32_t k1, hipStream_t st);
+// check: kCheck* bits (which health tests the recompute applies)
 template <typename T> void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st,
-                                          bool with_obs = false);
+                                          bool with_obs = false, int check = 0);
 template <typename T> void launch_export(const LatTable& lt, int li, const T* th, DevState s, T* out, hipStream_t st);
 template <typename T> void launch_import(const LatTable& lt, int li, T* th, DevState s, const T* in, hipStream_t st);
 void launch_end_sweep(const LatTable& lt, DevState s, int measure, int approach, int with_or, hipStream_t st);

@@ -609,6 +609,9 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
             s.E[g] = En;
             s.bits[g] |= (uint16_t)(1u << colour);
             s.hb_acc[g] += 1ull;
+            if constexpr (VAR == kHbFuseOr) {
+                if (mode != kModeTune) s.fu_acc[g] += 1ull;
+            }
         }
         atomicExch(s.acc + g, 0ull);
     }
@@ -986,10 +989,13 @@ __device__ __forceinline__ double cos_plaq(double x) {
 // Full FP64 energy: E = sum_{x, mu<nu} cos theta_{mu nu}(x), one thread per
 // site.  The first half of a chain's blocks takes the even sites, the second
 // half the odd ones, so the parity and with it every plane base is uniform
-// over a block.
+// over a block.  check (kCheck* bits) adds the health tests of the chain's
+// incremental E before it is replaced: any non-finite plaquette angle, the
+// drift against the recomputed E, and the recomputed E against the chain's
+// restriction; failures set sticky kHealth* flags that the host reads.
 // ---------------------------------------------------------------------------
 template <typename T, bool OBS>
-__global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restrict__ th, DevState s) {
+__global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restrict__ th, DevState s, int check) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int li = find_lat_site(lt, b);
     const LatDev& L = lt.l[li];
@@ -1003,6 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
     const int p = tile >= half ? 1 : 0;
     const uint32_t h = (uint32_t)(tile - p * half) * kBlock + threadIdx.x;
     long long fx = 0, fa = 0;
+    int bad = 0;   // a plaquette angle that is not finite
     if (h < L.V2) {
         int x[4];
         decode_half(L, h, p, x);
@@ -1021,15 +1028,35 @@ __global__ __launch_bounds__(kBlock) void k_energy(LatTable lt, const T* __restr
                 const double t_nu_pmu = (double)ld_plane(plane_ptr(chain, curw, 2 * nu + (p ^ 1), L.V2), hup[mu]);
                 const double t_mu_pnu = (double)ld_plane(plane_ptr(chain, curw, 2 * mu + (p ^ 1), L.V2), hup[nu]);
                 const double ang = own[mu] + t_nu_pmu - t_mu_pnu - own[nu];
+                bad |= !(fabs(ang) < INFINITY);
                 const double cp = cos_plaq(ang);
                 fx += __double2ll_rn(cp * L.fx);
                 if (OBS) fa += __double2ll_rn(__fma_rn(2.0 * cp, cp, -1.0) * L.fx);   // cos 2 theta_P
             }
     }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(s.health + g, (uint32_t)kHealthNonFinite);
     const long long tot = block_sum_i64(fx);
     long long total = 0;
     if (threadIdx.x == 0 && chain_arrive(s.eacc + g, tot, L.ebpc, &total)) {
-        s.E[g] = (double)total * L.fxinv;
+        const double En = (double)total * L.fxinv;
+        if (check) {
+            // health of the chain's incremental E: its drift from the
+            // recomputed value, and (restricted sweeps) that the recomputed E
+            // lies in the chain's restriction up to that drift bound
+            const double bound = (sizeof(T) == 4 ? 1e-5 : 1e-9) * 12.0 * (double)L.V2;
+            const double d = fabs(En - s.E[g]);
+            uint32_t f = 0;
+            if (check & kCheckDrift) {
+                s.drift[g] = fmax(s.drift[g], d);
+                if (!(d <= bound)) f |= kHealthDrift;
+            }
+            if (check & kCheckInterval) {
+                const int gi = s.itv[g];
+                if (!(En >= s.lo[gi] - bound && En <= s.hi[gi] + bound)) f |= kHealthOutside;
+            }
+            if (f) atomicOr(s.health + g, f);
+        }
+        s.E[g] = En;
         atomicExch(s.eacc + g, 0ull);
     }
     if (OBS) {
@@ -1345,9 +1372,9 @@ void launch_or_pass(const LatTable& lt, T* th, DevState s, int colour, int to_al
 }
 
 template <typename T>
-void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st, bool with_obs) {
-    if (with_obs) hipLaunchKernelGGL((k_energy<T, true>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
-    else hipLaunchKernelGGL((k_energy<T, false>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s);
+void launch_energy(const LatTable& lt, const T* th, DevState s, hipStream_t st, bool with_obs, int check) {
+    if (with_obs) hipLaunchKernelGGL((k_energy<T, true>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, check);
+    else hipLaunchKernelGGL((k_energy<T, false>), dim3(lt.site_blocks), dim3(kBlock), 0, st, lt, th, s, check);
 }
 
 template <typename T>
@@ -1394,7 +1421,7 @@ void launch_test_vonmises(long n, double kappa, uint32_t k0, uint32_t k1, uint32
     template void launch_hb_pass<T>(const LatTable&, T*, DevState, int, int, int, uint32_t, uint32_t, hipStream_t); \
     template void launch_or_pass<T>(const LatTable&, T*, DevState, int, int, hipStream_t);                           \
     template void launch_hb_or_pass<T>(const LatTable&, T*, DevState, int, int, uint32_t, uint32_t, hipStream_t);     \
-    template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t, bool);                    \
+    template void launch_energy<T>(const LatTable&, const T*, DevState, hipStream_t, bool, int);                    \
     template void launch_export<T>(const LatTable&, int, const T*, DevState, T*, hipStream_t);                 \
     template void launch_import<T>(const LatTable&, int, T*, DevState, const T*, hipStream_t);                 \
     template void launch_test_vonmises<T>(long, double, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, double*, \

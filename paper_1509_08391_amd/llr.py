@@ -28,6 +28,21 @@ class LLRError(RuntimeError):
     pass
 
 
+class LLRNumericError(LLRError):
+    """LLR_ENUMERIC: a chain failed a health test (Context.health)."""
+
+
+class Rates(C.Structure):
+    _fields_ = [("sweeps", C.c_longlong), ("hb_class_passes", C.c_longlong), ("hb_class_accepts", C.c_longlong),
+                ("or_class_passes", C.c_longlong), ("or_class_relabelled", C.c_longlong),
+                ("re_proposals", C.c_longlong), ("re_accepts", C.c_longlong), ("link_updates", C.c_double),
+                ("seconds", C.c_double), ("link_updates_per_s", C.c_double), ("hb_acceptance", C.c_double),
+                ("or_acceptance", C.c_double), ("re_acceptance", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Params(C.Structure):
     _fields_ = [("n_th", C.c_int), ("n_a", C.c_int), ("n_rm", C.c_int), ("seed", C.c_uint64),
                 ("replica_exchange", C.c_int), ("overlap", C.c_double), ("recompute_every", C.c_int),
@@ -70,6 +85,8 @@ _SIGS = {
     "llr_enable_bits_log": [C.c_void_p, C.c_longlong],
     "llr_get_bits_log": [C.c_void_p, _p(C.c_uint16), _p(C.c_longlong)],
     "llr_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong), _p(C.c_longlong)],
+    "llr_get_rates": [C.c_void_p, _p(Rates)],
+    "llr_health": [C.c_void_p, _p(C.c_uint32), _p(C.c_double), C.c_int],
     "llr_link_stats": [C.c_void_p, _p(C.c_longlong), _p(C.c_longlong)],
     "llr_checkpoint": [C.c_void_p, C.c_char_p],
     "llr_restore": [C.c_void_p, C.c_char_p],
@@ -133,9 +150,13 @@ def lib():
     return _lib
 
 
+ENUMERIC = -6
+
+
 def _check(st, allow_warn=False):
     if st < 0 or (st > 0 and not allow_warn):
-        raise LLRError(f"llr status {st}: {lib().llr_last_error().decode()}")
+        cls = LLRNumericError if st == ENUMERIC else LLRError
+        raise cls(f"llr status {st}: {lib().llr_last_error().decode()}")
     return st
 
 
@@ -332,6 +353,22 @@ class Context:
         rp, ra = C.c_longlong(), C.c_longlong()
         _check(lib().llr_stats(self.h, _ptr(hp, C.c_longlong), _ptr(ha, C.c_longlong), C.byref(rp), C.byref(ra)))
         return hp, ha, rp.value, ra.value
+
+    def rates(self):
+        """Work done and rates since creation (llr_get_rates) as a dict."""
+        r = Rates()
+        _check(lib().llr_get_rates(self.h, C.byref(r)))
+        return r.as_dict()
+
+    def health(self, clear=False):
+        """Per chain: health flags (1 non-finite angle, 2 drift beyond the
+        bound, 4 E outside the restriction) and the largest drift seen at a
+        recompute; clear resets both."""
+        nch = sum(x[1] for x in self.lattices)
+        f = np.zeros(nch, dtype=np.uint32)
+        d = np.zeros(nch, dtype=np.float64)
+        _check(lib().llr_health(self.h, _ptr(f, C.c_uint32), _ptr(d, C.c_double), 1 if clear else 0))
+        return f, d
 
     # ---- checkpoints
     def checkpoint(self, path):

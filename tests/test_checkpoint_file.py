@@ -14,7 +14,7 @@ from paper_1509_08391_amd import llr
 EINVAL = -1
 
 
-def _file(lats, prm, sections=(), version=1, precision=1, magic=b"LLRCKPT1"):
+def _file(lats, prm, sections=(), version=2, precision=1, magic=b"LLRCKPT1"):
     b = bytearray(magic)
     b += struct.pack("<III", version, precision, len(lats))
     for L, E_low, dE in lats:
@@ -61,7 +61,7 @@ def test_truncated_corrupted_foreign_and_missing_files_are_rejected(tmp_path):
         "flipped_bit": good[:40] + bytes([good[40] ^ 0x10]) + good[41:],
         "flipped_crc": good[:-1] + bytes([good[-1] ^ 1]),
         "magic": _file(LATS, PRM, magic=b"LLRCKPT2"),
-        "version": _file(LATS, PRM, version=2),
+        "version": _file(LATS, PRM, version=1),
         "precision": _file(LATS, PRM, precision=7),
         "odd_L": _file([(5, [1.0], 1.0)], PRM),
         "no_lattices": _file([], PRM),

@@ -1,7 +1,8 @@
 """Checkpoint and restore of Algorithm 1's state through the C ABI: a run
 interrupted after N sweeps, saved, restored into a fresh context and
 continued for N more sweeps is the uninterrupted 2N-sweep run bit for bit
-(angles, accept bits, chain <-> interval labels, a^(n), energies, counters)."""
+(angles, accept bits, chain <-> interval labels, a^(n), energies, counters,
+the work counts of llr_get_rates)."""
 import numpy as np
 import pytest
 
@@ -45,6 +46,9 @@ def _snapshot(ctx):
         out[f"hist{i}"] = ctx.get_history(i)
     hp, ha, rp, ra = ctx.stats()
     out["hp"], out["ha"], out["re"] = hp, ha, np.array([rp, ra])
+    r = ctx.rates()
+    out["rates"] = np.array([r[k] for k in ("sweeps", "hb_class_passes", "hb_class_accepts", "or_class_passes",
+                                            "or_class_relabelled", "re_proposals", "re_accepts", "link_updates")])
     return out
 
 

@@ -181,7 +181,8 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWE
     return E, flagged
 
 
-def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GROUPED):
+def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GROUPED, a=1.0, interval=0,
+                   lattice_id=0):
     """Per-link linear response of one oracle sweep (FP64): the factor by which
     a 1e-9 random perturbation of the input state is amplified at each output
     link, RMS over n_dir independent perturbations (one random direction alone
@@ -190,11 +191,13 @@ def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GR
     through the same propagation, so this is the link's conditioning."""
     rng = np.random.default_rng(0)
     base = np.ascontiguousarray(th_k[None].copy())
-    oracle.sweeps(d, L, base, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED, order=order)
+    oracle.sweeps(d, L, base, [a], [lo], [hi], [interval], [E0], 1, sweep, seed=SEED, order=order,
+                  lattice_id=lattice_id)
     acc = np.zeros(th_k.shape)
     for _ in range(n_dir):
         t = np.ascontiguousarray(th_k[None] + rng.normal(0.0, 1e-9, th_k.shape)[None])
-        oracle.sweeps(d, L, t, [1.0], [lo], [hi], [0], [E0], 1, sweep, seed=SEED, order=order)
+        oracle.sweeps(d, L, t, [a], [lo], [hi], [interval], [E0], 1, sweep, seed=SEED, order=order,
+                      lattice_id=lattice_id)
         acc += (circ_dist(base[0], t[0]) / 1e-9) ** 2
     return np.sqrt(acc / n_dir)
 
