@@ -186,7 +186,8 @@ llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
  *     rejected class one overrelaxation of its old angles (with the rejected
  *     proposal, (2 - acceptance) updates per class link).
  * Applies to the restricted, free and multicanonical sweeps of llr_run /
- * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run;
+ * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run (whose
+ * accepted classes then get heatbath-only dynamics, for the same reason);
  * sweeps with the per-link restriction and approach-mode sweeps stay grouped.
  * LLR_EINVAL for a null context or another value. */
 enum { LLR_SWEEP_GROUPED = 0, LLR_SWEEP_INTERLEAVED = 1 };
