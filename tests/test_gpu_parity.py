@@ -160,7 +160,7 @@ def test_one_sweep_fp64_batched_chains_and_lattices(llr):
         col += n
 
 
-def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWEEP_GROUPED):
+def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWEEP_GROUPED, interval=0):
     """One FP32-state sweep of one chain by the oracle, pass by pass (in the
     given order of the class passes), returning the set of links whose
     sampler test had a margin below 1e-5."""
@@ -169,15 +169,17 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWE
     par = np.array([sum((s // L ** m) % L for m in range(d)) % 2 for s in range(V)])
     for col in range(2 * d):
         acc, E, dE, mg = oracle.class_pass(d, L, th, 1, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED,
-                                           sweep=sweep, interval=0, f32=True, want_margin=True)
+                                           sweep=sweep, interval=interval, f32=True, want_margin=True)
         mu, p = col >> 1, col & 1
         idx = np.nonzero(par == p)[0]
         flagged[mu, idx[mg < 1e-5]] = True
         if order == oracle.SWEEP_INTERLEAVED:
-            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep,
+                              interval=interval, f32=True)
     if order == oracle.SWEEP_GROUPED:
         for col in range(2 * d):
-            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep, f32=True)
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep,
+                              interval=interval, f32=True)
     return E, flagged
 
 
@@ -739,6 +741,60 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     for j, k in enumerate(_SAMPLE):
         assert int(bits[0, k]) == int(br[0, j]), (k, bits[0, k], br[0, j])
         assert abs(Eg[k] - Er[j]) < 1e-9 * abs(Er[j])
+
+
+def test_full_size_one_sweep_sampled_chains_fp32(llr):
+    """One whole FP32 sweep (grouped order) at the benchmark's shape and launch
+    configuration, link by link on the six sampled chains, against the
+    oracle's FP32-state sweep of the same chains (FP64 arithmetic on
+    FP32-rounded angles, the same 23-bit uniforms).  A heatbath link whose
+    sampler test has a margin below 1e-5 may take the other branch in FP32
+    (the oracle flags it); its different angle changes the staples of its
+    neighbours in the later passes of the sweep, and those of theirs, so the
+    bar is statistical: chains whose interval decisions differ anywhere in
+    the sweep are set aside (at most two of six), and on the others the
+    median link is within 1e-6 and 99.9 % of the links are within
+    1e-6 x max(10, the link's amplification through the sweep, measured on
+    the oracle), the bar of the small-lattice FP32 sweep test; the energy
+    within 0.1 plus 2R <= 12 per flagged link whose angle differs by more
+    than 1e-3 (measured: every chain compared, 19-26 flagged links each,
+    99.983-100 % within the bar, medians 2.4e-7, energies within 0.015)."""
+    import torch
+    d, L = 4, 20
+    th, E, E_low, dE, a = _full_size_states(np.float32)
+    ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], a=[a])
+    ctx.set_tiles(4, 2)
+    ctx.set_order(True)
+    ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
+    bits = ctx.sweeps(1, sweep0=7)
+    got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy().astype(np.float64)
+    Eg, _ = ctx.get_energy(0)
+    ctx.close()
+    compared = 0
+    for j, k in enumerate(_SAMPLE):
+        tr = th[k].copy()
+        lo, hi = E_low[k], E_low[k] + dE
+        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, a[k], lo, hi, E[k], 7, interval=k)
+        # the oracle's decisions, replayed from its energies, against the GPU's bits
+        tb = th[k].copy()
+        Eb, br = oracle.sweeps(d, L, np.ascontiguousarray(tb[None]), [a[k]], [lo], [hi], [k], [E[k]], 1, 7,
+                               seed=SEED, f32=True)
+        if int(bits[0, k]) & 0xff != int(br[0, 0]) & 0xff:
+            print(f"\nchain {k}: interval decisions differ ({int(bits[0, k]) & 0xff:08b} vs "
+                  f"{int(br[0, 0]) & 0xff:08b}), set aside")
+            continue
+        compared += 1
+        amp = _amplification(d, L, th[k], lo, hi, E[k], 7, a=a[k], interval=k)
+        dist = circ_dist(got[j], tr)
+        bar = 1e-6 * np.maximum(amp, 10.0)
+        frac = np.mean(dist <= bar)
+        print(f"\nchain {k}: {int(flagged.sum())} flagged links, median {np.median(dist):.2e}, "
+              f"within bar {frac:.5f}, max {dist.max():.2e}, |dE| {abs(Eg[k] - Er):.3e}")
+        assert np.median(dist) < 1e-6
+        assert frac >= 0.999, (k, frac)
+        n_div = int(np.sum(flagged & (dist > 1e-3)))
+        assert abs(Eg[k] - Er) < 0.1 + 12.0 * n_div, (k, Eg[k] - Er, n_div)
+    assert compared >= 4
 
 
 def test_full_size_class_passes_sampled_chains_fp32(llr):
