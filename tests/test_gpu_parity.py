@@ -797,6 +797,46 @@ def test_full_size_one_sweep_sampled_chains_fp32(llr):
     assert compared >= 4
 
 
+def test_full_size_runs_are_deterministic(llr):
+    """Run-to-run determinism at the benchmark's shape and launch
+    configuration (128 chains of L = 20, FP32, autotuned tiles): three
+    contexts with the same seed run hot start, approach and one Robbins-Monro
+    iteration (sweeps replayed from captured graphs, replica exchange,
+    recompute, measurement) and end bit for bit equal (angles, energies,
+    chain <-> interval labels, a_k, acceptance counts).  The chain sums are
+    fixed-point integers, so a race in the class passes' LDS queue or
+    reductions would show up as a difference.  The third context walks the
+    blocks in one order instead of the serpentine one, which must not change
+    the result either."""
+    L, n = 20, 128
+    V6 = 6 * L ** 4
+    dE = 0.0005 * V6
+    E_low = 0.60 * V6 + dE * np.arange(n)
+    out = []
+    for serpentine in (True, True, False):
+        ctx = llr.Context(precision=llr.FP32, device=0)
+        ctx.set_params(n_th=3, n_a=4, n_rm=1, seed=SEED, replica_exchange=True, overlap=1.0, recompute_every=2,
+                       approach_cap=20000)
+        ctx.add_lattice(L, E_low, dE)
+        ctx.bind_state()
+        ctx.set_a(0, 1.0)
+        ctx.set_order(serpentine)
+        ctx.hot_start()
+        ctx.approach()
+        ctx.autotune()
+        ctx.set_tiles(4, 2)
+        ctx.run()
+        E, conf = ctx.get_energy(0)
+        a, _, _ = ctx.get_a(0)
+        hp, ha, rp, ra = ctx.stats()
+        out.append(dict(theta=ctx.export_state(0).cpu().numpy(), E=E, conf=conf, a=a, ha=ha, re=np.array([rp, ra])))
+        ctx.close()
+    assert 0 < out[0]["re"][1] <= out[0]["re"][0]
+    for other in out[1:]:
+        for k in out[0]:
+            assert np.array_equal(out[0][k], other[k]), k
+
+
 def test_full_size_class_passes_sampled_chains_fp32(llr):
     """The same shape and launch configuration with FP32 angles, one class at
     a time (links of one class share no plaquette, so a link that differs

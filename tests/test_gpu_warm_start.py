@@ -107,3 +107,41 @@ def test_mlp_warm_start_converges_in_fewer_sweeps(llr):
     both = cold[1] >= 0
     assert both.sum() >= NK // 2
     assert np.median(np.abs(cold[0][both] - warm[0][both])) < 1.5e-3
+
+
+@pytest.mark.parametrize("bf16", [True, False])
+def test_warm_start_sets_predictions_and_falls_back(llr, bf16):
+    """llr_mlp_warm_start (Sec. 2.4's initial a_i, with plain Robbins-Monro
+    kept as the fallback): with a range that holds every prediction, a_k^(0)
+    is the network's prediction at the interval centres u = c_k/(6V), 1/L,
+    bit for bit as llr_mlp_predict gives it; predictions outside
+    [a_min, a_max] and non-finite ones are replaced by the cold start
+    a^(0) = 1 and counted; an empty range is an argument error."""
+    L, n = 8, 24
+    V6 = 6 * L ** 4
+    dE = 0.005 * V6
+    E_low = 0.55 * V6 + dE * np.arange(n)
+    ctx = llr.Context(precision=llr.FP32, device=0)
+    ctx.set_params(seed=SEED)
+    ctx.add_lattice(L, E_low, dE)
+    ctx.bind_state()
+    w = ctx.mlp_init(7)
+    u = ((E_low + 0.5 * dE) / V6).astype(np.float32)
+    pred = ctx.mlp_predict(w, u, np.full(n, 1.0 / L, dtype=np.float32), bf16=bf16)
+    assert np.all(np.isfinite(pred)) and np.ptp(pred) > 0
+    a0, nf = ctx.mlp_warm_start(0, w, pred.min() - 1.0, pred.max() + 1.0, bf16=bf16)
+    assert nf == 0 and np.array_equal(a0, pred)
+    assert np.array_equal(ctx.get_a(0)[0], pred)
+    lo, hi = np.quantile(pred, [0.25, 0.75])
+    a0, nf = ctx.mlp_warm_start(0, w, lo, hi, bf16=bf16)
+    out = (pred < lo) | (pred > hi)
+    assert nf == int(out.sum()) > 0
+    assert np.all(a0[out] == 1.0) and np.array_equal(a0[~out], pred[~out])
+    assert np.array_equal(ctx.get_a(0)[0], a0)
+    w_bad = w.copy()
+    w_bad[:] = np.nan
+    a0, nf = ctx.mlp_warm_start(0, w_bad, pred.min() - 1.0, pred.max() + 1.0, bf16=bf16)
+    assert nf == n and np.all(a0 == 1.0)
+    with pytest.raises(llr.LLRError):
+        ctx.mlp_warm_start(0, w, 1.1, 0.9, bf16=bf16)
+    ctx.close()
