@@ -1,55 +1,55 @@
 """Runs of Algorithm 1 on the configurations the method is measured on.
 
-  config1  L=8, 32 intervals from u = 0.55, dE = 0.005 6V, N_TH = 200,
+  l8        L=8, 32 intervals from u = 0.55, dE = 0.005 6V, N_TH = 200,
            N_A = 500, N_RM = 50, a^(0) = 1; once in FP64 and once with FP32
            angles; <u>(beta), C_V(beta) on beta in [0.98, 1.04].
-  config2  L = 12, 16, 20 batched in one launch, 64 intervals each over
+  batched   L = 12, 16, 20 batched in one launch, 64 intervals each over
            u in [0.58, 0.68], replica exchange after every sweep, FP32,
            N_TH = 200, N_A = 1000, N_RM = 100.
-  config3  warm start: the network a(u, 1/L) trained on the converged a_k of
-           config1 (L=8) and config2 (L=12, 16), predicting the L=20 interval
-           set of config4; Robbins-Monro from the prediction and from
+  warmstart warm start: the network a(u, 1/L) trained on the converged a_k of
+           l8 (L=8) and batched (L=12, 16), predicting the L=20 interval
+           set of l20; Robbins-Monro from the prediction and from
            a^(0) = 1, compared by the sweeps until |a^(n+1) - a^(n)| < 1e-4.
-  config4  L = 20, 128 intervals from u = 0.60, dE = 0.0005 6V, warm start,
+  l20       L = 20, 128 intervals from u = 0.60, dE = 0.0005 6V, warm start,
            replica exchange, FP32, N_TH = 500, N_A = 2000, N_RM = 100;
            ln rho, C_V(beta) on beta in [1.008, 1.012], beta_c and peak.
 
-  config4r N_B = 8 independent repetitions of config4 (eight lattices of one
+  l20reps   N_B = 8 independent repetitions of l20 (eight lattices of one
            context; the lattice index enters every random counter), warm
            start, N_RM = 25: bootstrap errors of beta_c and the C_V peak
            (Sec. 2.4, Sec. 3.2), and the two peaks of P_beta(E) at beta_c.
 
   muca12   multicanonical sampling at L = 12 with W = 1/rho~ from the
-           converged L=12 a_k of config2 (Sec. 2.6): 64 chains, flatness of
+           converged L=12 a_k of batched (Sec. 2.6): 64 chains, flatness of
            the energy histogram, tunnellings between the ends of the range,
            and <u>(beta) by reweighting (eq. (4.7)) next to the LLR
            reconstruction from the same a_k.
 
-  dE8      the delta E study of Sec. 3.5 at L = 8: the config1 range
+  dE8      the delta E study of Sec. 3.5 at L = 8: the l8 range
            u in [0.55, 0.71] cut into 16, 32, 64 and 128 intervals, eight
            replicas each, FP32; the C_V peak against delta E and the fit
            C_V(dE) = C_V(0) + 6V b_dis dE^2.
 
   obs8     a non-action observable through restricted double brackets
-           (Sec. 2.3): after an L=8 run with config1's dE over u in
+           (Sec. 2.3): after an L=8 run with l8's dE over u in
            [0.50, 0.71] (42 intervals, FP32), 400 restricted
            measurements per interval of E and sum_P cos 2 theta_P;
            <u>(beta) and <cos 2 theta_P>(beta) on [0.98, 1.04] by eqs.
            (l9)-(l10), next to direct canonical runs at beta = 0.98, 1.04.
 
-  config4b config4 repeated: part p runs two independent replicas as two
+  l20parts  l20 repeated: part p runs two independent replicas as two
            lattices of one context (seed SEED + 1000 p) with the warm start
            and N_RM = 100;
-           "config4b --combine" bootstraps beta_c and the C_V peak over all
+           "l20parts --combine" bootstraps beta_c and the C_V peak over all
            parts' runs and locates the peaks of P_beta(E) at beta_c.
 
   linkcmp  the restriction imposed per link when each angle is drawn
            (Sec. 2.4) against class-wise rejection, FP32, no replica
            exchange, from one thermalised state per lattice: ms per sweep,
            the integrated autocorrelation time of E per interval, class
-           acceptance, links re-drawn per class pass.  L = 8 (config1's
-           intervals, a_k from a 20-iteration run) and L = 20 (config4's
-           intervals, a_k of a converged run from a config4b_part0.json
+           acceptance, links re-drawn per class pass.  L = 8 (l8's
+           intervals, a_k from a 20-iteration run) and L = 20 (l20's
+           intervals, a_k of a converged run from an l20parts_part0.json
            under --inputs, else a_k = 1.011 ~ beta_c(20) throughout).
   linkprof 60 sweeps per mode of the L = 20 set only, for a kernel trace.
 
@@ -61,7 +61,7 @@
   --order  grouped (default) or interleaved: the sweep order of the
            Algorithm 1 runs of every configuration.
 
-  batchprof the config2 lattice set (L = 12, 16, 20, 64 intervals each, one
+  batchprof the batched lattice set (L = 12, 16, 20, 64 intervals each, one
            launch per class pass for all three), FP32, replica exchange,
            a_k = 1: hot start, approach, autotune, then 200 restricted sweeps
            timed; for a kernel trace of the batched launch.
@@ -71,12 +71,12 @@
            16, 18 (part 1), 96 intervals over u in [0.56, 0.70], four replicas
            each (lattices of one context), replica exchange, FP32,
            N_TH = 200, N_A = 800, N_RM = 80, warm start from the network of
-           config3 evaluated at (u, 1/L); per L a bootstrap over the replicas.
-           "fss --combine" adds L = 20 from the config4b parts and fits
+           warmstart evaluated at (u, 1/L); per L a bootstrap over the replicas.
+           "fss --combine" adds L = 20 from the l20parts parts and fits
            beta_c(L) = beta_c + sum_k B_k L^-4k and C_V/(6V) = G^2/4 + ...
 
 Each writes a JSON record.  Usage:
-    python -m paper_1509_08391_amd.experiments config1 [--out DIR]
+    python -m paper_1509_08391_amd.experiments l8 [--out DIR]
 """
 from __future__ import annotations
 
@@ -173,7 +173,7 @@ def _reconstruct(L, E_low, dE, a, blo, bhi, nb=61):
                 cv_peak=pk, cv_peak_over_6v=pk / V6)
 
 
-def config1(log, replicas=8):
+def run_l8(log, replicas=8):
     """The L=8 interval set as `replicas` independent lattices of one context
     (the lattice index enters every random counter), in FP64 and in FP32."""
     L = 8
@@ -196,7 +196,7 @@ def config1(log, replicas=8):
     return rec
 
 
-def config2(log):
+def run_batched(log):
     lats = []
     for L in (12, 16, 20):
         V6 = 6 * L ** 4
@@ -208,7 +208,7 @@ def config2(log):
     return dict(results=res, meta=meta)
 
 
-def config4_intervals():
+def l20_intervals():
     L = 20
     V6 = 6 * L ** 4
     dE = 0.0005 * V6
@@ -229,7 +229,7 @@ def train_network(points, epochs=4000, lr=3e-3, seed=SEED):
     return w, hist, float(np.sqrt(np.mean((pred - a) ** 2)))
 
 
-def config3(log, c1, c2, n_rm=20):
+def run_warmstart(log, c1, c2, n_rm=20):
     pts = []
     r1 = c1["fp64"]["results"]
     a8 = np.mean([r["a"] for r in r1], axis=0)
@@ -242,7 +242,7 @@ def config3(log, c1, c2, n_rm=20):
             for e, a in zip(r["E_low"], r["a"]):
                 pts.append(((e + 0.5 * r["dE"]) / V6, 1.0 / r["L"], a))
     w, hist, rms = train_network(pts)
-    L, E_low, dE = config4_intervals()
+    L, E_low, dE = l20_intervals()
     V6 = 6 * L ** 4
     u20 = (E_low + 0.5 * dE) / V6
     ctx = llr.Context(precision=llr.FP32, device=0)
@@ -258,8 +258,8 @@ def config3(log, c1, c2, n_rm=20):
                 a_mlp=a_mlp.tolist(), runs=runs, n_rm=n_rm)
 
 
-def config4(log, c3, n_rm=100):
-    L, E_low, dE = config4_intervals()
+def run_l20(log, c3, n_rm=100):
+    L, E_low, dE = l20_intervals()
     a0 = np.array(c3["a_mlp"])
     res, meta = _run([(L, E_low, dE)], llr.FP32, 500, 2000, n_rm, True, a0=[a0], log=log)
     r = res[0]
@@ -267,8 +267,8 @@ def config4(log, c3, n_rm=100):
     return dict(result=r, meta=meta)
 
 
-def config4_replicas(log, c3, n_rep=8, n_rm=25, n_boot=1000):
-    L, E_low, dE = config4_intervals()
+def l20_replicas(log, c3, n_rep=8, n_rm=25, n_boot=1000):
+    L, E_low, dE = l20_intervals()
     V6 = 6 * L ** 4
     a0 = np.array(c3["a_mlp"])
     res, meta = _run([(L, E_low, dE)] * n_rep, llr.FP32, 500, 2000, n_rm, True, a0=[a0] * n_rep, log=log)
@@ -395,7 +395,7 @@ def obs8(log, n_meas=400, gap=2):
     V6 = 6 * L ** 4
     NP = V6
     dE = 0.005 * V6
-    # config1's dE, with the range extended down to u = 0.50 so that the
+    # l8's dE, with the range extended down to u = 0.50 so that the
     # canonical distribution at beta = 0.98 (<u> ~ 0.55) lies inside it
     E_low = 0.50 * V6 + dE * np.arange(42)
     cen = E_low + 0.5 * dE
@@ -448,8 +448,8 @@ def obs8(log, n_meas=400, gap=2):
                 n_meas=n_meas, gap=gap)
 
 
-def config4b_part(log, c3, part, n_rep=2, n_rm=100):
-    L, E_low, dE = config4_intervals()
+def l20_part(log, c3, part, n_rep=2, n_rm=100):
+    L, E_low, dE = l20_intervals()
     a0 = np.array(c3["a_mlp"])
     res, meta = _run([(L, E_low, dE)] * n_rep, llr.FP32, 500, 2000, n_rm, True, seed=SEED + 1000 * part,
                      a0=[a0] * n_rep, log=log)
@@ -457,8 +457,8 @@ def config4b_part(log, c3, part, n_rep=2, n_rm=100):
                 meta=meta)
 
 
-def config4b_combine(log, parts, n_boot=2000):
-    L, E_low, dE = config4_intervals()
+def l20_parts_combine(log, parts, n_boot=2000):
+    L, E_low, dE = l20_intervals()
     V6 = 6 * L ** 4
     cen = E_low + 0.5 * dE
     A = np.array([r["a"] for p in parts for r in p["runs"]])
@@ -576,7 +576,7 @@ def link_compare(log, a20, n_meas8=8000, n_meas20=4000):
     E_low = 0.55 * V6 + dE * np.arange(32)
     res, _ = _run([(L, E_low, dE)], llr.FP32, 200, 500, 20, False, log=log)
     rec = dict(L8=_link_lattice(log, L, E_low, dE, res[0]["a"], n_meas8, 500, SEED + 17))
-    L, E_low, dE = config4_intervals()
+    L, E_low, dE = l20_intervals()
     rec["L20"] = _link_lattice(log, L, E_low, dE, a20, n_meas20, 200, SEED + 19)
     return rec
 
@@ -595,13 +595,13 @@ def order_compare(log, a20, n_meas8=8000, n_meas20=8000):
     E_low = 0.55 * V6 + dE * np.arange(32)
     res, _ = _run([(L, E_low, dE)], llr.FP32, 200, 500, 20, False, log=log)
     rec = dict(L8=_link_lattice(log, L, E_low, dE, res[0]["a"], n_meas8, 500, SEED + 23, runs, pairs))
-    L, E_low, dE = config4_intervals()
+    L, E_low, dE = l20_intervals()
     rec["L20"] = _link_lattice(log, L, E_low, dE, a20, n_meas20, 200, SEED + 29, runs, pairs)
     return rec
 
 
 def link_profile(log, a20, n=60):
-    L, E_low, dE = config4_intervals()
+    L, E_low, dE = l20_intervals()
     ctx = llr.Context(precision=llr.FP32, device=0)
     ctx.set_params(seed=SEED + 19, replica_exchange=False, recompute_every=10, approach_cap=20000)
     ctx.add_lattice(L, E_low, dE)
@@ -688,7 +688,7 @@ def fss_combine(log, parts, c4b_parts, n_boot=2000):
             if k.isdigit():
                 rows[int(k)] = (v["beta_c"], v["beta_c_err"], v["cv_peak_over_6v"], v["cv_peak_over_6v_err"])
     if c4b_parts:
-        L, E_low, dE = config4_intervals()
+        L, E_low, dE = l20_intervals()
         V6 = 6 * L ** 4
         cen = E_low + 0.5 * dE
         A = np.array([r["a"] for p in c4b_parts for r in p["runs"]])
@@ -720,12 +720,12 @@ def fss_combine(log, parts, c4b_parts, n_boot=2000):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["config1", "config2", "config3", "config4", "config4r", "muca12",
+    ap.add_argument("which", choices=["l8", "batched", "warmstart", "l20", "l20reps", "muca12",
                                             "dE8", "obs8",
-                                            "config4b", "linkcmp", "linkprof", "fss", "batchprof", "ordercmp"])
+                                            "l20parts", "linkcmp", "linkprof", "fss", "batchprof", "ordercmp"])
     ap.add_argument("--out", default="experiment_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
-                    "(config3 reads config1 and config2, config4 reads config3); default --out")
+                    "(warmstart reads l8 and batched, l20 reads warmstart); default --out")
     ap.add_argument("--n-rm", type=int, default=None)
     ap.add_argument("--part", type=int, default=0)
     ap.add_argument("--combine", action="store_true")
@@ -744,16 +744,16 @@ def main():
             return json.load(f)
 
     t0 = time.perf_counter()
-    if args.which == "config1":
-        rec = config1(log)
-    elif args.which == "config2":
-        rec = config2(log)
-    elif args.which == "config3":
-        rec = config3(log, load("config1"), load("config2"), n_rm=args.n_rm or 20)
-    elif args.which == "config4":
-        rec = config4(log, load("config3"), n_rm=args.n_rm or 100)
+    if args.which == "l8":
+        rec = run_l8(log)
+    elif args.which == "batched":
+        rec = run_batched(log)
+    elif args.which == "warmstart":
+        rec = run_warmstart(log, load("l8"), load("batched"), n_rm=args.n_rm or 20)
+    elif args.which == "l20":
+        rec = run_l20(log, load("warmstart"), n_rm=args.n_rm or 100)
     elif args.which == "muca12":
-        rec = muca12(log, load("config2"))
+        rec = muca12(log, load("batched"))
     elif args.which == "dE8":
         rec = dE_study_8(log)
     elif args.which == "obs8":
@@ -770,33 +770,33 @@ def main():
                 with open(f) as fh:
                     out.append(json.load(fh))
             return out
-        rec = fss_combine(log, recs("fss_part*.json"), recs("config4b_part*.json"))
+        rec = fss_combine(log, recs("fss_part*.json"), recs("l20_part*.json"))
     elif args.which == "fss":
-        rec = fss_part(log, load("config3"), args.part)
+        rec = fss_part(log, load("warmstart"), args.part)
     elif args.which in ("linkcmp", "linkprof", "ordercmp"):
-        # converged L=20 a_k when a config4b record is given, else beta_c(20) throughout
-        src = os.path.join(args.inputs or args.out, "config4b_part0.json")
-        a20 = load("config4b_part0")["runs"][0]["a"] if os.path.exists(src) else [1.011] * 128
+        # converged L=20 a_k when a l20parts record is given, else beta_c(20) throughout
+        src = os.path.join(args.inputs or args.out, "l20parts_part0.json")
+        a20 = load("l20parts_part0")["runs"][0]["a"] if os.path.exists(src) else [1.011] * 128
         if args.which == "linkcmp":
             rec = link_compare(log, a20)
         elif args.which == "ordercmp":
             rec = order_compare(log, a20)
         else:
             rec = link_profile(log, a20)
-    elif args.which == "config4b" and args.combine:
+    elif args.which == "l20parts" and args.combine:
         import glob
         parts = []
-        for f in sorted(glob.glob(os.path.join(args.inputs or args.out, "config4b_part*.json"))):
+        for f in sorted(glob.glob(os.path.join(args.inputs or args.out, "l20_part*.json"))):
             with open(f) as fh:
                 parts.append(json.load(fh))
-        rec = config4b_combine(log, parts)
-    elif args.which == "config4b":
-        rec = config4b_part(log, load("config3"), args.part, n_rm=args.n_rm or 100)
+        rec = l20_parts_combine(log, parts)
+    elif args.which == "l20parts":
+        rec = l20_part(log, load("warmstart"), args.part, n_rm=args.n_rm or 100)
     else:
-        rec = config4_replicas(log, load("config3"), n_rm=args.n_rm or 25)
+        rec = l20_replicas(log, load("warmstart"), n_rm=args.n_rm or 25)
     rec["wall_seconds"] = time.perf_counter() - t0
     name = args.which
-    if args.which in ("config4b", "fss"):
+    if args.which in ("l20parts", "fss"):
         name = f"{args.which}_combined" if args.combine else f"{args.which}_part{args.part}"
     with open(os.path.join(args.out, f"{name}.json"), "w") as f:
         json.dump(rec, f)

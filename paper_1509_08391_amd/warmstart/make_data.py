@@ -79,7 +79,7 @@ def train(pts):
 
 
 def reference(w, a_lo, a_hi, n_rm=60):
-    L, E_low, dE = ex.config4_intervals()
+    L, E_low, dE = ex.l20_intervals()
     runs = []
     for k, seed in enumerate(REF_SEEDS):
         ctx = llr.Context(precision=llr.FP32, device=0)

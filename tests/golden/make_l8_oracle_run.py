@@ -1,4 +1,4 @@
-"""Writes tests/golden/config1_oracle_fp64.json: the FP64 oracle's full run of
+"""Writes tests/golden/l8_oracle_run_fp64.json: the FP64 oracle's full run of
 the L=8 case (32 intervals from u = 0.55 with dE = 0.005 6V, N_TH = 200,
 N_A = 500, N_RM = 50, a^(0) = 1, hot start, seed 1509083910) and its
 reconstruction of <u>(beta), C_V(beta) on beta in [0.98, 1.04] and of beta_c.
@@ -32,7 +32,7 @@ def main():
            "conv_iter": r["conv_iter"].tolist(), "approach_sweeps": r["approach_sweeps"],
            "beta": beta.tolist(), "u_mean": u.tolist(), "cv": cv.tolist(), "ln_rho": lr.tolist(),
            "beta_c": bc, "cv_peak": pk, "oracle_seconds": time.time() - t0, "threads": oracle.num_threads()}
-    with open(os.path.join(HERE, "config1_oracle_fp64.json"), "w") as f:
+    with open(os.path.join(HERE, "l8_oracle_run_fp64.json"), "w") as f:
         json.dump(out, f)
     print("done", time.time() - t0)
 

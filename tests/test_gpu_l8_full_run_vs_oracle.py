@@ -1,5 +1,5 @@
 """Full L = 8 runs of Algorithm 1 on the GPU against the FP64 oracle's full run
-of the same case (stored by tests/golden/make_config1_oracle.py, which calls
+of the same case (stored by tests/golden/make_l8_oracle_run.py, which calls
 only the oracle): 32 intervals from u = 0.55 with dE = 0.005 6V, N_TH = 200,
 N_A = 500, N_RM = 50, a^(0) = 1, hot start.
 
@@ -30,7 +30,7 @@ import pytest
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config1_oracle_fp64.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "l8_oracle_run_fp64.json")
 REPLICAS = 8
 
 
@@ -51,7 +51,7 @@ def golden():
 
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
-def test_config1_replicas_bracket_the_oracle_run(llr, golden, prec):
+def test_l8_replicas_bracket_the_oracle_run(llr, golden, prec):
     g = golden
     L, dE = g["L"], g["dE"]
     V6 = 6 * L ** 4

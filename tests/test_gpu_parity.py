@@ -370,7 +370,7 @@ def test_driver_mixed_lattices_fp64(llr):
 
 
 @pytest.mark.slow
-def test_full_run_config0_statistical_fp64_and_fp32(llr):
+def test_full_run_l4_statistical_fp64_and_fp32(llr):
     """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
     dE = 0.025 6V, N_TH = N_A = 100, N_RM = 20, a^(0) = 1, hot start).  Beyond
     ~15 sweeps the two implementations follow different trajectories, so the
@@ -412,7 +412,7 @@ def test_full_run_config0_statistical_fp64_and_fp32(llr):
         se = np.sqrt(G.var(0, ddof=1) / G.shape[0] + O.var(0, ddof=1) / O.shape[0])
         diff = G.mean(0) - O.mean(0)
         z = np.abs(diff) / se
-        print(f"\nconfig0 {prec}, 64 + 64 runs: max |mean a_GPU - mean a_oracle| {np.abs(diff).max():.2e}, "
+        print(f"\nl4 {prec}, 64 + 64 runs: max |mean a_GPU - mean a_oracle| {np.abs(diff).max():.2e}, "
               f"combined standard error {se.min():.1e}-{se.max():.1e}, max z {z.max():.2f}, "
               f"mean difference over intervals {diff.mean():+.1e} +- {np.sqrt(np.sum(se ** 2)) / se.size:.1e}")
         assert np.all(z < 4.0), (prec, z, diff)
