@@ -101,3 +101,29 @@ def test_restore_rejects_other_lattice_sets(llr, tmp_path):
     with pytest.raises(llr.LLRError):
         wrong_prec.restore(path)
     wrong_prec.close()
+
+
+def test_checkpoint_during_the_approach(llr, tmp_path):
+    """A checkpoint taken between two llr_approach_continue calls: the restored
+    context finishes the approach and the Robbins-Monro iterations exactly as
+    the uninterrupted one (approach counters, per-colour couplings and steps
+    of the approach rule, and the open approach are part of the state)."""
+    path = str(tmp_path / "ap.ckpt")
+    ref = _setup(llr, llr.FP32, 0)
+    ref.approach_begin()
+    ref.approach_continue(3)
+    ref.checkpoint(path)
+    s_ref, done_ref = ref.approach_continue(4000)
+    ref.rm_begin()
+    ref.rm_step(1)
+    want = _snapshot(ref)
+    ref.close()
+    ctx = llr.Context.from_checkpoint(path)
+    s_got, done_got = ctx.approach_continue(4000)
+    ctx.rm_begin()
+    ctx.rm_step(1)
+    got = _snapshot(ctx)
+    ctx.close()
+    assert done_ref and done_got and np.array_equal(s_ref, s_got)
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k

@@ -743,8 +743,9 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
         assert abs(Eg[k] - Er[j]) < 1e-9 * abs(Er[j])
 
 
-def test_full_size_one_sweep_sampled_chains_fp32(llr):
-    """One whole FP32 sweep (grouped order) at the benchmark's shape and launch
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+def test_full_size_one_sweep_sampled_chains_fp32(llr, order):
+    """One whole FP32 sweep (in either order) at the benchmark's shape and launch
     configuration, link by link on the six sampled chains, against the
     oracle's FP32-state sweep of the same chains (FP64 arithmetic on
     FP32-rounded angles, the same 23-bit uniforms).  A heatbath link whose
@@ -758,13 +759,17 @@ def test_full_size_one_sweep_sampled_chains_fp32(llr):
     the oracle), the bar of the small-lattice FP32 sweep test; the energy
     within 0.1 plus 2R <= 12 per flagged link whose angle differs by more
     than 1e-3 (measured: every chain compared, 19-26 flagged links each,
-    99.983-100 % within the bar, medians 2.4e-7, energies within 0.015)."""
+    99.983-100 % within the bar, medians 2.4e-7, energies within 0.015 in
+    the grouped order; 99.997-100 %, medians 1.2-2.4e-7, energies within
+    0.024 in the interleaved order)."""
     import torch
     d, L = 4, 20
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
     th, E, E_low, dE, a = _full_size_states(np.float32)
     ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], a=[a])
     ctx.set_tiles(4, 2)
     ctx.set_order(True)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
     ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
     bits = ctx.sweeps(1, sweep0=7)
     got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy().astype(np.float64)
@@ -774,17 +779,17 @@ def test_full_size_one_sweep_sampled_chains_fp32(llr):
     for j, k in enumerate(_SAMPLE):
         tr = th[k].copy()
         lo, hi = E_low[k], E_low[k] + dE
-        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, a[k], lo, hi, E[k], 7, interval=k)
+        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, a[k], lo, hi, E[k], 7, order=o_order, interval=k)
         # the oracle's decisions, replayed from its energies, against the GPU's bits
         tb = th[k].copy()
         Eb, br = oracle.sweeps(d, L, np.ascontiguousarray(tb[None]), [a[k]], [lo], [hi], [k], [E[k]], 1, 7,
-                               seed=SEED, f32=True)
+                               seed=SEED, f32=True, order=o_order)
         if int(bits[0, k]) & 0xff != int(br[0, 0]) & 0xff:
             print(f"\nchain {k}: interval decisions differ ({int(bits[0, k]) & 0xff:08b} vs "
                   f"{int(br[0, 0]) & 0xff:08b}), set aside")
             continue
         compared += 1
-        amp = _amplification(d, L, th[k], lo, hi, E[k], 7, a=a[k], interval=k)
+        amp = _amplification(d, L, th[k], lo, hi, E[k], 7, a=a[k], interval=k, order=o_order)
         dist = circ_dist(got[j], tr)
         bar = 1e-6 * np.maximum(amp, 10.0)
         frac = np.mean(dist <= bar)
