@@ -714,8 +714,8 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     differences of the two sides' sin, cos and atan2 by ~1/R in
     phi = arg(C + iS); with P(R < r) ~ r^2 the largest amplification over N
     links grows like sqrt(N), about 1e3 here, and measured maxima are ~2e-12.)
-    In both orders of the class passes; the interleaved one, the benchmark's,
-    runs the fused launches."""
+    In both orders of the class passes; the interleaved one runs the fused
+    launches."""
     import torch
     d, L = 4, 20
     th, E, E_low, dE, a = _full_size_states(np.float64)
