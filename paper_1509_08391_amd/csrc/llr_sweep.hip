@@ -424,7 +424,10 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
                                          int mode, int kind, uint32_t k0, uint32_t k1, int b) {
     using M = Math<T>;
     constexpr int NT = kBlock * LPT;
-    __shared__ T s_q[NT], s_rm1[NT], s_kg2[NT], s_ch[NT], s_sh[NT];
+    // queued links keep only their |kappa|: the queue recomputes the sampler
+    // constants (the same operations, so the same values), which keeps the
+    // block's LDS small enough for one more resident block per CU
+    __shared__ T s_ak[NT], s_ch[NT], s_sh[NT];
     __shared__ unsigned char s_res[NT];
     __shared__ short s_queue[2][NT];
     __shared__ int s_qn[2];
@@ -490,9 +493,7 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
                 if (!got[r]) got[r] = vm_attempt(w.z, w.w, q, rm1, kg2, ch[r], sh[r]);
             }
             if (!got[r]) {
-                s_q[e] = q;
-                s_rm1[e] = rm1;
-                s_kg2[e] = kg2;
+                s_ak[e] = ak;
                 s_res[e] = 0;
             }
         }
@@ -513,7 +514,8 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
             // queue entry e = r kBlock + tid: link r of thread tid
             const uint32_t he = ct.pos0 + (uint32_t)(e & (kBlock - 1)) + L.P * (uint32_t)(ct.x3_0 + e / kBlock);
             const uint4 w = philox10(make_uint4(he, c1base | (uint32_t)m, sweep, c3), k0, k1);
-            const T qe = s_q[e], rme = s_rm1[e], kge = s_kg2[e];
+            T qe, rme, kge;
+            vm_constants(s_ak[e], qe, rme, kge);
             T che = T(1), she = T(0);
             bool acc = vm_attempt(w.x, w.y, qe, rme, kge, che, she);
             if (!acc) acc = vm_attempt(w.z, w.w, qe, rme, kge, che, she);
@@ -617,8 +619,13 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
     }
 }
 
+// FP32 passes with 4 class links per thread: registers kept to 72 so that
+// seven wavefronts per SIMD fit (the LDS of the queue allows more)
+template <typename T, int LPT>
+struct HbWaves { static constexpr int value = (sizeof(T) == 4 && LPT == 4) ? 7 : 1; };
+
 template <typename T, int MU, int LPT, int VAR>
-__global__ __launch_bounds__(kBlock) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
+__global__ __launch_bounds__(kBlock, (HbWaves<T, LPT>::value)) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
                                                int kind, uint32_t k0, uint32_t k1, int reverse) {
     const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     hb_block<T, MU, LPT, VAR>(lt, th, s, parity, mode, kind, k0, k1, reverse ? (int)gridDim.x - 1 - b0 : b0);
