@@ -619,13 +619,15 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
     }
 }
 
-// FP32 passes with 4 class links per thread: registers kept to 72 so that
-// seven wavefronts per SIMD fit (the LDS of the queue allows more)
-template <typename T, int LPT>
-struct HbWaves { static constexpr int value = (sizeof(T) == 4 && LPT == 4) ? 7 : 1; };
+// The plain FP32 pass with 4 class links per thread: registers kept to 72
+// so that seven wavefronts per SIMD fit (the LDS of the queue allows more).
+// Measured: heatbath 98.1 -> 97.0 us at L=20 x 128; the fused pass, capped
+// the same way, slowed from 108 to 132 us, so it keeps its registers.
+template <typename T, int LPT, int VAR>
+struct HbWaves { static constexpr int value = (sizeof(T) == 4 && LPT == 4 && VAR == kHbPlain) ? 7 : 1; };
 
 template <typename T, int MU, int LPT, int VAR>
-__global__ __launch_bounds__(kBlock, (HbWaves<T, LPT>::value)) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
+__global__ __launch_bounds__(kBlock, (HbWaves<T, LPT, VAR>::value)) void k_hb(LatTable lt, T* __restrict__ th, DevState s, int parity, int mode,
                                                int kind, uint32_t k0, uint32_t k1, int reverse) {
     const int b0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     hb_block<T, MU, LPT, VAR>(lt, th, s, parity, mode, kind, k0, k1, reverse ? (int)gridDim.x - 1 - b0 : b0);
