@@ -332,8 +332,10 @@ def test_approach_parity_fp64(llr):
     assert np.all((E >= E_low) & (E <= E_low + dE))
 
 
-def test_driver_mixed_lattices_fp64(llr):
-    """L=4 and L=6 chains batched in one launch; each lattice against its own
+@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+def test_driver_mixed_lattices_fp64(llr, order):
+    """L=4 and L=6 chains batched in one launch, in either sweep order (the
+    interleaved one runs the fused launches); each lattice against its own
     oracle run (lattice id in the Philox counter): 4 sweeps, two RM
     iterations.  a_k within 1e-7, the single-lattice driver run's bar
     (measured 5e-13 and 2e-13).  Angles: with the random numbers fixed the
@@ -342,9 +344,12 @@ def test_driver_mixed_lattices_fp64(llr):
     modulus R, so after four sweeps most links agree to ~1e-12 and a few
     have grown further.  Measured: L=4 median 1e-12, max 5e-10; L=6 median
     7e-13, 99 % 8e-10, 99.9 % 4.5e-9, max 6.6e-7 (115 of 15552 links above
-    1e-9).  Bars: median 1e-11, 99 % of links 1e-8, every link 1e-5."""
+    1e-9), in the grouped order; in the interleaved order a_k within 1.1e-12
+    and every angle within 2.4e-11.  Bars: median 1e-11, 99 % of links
+    1e-8, every link 1e-5."""
     import torch
     d = 4
+    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
     lats = []
     for L, n in [(4, 4), (6, 3)]:
         V6 = 6 * L ** 4
@@ -352,17 +357,18 @@ def test_driver_mixed_lattices_fp64(llr):
         E_low = 0.58 * V6 + dE * np.arange(n)
         lats.append((L, E_low, dE, _states_in_intervals(L, E_low, dE, seed=L)))
     ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=0, n_a=2, n_rm=2, recompute_every=3)
+    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
     for i, x in enumerate(lats):
         ctx.import_state(i, torch.from_numpy(x[3]))
     ctx.run()
     for i, (L, E_low, dE, th) in enumerate(lats):
         r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=0, n_a=2, n_rm=2, seed=SEED, recompute_every=3,
-                           lattice_id=i, theta=th, approach_cap=0)
+                           lattice_id=i, theta=th, approach_cap=0, order=o_order)
         a, it, sw = ctx.get_a(i)
         da = np.max(np.abs(a - r["a"]))
         dist = circ_dist(ctx.export_state(i).cpu().numpy(), r["theta"]).ravel()
         q = np.quantile(dist, [0.5, 0.99, 0.999, 0.9999, 1.0])
-        print(f"\nmixed lattices, L={L}: max |a - a_oracle| {da:.2e}; angle differences: median {q[0]:.1e}, "
+        print(f"\nmixed lattices ({order}), L={L}: max |a - a_oracle| {da:.2e}; angle differences: median {q[0]:.1e}, "
               f"99% {q[1]:.1e}, 99.9% {q[2]:.1e}, 99.99% {q[3]:.1e}, max {q[4]:.1e}; "
               f"links above 1e-9: {int(np.sum(dist > 1e-9))} of {dist.size}")
         assert da < 1e-7
