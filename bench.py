@@ -196,6 +196,18 @@ def rm_convergence(llr, n_plain, n_mlp):
     return out
 
 
+def link_updates(order, V, n_chains, n_sweeps, hb_acceptance):
+    """Link updates done by n_sweeps sweeps of n_chains chains of V sites.
+    Grouped order: every link gets one heatbath and one overrelaxation per
+    sweep, 2 x 4V.  Interleaved order: 8 fused passes of V/2 class links, one
+    update per link of an accepted heatbath class (the overrelaxation that
+    follows on the same staples is a relabelled draw) and two (rejected
+    proposal, overrelaxation) per link of a rejected one."""
+    if order == "grouped":
+        return 2.0 * 4 * V * n_chains * n_sweeps
+    return (2.0 - hb_acceptance) * 8 * (V // 2) * n_chains * n_sweeps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,12 +313,7 @@ def main():
     nsw = args.n_th + args.n_a
     dt = t1 - t0
     hb_acc_timed = float((ha - ha0).sum() / max((hp - hp0).sum(), 1))
-    if args.order == "grouped":
-        updates = 2.0 * 4 * V * N_INT * nsw * args.steps
-    else:
-        # 8 fused passes per sweep of V/2 class links each: 1 update per link
-        # of an accepted class, 2 (proposal + overrelaxation) of a rejected one
-        updates = (2.0 - hb_acc_timed) * 8 * (V // 2) * N_INT * nsw * args.steps
+    updates = link_updates(args.order, V, N_INT, nsw * args.steps, hb_acc_timed)
     value = updates / dt
     esz = 4 if prec == llr.FP32 else 8
     # algorithmic bytes of one heatbath pass: the pass reads the whole lattice
