@@ -60,6 +60,10 @@
 
   --order  grouped (default) or interleaved: the sweep order of the
            Algorithm 1 runs of every configuration.
+  --jsonl  a file to which every Robbins-Monro iteration of those runs
+           appends one JSON line: a_k and max |a^(n+1) - a^(n)| per lattice,
+           acceptance rates, link updates and updates/s so far, the largest
+           recompute drift and the chains the health tests flagged.
 
   batchprof the batched lattice set (L = 12, 16, 20, 64 intervals each, one
            launch per class pass for all three), FP32, replica exchange,
@@ -93,6 +97,27 @@ from . import llr
 SEED = 1509083910
 # order of the class passes in the sweeps of _run (command-line --order)
 SWEEP_ORDER = llr.SWEEP_GROUPED
+# JSON-lines record of every Robbins-Monro iteration of _run (command-line
+# --jsonl), None for none
+JSONL = None
+
+
+def _iteration_record(ctx, lattices, it, a_prev, t):
+    """One line of the per-iteration record: per lattice a_k and the largest
+    |a^(n+1) - a^(n)|; acceptance rates, link updates and their rate so far
+    (llr_get_rates); the largest drift of the incremental energy at a
+    recompute and the chains the health tests flagged (llr_health)."""
+    r = ctx.rates()
+    flags, drift = ctx.health()
+    lats = []
+    for i in range(len(lattices)):
+        a = ctx.get_a(i)[0]
+        lats.append(dict(L=lattices[i][0], a=a.tolist(), max_da=float(np.max(np.abs(a - a_prev[i])))))
+        a_prev[i] = a
+    return dict(iteration=it + 1, seconds=t, lattices=lats, hb_acceptance=r["hb_acceptance"],
+                re_acceptance=r["re_acceptance"], or_acceptance=r["or_acceptance"], sweeps=r["sweeps"],
+                link_updates=r["link_updates"], link_updates_per_s=r["link_updates_per_s"],
+                max_recompute_drift=float(drift.max()), chains_flagged=int(np.count_nonzero(flags)))
 
 
 def _updates_per_class_link(ctx, before):
@@ -131,15 +156,22 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
     tiles = ctx.autotune()
     ctx.rm_begin()
     st0 = ctx.stats()
+    jl = open(JSONL, "a") if JSONL else None
+    a_prev = [ctx.get_a(i)[0] for i in range(len(lattices))]
     t1 = time.perf_counter()
     t_log = t1
     for it in range(n_rm):
         ctx.rm_step(1)
         now = time.perf_counter()
+        if jl:
+            jl.write(json.dumps(_iteration_record(ctx, lattices, it, a_prev, now - t1)) + "\n")
+            jl.flush()
         if log and (now - t_log > 20.0 or it == n_rm - 1):
             log(f"RM iteration {it + 1}/{n_rm}, {now - t1:.1f} s")
             t_log = now
     t_rm = time.perf_counter() - t1
+    if jl:
+        jl.close()
     per_link = _updates_per_class_link(ctx, st0)
     out = []
     for i, (L, E_low, dE) in enumerate(lattices):
@@ -731,8 +763,12 @@ def main():
     ap.add_argument("--combine", action="store_true")
     ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped",
                     help="order of the class passes in the sweeps of the Algorithm 1 runs")
+    ap.add_argument("--jsonl", default=None,
+                    help="append one JSON line per Robbins-Monro iteration of the Algorithm 1 runs to this file "
+                         "(a_k, max |da_k|, acceptance rates, link updates/s, recompute drift, health)")
     args = ap.parse_args()
-    global SWEEP_ORDER
+    global SWEEP_ORDER, JSONL
+    JSONL = args.jsonl
     SWEEP_ORDER = llr.SWEEP_INTERLEAVED if args.order == "interleaved" else llr.SWEEP_GROUPED
     os.makedirs(args.out, exist_ok=True)
 
