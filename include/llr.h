@@ -240,7 +240,12 @@ llr_status llr_get_ln_rho(llr_ctx *ctx, int lattice_id, double *centres, double 
  * device needed): precision, number of lattices, and per lattice L,
  * n_intervals and dE (host arrays of at least 8), E_low (host, the sum of
  * n_intervals, lattice after lattice; may be NULL) and the parameters (may be
- * NULL).  Same errors as llr_restore's file checks. */
+ * NULL).  It checks the whole file as llr_restore does before touching the
+ * device: magic, version, CRC, header values that llr_add_lattice and
+ * llr_set_params would accept, and a section table that covers the rest of
+ * the file with every section present once at the size the header implies
+ * (a^(n) either empty or of n_rm + 1 entries per interval).  LLR_EINVAL
+ * otherwise. */
 llr_status llr_checkpoint(llr_ctx *ctx, const char *path);
 llr_status llr_restore(llr_ctx *ctx, const char *path);
 llr_status llr_checkpoint_info(const char *path, int *precision, int *n_lattices, int *L, int *n_intervals,

@@ -734,6 +734,27 @@ static llr_status observables_impl(llr_ctx* c, int n_meas, int gap, long long sw
 }
 
 // ================================================================= C ABI
+// Checks shared by llr_set_params, llr_add_lattice and the checkpoint reader.
+static llr_status check_params(const llr_params& p) {
+    if (p.n_a < 1 || p.n_th < 0 || p.n_rm < 0 || p.recompute_every < 1 || p.approach_cap < 0 || !(p.eps >= 0) ||
+        !(p.overlap >= 0))
+        return fail(LLR_EINVAL, "invalid parameters");
+    return LLR_OK;
+}
+
+static llr_status check_lattice(int L, int n_intervals, const double* E_low, double dE) {
+    if (L < 2 || L > 32 || (L & 1)) return fail(LLR_EINVAL, "L must be even and in [2, 32]");
+    if (n_intervals < 1 || n_intervals > 4096) return fail(LLR_EINVAL, "n_intervals must be in [1, 4096]");
+    if (!(dE > 0)) return fail(LLR_EINVAL, "dE must be > 0");
+    const double six_v = 6.0 * (double)L * L * L * L;
+    for (int k = 0; k < n_intervals; ++k) {
+        if (!std::isfinite(E_low[k])) return fail(LLR_EINVAL, "non-finite interval edge");
+        if (k && !(E_low[k] > E_low[k - 1])) return fail(LLR_EINVAL, "interval edges must ascend");
+        if (E_low[k] < -six_v || E_low[k] + dE > six_v) return fail(LLR_EINVAL, "interval outside [-6V, 6V]");
+    }
+    return LLR_OK;
+}
+
 extern "C" {
 
 const char* llr_last_error(void) { return g_err.c_str(); }
@@ -779,9 +800,7 @@ void llr_destroy(llr_ctx* c) {
 
 llr_status llr_set_params(llr_ctx* c, const llr_params* p) {
     if (!c || !p) return fail(LLR_EINVAL, "null argument");
-    if (p->n_a < 1 || p->n_th < 0 || p->n_rm < 0 || p->recompute_every < 1 || p->approach_cap < 0 ||
-        !(p->eps >= 0) || !(p->overlap >= 0))
-        return fail(LLR_EINVAL, "invalid parameters");
+    if (check_params(*p) != LLR_OK) return LLR_EINVAL;
     const bool width_changed = c->laid_out && (p->replica_exchange != c->prm.replica_exchange || p->overlap != c->prm.overlap);
     c->prm = *p;
     drop_graphs(c);
@@ -792,16 +811,8 @@ llr_status llr_set_params(llr_ctx* c, const llr_params* p) {
 llr_status llr_add_lattice(llr_ctx* c, int L, int n_intervals, const double* E_low, double dE, int* lattice_id) {
     if (!c || !E_low) return fail(LLR_EINVAL, "null argument");
     if (c->laid_out) return fail(LLR_ESTATE, "lattices must be added before llr_state_bytes/llr_bind_state");
-    if (L < 2 || L > 32 || (L & 1)) return fail(LLR_EINVAL, "L must be even and in [2, 32]");
-    if (n_intervals < 1 || n_intervals > 4096) return fail(LLR_EINVAL, "n_intervals must be in [1, 4096]");
-    if (!(dE > 0)) return fail(LLR_EINVAL, "dE must be > 0");
+    if (check_lattice(L, n_intervals, E_low, dE) != LLR_OK) return LLR_EINVAL;
     if ((int)c->lats.size() >= kMaxLat) return fail(LLR_EINVAL, "at most 8 lattices");
-    const double six_v = 6.0 * (double)L * L * L * L;
-    for (int k = 0; k < n_intervals; ++k) {
-        if (!std::isfinite(E_low[k])) return fail(LLR_EINVAL, "non-finite interval edge");
-        if (k && !(E_low[k] > E_low[k - 1])) return fail(LLR_EINVAL, "interval edges must ascend");
-        if (E_low[k] < -six_v || E_low[k] + dE > six_v) return fail(LLR_EINVAL, "interval outside [-6V, 6V]");
-    }
     HostLat h;
     h.L = L;
     h.n = n_intervals;
@@ -1811,17 +1822,20 @@ namespace {
 const char kCkMagic[8] = {'L', 'L', 'R', 'C', 'K', 'P', 'T', '1'};
 constexpr uint32_t kCkVersion = 2;
 
-uint32_t crc32_update(uint32_t crc, const unsigned char* p, size_t n) {
-    static uint32_t table[256];
-    static bool init = false;
-    if (!init) {
+struct Crc32Table {
+    uint32_t t[256];
+    Crc32Table() {
         for (uint32_t i = 0; i < 256; ++i) {
             uint32_t c = i;
             for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
-            table[i] = c;
+            t[i] = c;
         }
-        init = true;
     }
+};
+
+uint32_t crc32_update(uint32_t crc, const unsigned char* p, size_t n) {
+    static const Crc32Table tab;   // initialised once, thread-safe
+    const uint32_t* table = tab.t;
     crc = ~crc;
     for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xffu] ^ (crc >> 8);
     return ~crc;
@@ -1861,12 +1875,31 @@ struct CkLattice {
     std::vector<double> E_low;
 };
 
+struct CkSection {
+    uint32_t tag;
+    uint64_t bytes;
+    const unsigned char* at;   // into the loaded file
+};
+
 struct CkHeader {
     uint32_t precision = 0;
     std::vector<CkLattice> lats;
     llr_params prm{};
-    size_t body = 0;   // offset of the first section
+    std::vector<CkSection> secs;
+    const CkSection* find(uint32_t tag) const {
+        for (const auto& x : secs)
+            if (x.tag == tag) return &x;
+        return nullptr;
+    }
 };
+
+// Bytes of the driver's host section: 11 i32 flags and tiles, then per
+// lattice the approach sweep count (i64), its done flag (i32) and a0[n].
+size_t ck_host_bytes(const std::vector<CkLattice>& lats) {
+    size_t b = 4 * 11;
+    for (const auto& l : lats) b += 8 + 4 + 8 * (size_t)l.n;
+    return b;
+}
 
 // Reads the whole file, checks magic, version, size and CRC, and parses the
 // header.  Host only.
@@ -1899,12 +1932,46 @@ llr_status ck_load(const char* path, std::vector<unsigned char>& data, CkHeader&
             return fail(LLR_EINVAL, "bad lattice in checkpoint");
         l.E_low.resize(l.n);
         if (!r.get(l.E_low.data(), 8 * (size_t)l.n)) return fail(LLR_EINVAL, "checkpoint header truncated");
+        if (check_lattice(l.L, l.n, l.E_low.data(), l.dE) != LLR_OK) return fail(LLR_EINVAL, "bad lattice in checkpoint");
     }
     llr_params& p = h.prm;
     if (!r.val(&p.n_th) || !r.val(&p.n_a) || !r.val(&p.n_rm) || !r.val(&p.seed) || !r.val(&p.replica_exchange) ||
         !r.val(&p.overlap) || !r.val(&p.recompute_every) || !r.val(&p.eps) || !r.val(&p.approach_cap))
         return fail(LLR_EINVAL, "checkpoint header truncated");
-    h.body = r.off;
+    if (check_params(p) != LLR_OK) return fail(LLR_EINVAL, "bad parameters in checkpoint");
+    // the section table: every section inside the file, each tag known and
+    // present once, with the size the header implies
+    h.secs.clear();
+    while (r.off < r.n) {
+        CkSection x{};
+        if (!r.val(&x.tag) || !r.val(&x.bytes) || x.bytes > r.n - r.off) return fail(LLR_EINVAL, "checkpoint section truncated");
+        if (x.tag < kTagState || x.tag > kTagRates) return fail(LLR_EINVAL, "unknown checkpoint section");
+        if (h.find(x.tag)) return fail(LLR_EINVAL, "duplicate checkpoint section");
+        x.at = r.p + r.off;
+        r.off += (size_t)x.bytes;
+        h.secs.push_back(x);
+    }
+    size_t n = 0, sites = 0;
+    for (const auto& l : h.lats) {
+        n += (size_t)l.n;
+        sites += (size_t)l.n * 8 * ((size_t)l.L * l.L * l.L * l.L);   // both planes of every colour
+    }
+    const size_t state_bytes = sites * (h.precision == LLR_FP32 ? 4 : 8);
+    struct Want { uint32_t tag; size_t bytes; };
+    const Want want[] = {
+        {kTagState, state_bytes}, {kTagCur, 8 * n}, {kTagE, 8 * n}, {kTagItv, 4 * n}, {kTagB, 64 * n},
+        {kTagEta, 64 * n}, {kTagSprev, 32 * n}, {kTagHbProp, 8 * n}, {kTagHbAcc, 8 * n}, {kTagA, 8 * n},
+        {kTagConf, 4 * n}, {kTagSumE, 8 * n}, {kTagConvIter, 4 * n}, {kTagConvSweeps, 8 * n},
+        {kTagLinkFix, 8 * n}, {kTagLinkArc, 8 * n}, {kTagLatDone, 4 * (size_t)kMaxLat}, {kTagMuLnRho, 8 * n},
+        {kTagMuB, 8 * (size_t)kMaxLat}, {kTagScalars, 28}, {kTagFuAcc, 8 * n}, {kTagRates, 32},
+        {kTagHost, ck_host_bytes(h.lats)}};
+    for (const auto& x : want) {
+        const CkSection* q = h.find(x.tag);
+        if (!q || q->bytes != x.bytes) return fail(LLR_EINVAL, "checkpoint section missing or of the wrong size");
+    }
+    const CkSection* ah = h.find(kTagAHist);   // empty, or a^(0..n_rm) of every interval
+    if (!ah || (ah->bytes != 0 && ah->bytes != 8 * ((size_t)p.n_rm + 1) * n))
+        return fail(LLR_EINVAL, "checkpoint history of the wrong size");
     return LLR_OK;
 }
 
@@ -1978,7 +2045,7 @@ llr_status llr_checkpoint(llr_ctx* c, const char* path) {
     CKD(kTagSumE, s.sumE, 8 * (size_t)n)
     CKD(kTagConvIter, s.conv_iter, 4 * (size_t)n)
     CKD(kTagConvSweeps, s.conv_sweeps, 8 * (size_t)n)
-    CKD(kTagAHist, s.a_hist, s.a_hist ? 8 * (size_t)(p.n_rm + 1) * n : 0)
+    CKD(kTagAHist, s.a_hist, s.a_hist ? 8 * ((size_t)p.n_rm + 1) * n : 0)
     CKD(kTagLinkFix, s.link_fix, 8 * (size_t)n)
     CKD(kTagLinkArc, s.link_arc, 8 * (size_t)n)
     CKD(kTagLatDone, s.lat_done, 4 * (size_t)kMaxLat)
@@ -2044,42 +2111,13 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     }
     const int n = c->lt.n_chains;
     const llr_params& p = h.prm;
-    // parse and size-check every section before anything is written to the device
-    struct Sec { uint32_t tag; uint64_t bytes; const unsigned char* at; };
-    std::vector<Sec> secs;
-    CkReader r{data.data(), data.size() - 4};
-    r.off = h.body;
-    while (r.off < r.n) {
-        Sec x{};
-        if (!r.val(&x.tag) || !r.val(&x.bytes) || x.bytes > r.n - r.off) return fail(LLR_EINVAL, "checkpoint section truncated");
-        x.at = r.p + r.off;
-        r.off += (size_t)x.bytes;
-        secs.push_back(x);
-    }
-    auto find = [&](uint32_t tag) -> const Sec* {
-        for (const auto& x : secs)
-            if (x.tag == tag) return &x;
-        return nullptr;
-    };
-    struct Want { uint32_t tag; size_t bytes; };
-    const Want want[] = {
-        {kTagState, c->state_bytes}, {kTagCur, 8 * (size_t)n}, {kTagE, 8 * (size_t)n}, {kTagItv, 4 * (size_t)n},
-        {kTagB, 64 * (size_t)n}, {kTagEta, 64 * (size_t)n}, {kTagSprev, 32 * (size_t)n}, {kTagHbProp, 8 * (size_t)n},
-        {kTagHbAcc, 8 * (size_t)n}, {kTagA, 8 * (size_t)n}, {kTagConf, 4 * (size_t)n}, {kTagSumE, 8 * (size_t)n},
-        {kTagConvIter, 4 * (size_t)n}, {kTagConvSweeps, 8 * (size_t)n}, {kTagLinkFix, 8 * (size_t)n},
-        {kTagLinkArc, 8 * (size_t)n}, {kTagLatDone, 4 * (size_t)kMaxLat}, {kTagMuLnRho, 8 * (size_t)n},
-        {kTagMuB, 8 * (size_t)kMaxLat}, {kTagScalars, 28}, {kTagFuAcc, 8 * (size_t)n}, {kTagRates, 32}};
-    for (const auto& x : want) {
-        const Sec* q = find(x.tag);
-        if (!q || q->bytes != x.bytes) return fail(LLR_EINVAL, "checkpoint section missing or of the wrong size");
-    }
-    const Sec* ah = find(kTagAHist);
-    if (!ah || (ah->bytes != 0 && ah->bytes != 8 * (size_t)(p.n_rm + 1) * n))
-        return fail(LLR_EINVAL, "checkpoint history of the wrong size");
-    const Sec* hs = find(kTagHost);
-    size_t host_bytes = 4 * 11;
-    for (const auto& l : h.lats) host_bytes += 8 + 4 + 8 * (size_t)l.n;
-    if (!hs || hs->bytes != host_bytes) return fail(LLR_EINVAL, "checkpoint driver state of the wrong size");
+    // the reader has size-checked every section against the header, and the
+    // header equals the context's lattice set, so every section fits the
+    // context's buffers; nothing is written to the device before this point
+    auto find = [&](uint32_t tag) { return h.find(tag); };
+    if (find(kTagState)->bytes != c->state_bytes) return fail(LLR_EINVAL, "checkpoint state of the wrong size");
+    const CkSection* ah = find(kTagAHist);
+    const CkSection* hs = find(kTagHost);
     CkReader hr{hs->at, (size_t)hs->bytes};
     int rm_done, rm_open, ap_open, have_e, inter, per_link, muca, tuned, hbl, orl, serp;
     hr.val(&rm_done); hr.val(&rm_open); hr.val(&ap_open); hr.val(&have_e); hr.val(&inter); hr.val(&per_link);
@@ -2093,7 +2131,7 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     if ((st = upload_intervals(c)) != LLR_OK) return st;
     const DevState& s = c->ds;
     auto up = [&](uint32_t tag, void* d) -> llr_status {
-        const Sec* q = find(tag);
+        const CkSection* q = find(tag);
         if (q->bytes) HIPCHK(hipMemcpy(d, q->at, (size_t)q->bytes, hipMemcpyHostToDevice));
         return LLR_OK;
     };
@@ -2111,10 +2149,10 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
         c->ds.a_hist = nullptr;
     }
     if (ah->bytes) {
-        if ((st = dalloc(c, &c->ds.a_hist, (size_t)(p.n_rm + 1) * n)) != LLR_OK) return st;
+        if ((st = dalloc(c, &c->ds.a_hist, ((size_t)p.n_rm + 1) * n)) != LLR_OK) return st;
         HIPCHK(hipMemcpy(c->ds.a_hist, ah->at, (size_t)ah->bytes, hipMemcpyHostToDevice));
     }
-    const Sec* sc = find(kTagScalars);
+    const CkSection* sc = find(kTagScalars);
     HIPCHK(hipMemcpy(s.sweep_ctr, sc->at, 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(s.approach_ctr, sc->at + 4, 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(s.rm_iter, sc->at + 8, 4, hipMemcpyHostToDevice));

@@ -1,6 +1,9 @@
 """Checkpoint files on the host (no device): a file written to the documented
 layout is read back by llr_checkpoint_info; a truncated, corrupted, foreign or
-missing file is rejected with LLR_EINVAL before any device work."""
+missing file, a header value that llr_add_lattice or llr_set_params would
+refuse, and a section table that does not fit the header (a section missing,
+repeated, unknown or of the wrong size) are rejected with LLR_EINVAL before
+any device work."""
 import ctypes as C
 import os
 import struct
@@ -30,6 +33,36 @@ def _file(lats, prm, sections=(), version=2, precision=1, magic=b"LLRCKPT1"):
 LATS = [(4, [600.0, 640.0, 680.0], 40.0), (6, [3000.0, 3100.0], 100.0)]
 PRM = (5, 7, 3, 1509083910, 1, 1.0, 10, 1e-4, 200)
 
+# section tags in the order the library writes them
+(T_STATE, T_CUR, T_E, T_ITV, T_B, T_ETA, T_SPREV, T_HBPROP, T_HBACC, T_A, T_CONF, T_SUME, T_CONVITER,
+ T_CONVSWEEPS, T_AHIST, T_LINKFIX, T_LINKARC, T_LATDONE, T_MULNRHO, T_MUB, T_SCALARS, T_HOST, T_FUACC,
+ T_RATES) = range(1, 25)
+
+
+def section_sizes(lats, n_rm, precision=1, history=True):
+    """(tag, bytes) of every section of a checkpoint, as the header implies
+    them: n chains (one per interval), both planes of every colour of every
+    chain, 8 lattice slots."""
+    n = sum(len(E) for _, E, _ in lats)
+    state = sum(len(E) * 8 * L ** 4 for L, E, _ in lats) * (4 if precision == 1 else 8)
+    host = 4 * 11 + sum(8 + 4 + 8 * len(E) for _, E, _ in lats)
+    sizes = [(T_STATE, state), (T_CUR, 8 * n), (T_E, 8 * n), (T_ITV, 4 * n), (T_B, 64 * n), (T_ETA, 64 * n),
+             (T_SPREV, 32 * n), (T_HBPROP, 8 * n), (T_HBACC, 8 * n), (T_A, 8 * n), (T_CONF, 4 * n),
+             (T_SUME, 8 * n), (T_CONVITER, 4 * n), (T_CONVSWEEPS, 8 * n),
+             (T_AHIST, 8 * (n_rm + 1) * n if history else 0), (T_LINKFIX, 8 * n), (T_LINKARC, 8 * n),
+             (T_LATDONE, 32), (T_MULNRHO, 8 * n), (T_MUB, 64), (T_SCALARS, 28), (T_HOST, host),
+             (T_FUACC, 8 * n), (T_RATES, 32)]
+    return sizes
+
+
+def full_sections(lats, n_rm, precision=1, history=True):
+    """Every section of a checkpoint, zero-filled."""
+    return [(t, b"\0" * k) for t, k in section_sizes(lats, n_rm, precision, history)]
+
+
+def _replace(secs, tag, data):
+    return [(t, data if t == tag else d) for t, d in secs]
+
 
 def _info(path):
     return llr.checkpoint_info(str(path))
@@ -43,7 +76,7 @@ def _status(path):
 
 def test_documented_layout_reads_back(tmp_path):
     p = tmp_path / "ok.ckpt"
-    p.write_bytes(_file(LATS, PRM, sections=[(1, b"\0" * 16)]))
+    p.write_bytes(_file(LATS, PRM, sections=full_sections(LATS, PRM[2])))
     info = _info(p)
     assert info["precision"] == llr.FP32
     assert [(L, list(E), dE) for L, E, dE in info["lattices"]] == [(L, list(E), dE) for L, E, dE in LATS]
@@ -52,8 +85,17 @@ def test_documented_layout_reads_back(tmp_path):
             prm.eps, prm.approach_cap) == PRM
 
 
+def test_file_without_history_reads_back(tmp_path):
+    p = tmp_path / "ok.ckpt"
+    p.write_bytes(_file(LATS, PRM, sections=full_sections(LATS, PRM[2], history=False)))
+    assert _status(p) == 0
+
+
 def test_truncated_corrupted_foreign_and_missing_files_are_rejected(tmp_path):
-    good = _file(LATS, PRM, sections=[(1, b"\1" * 64)])
+    secs = full_sections(LATS, PRM[2])
+    good = _file(LATS, PRM, sections=secs)
+    bad_prm = list(PRM)
+    bad_prm[1] = 0                                     # n_a = 0
     cases = {
         "truncated_tail": good[:-7],
         "truncated_header": good[:20],
@@ -65,6 +107,18 @@ def test_truncated_corrupted_foreign_and_missing_files_are_rejected(tmp_path):
         "precision": _file(LATS, PRM, precision=7),
         "odd_L": _file([(5, [1.0], 1.0)], PRM),
         "no_lattices": _file([], PRM),
+        "descending_edges": _file([(4, [640.0, 600.0], 40.0)], PRM,
+                                  sections=full_sections([(4, [640.0, 600.0], 40.0)], PRM[2])),
+        "edge_outside_6V": _file([(4, [1500.0], 40.0)], PRM, sections=full_sections([(4, [1500.0], 40.0)], PRM[2])),
+        "bad_params": _file(LATS, tuple(bad_prm), sections=secs),
+        "no_sections": _file(LATS, PRM),
+        "section_missing": _file(LATS, PRM, sections=[x for x in secs if x[0] != T_RATES]),
+        "section_short": _file(LATS, PRM, sections=_replace(secs, T_E, b"\0" * 8)),
+        "state_of_fp64_size": _file(LATS, PRM, sections=full_sections(LATS, PRM[2], precision=0)),
+        "history_of_wrong_size": _file(LATS, PRM, sections=_replace(secs, T_AHIST, b"\0" * 8)),
+        "section_repeated": _file(LATS, PRM, sections=secs + [(T_RATES, b"\0" * 32)]),
+        "section_unknown": _file(LATS, PRM, sections=secs + [(99, b"")]),
+        "section_past_end": good[:-4 - 32] + struct.pack("<I", zlib.crc32(good[:-4 - 32]) & 0xFFFFFFFF),
     }
     for name, data in cases.items():
         p = tmp_path / f"{name}.ckpt"
