@@ -15,7 +15,10 @@ beta_c and the C_V peak on beta in [1.008, 1.012].  One link update = one
 heatbath or one overrelaxation of one link.
 
 --order: grouped (default; heatbath of every colour, then overrelaxation of
-every colour, 16 launches per sweep: 2 x 4V updates per sweep) or interleaved
+every colour, 16 launches per sweep: 2 x 4V updates per sweep), staggered
+(the grouped passes on the first 64 chains and, overrelaxation first, on the
+other 64, the two halves on two streams so that heatbath and overrelaxation
+passes overlap; 2 x 4V updates per sweep) or interleaved
 (heatbath then overrelaxation per colour, one fused launch per colour).  In
 the interleaved order the overrelaxation reflects the heatbath draw just made
 on the same staples, which is again a von Mises draw: an accepted heatbath
@@ -90,7 +93,8 @@ def cpu_baseline(order, target_s=10.0):
     dE = 0.0005 * V6
     ref = _a_ref()
     cen = np.array(ref["E_low"]) + 0.5 * dE
-    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
+    o_order = {"interleaved": oracle.SWEEP_INTERLEAVED, "staggered": oracle.SWEEP_STAGGERED}.get(
+        order, oracle.SWEEP_GROUPED)
 
     def run(nch, budget):
         th = np.ascontiguousarray(np.concatenate(
@@ -202,8 +206,10 @@ def link_updates(order, V, n_chains, n_sweeps, hb_acceptance):
     sweep, 2 x 4V.  Interleaved order: 8 fused passes of V/2 class links, one
     update per link of an accepted heatbath class (the overrelaxation that
     follows on the same staples is a relabelled draw) and two (rejected
-    proposal, overrelaxation) per link of a rejected one."""
-    if order == "grouped":
+    proposal, overrelaxation) per link of a rejected one.  Staggered order:
+    the grouped order's passes on every chain (half of them overrelaxation
+    first), 2 x 4V."""
+    if order in ("grouped", "staggered"):
         return 2.0 * 4 * V * n_chains * n_sweeps
     return (2.0 - hb_acceptance) * 8 * (V // 2) * n_chains * n_sweeps
 
@@ -220,7 +226,7 @@ def main():
     ap.add_argument("--m2-iters-mlp", type=int, default=20,
                     help="Robbins-Monro iterations of the convergence run from the network's warm start")
     ap.add_argument("--no-m2", action="store_true", help="skip the plain-vs-network convergence runs")
-    ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped")
+    ap.add_argument("--order", choices=["grouped", "interleaved", "staggered"], default="grouped")
     ap.add_argument("--n-th", type=int, default=500)
     ap.add_argument("--n-a", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -262,7 +268,8 @@ def main():
     ctx.add_lattice(L, E_low, dE)
     ctx.bind_state()
     ctx.set_a(0, np.full(N_INT, 1.0))
-    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if args.order == "interleaved" else llr.SWEEP_GROUPED)
+    ctx.set_sweep_order({"grouped": llr.SWEEP_GROUPED, "interleaved": llr.SWEEP_INTERLEAVED,
+                         "staggered": llr.SWEEP_STAGGERED}[args.order])
     t_setup = time.perf_counter()
     ctx.hot_start()
     ctx.approach_begin()
@@ -322,11 +329,18 @@ def main():
     # update); the fused pass of the interleaved order writes two (the
     # overrelaxed candidate and the overrelaxed old angle): 10 angles per
     # class link for its two updates
+    # In the staggered order the heatbath and overrelaxation passes of the two
+    # chain halves overlap on two streams and one event pair spans a sweep's
+    # 16 launches: the figure is then the class passes' average, 9 angles per
+    # class link for either kind of pass, over the sweep's class-pass time.
     per_link = 10 if args.order == "interleaved" else 9
     bytes_per_hb_launch = N_INT * (V // 2) * per_link * esz
     hb_avg_s = tm["hb_ms"] / max(tm["hb_n"], 1) / 1e3
     achieved = bytes_per_hb_launch / hb_avg_s / 1e9 if hb_avg_s > 0 else 0.0
     or_avg_s = tm["or_ms"] / max(tm["or_n"], 1) / 1e3
+    kernel = {"grouped": "heatbath class pass (k_hb)",
+              "interleaved": "heatbath + overrelaxation class pass (k_hb, fused)",
+              "staggered": "class passes of both chain halves on two streams (k_hb, k_or), per pass"}[args.order]
     out = {
         "metric": "link updates/s at 20^4x128 intervals; RM sweeps to |da_k|<1e-4, plain vs MLP",
         "value": value,
@@ -349,10 +363,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": HB_TRAFFIC.get((args.precision, tiles[0], args.order)),
-                     "kernel": "heatbath class pass (k_hb)" if args.order == "grouped"
-                               else "heatbath + overrelaxation class pass (k_hb, fused)",
+                     "kernel": kernel,
                      "bytes_per_launch": bytes_per_hb_launch, "avg_launch_us": hb_avg_s * 1e6,
-                     "overrelaxation_avg_launch_us": or_avg_s * 1e6},
+                     "overrelaxation_avg_launch_us": or_avg_s * 1e6 if args.order != "staggered" else None},
         "acceptance": {"heatbath_class": hb_acc_timed, "overrelaxation": rates["or_acceptance"],
                        "replica_exchange": float(ra / max(rp, 1))},
         "approach_sweeps": int(ap_sweeps[0]),

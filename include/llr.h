@@ -185,12 +185,23 @@ llr_status llr_set_restriction(llr_ctx *ctx, int per_link);
  *     draw: an accepted class gets one update per link, not two, and a
  *     rejected class one overrelaxation of its old angles (with the rejected
  *     proposal, (2 - acceptance) updates per class link).
+ *   LLR_SWEEP_STAGGERED: the first ceil(n/2) chains of each lattice sweep in
+ *     the grouped order; the others take the overrelaxation of colours 0..7
+ *     first, then the heatbath of colours 0..7 (the grouped order's passes
+ *     continued half a sweep later; overrelaxation leaves E unchanged, so
+ *     every chain's sweep still ends with the E of its heatbath half).  The
+ *     two chain sets share no link and run on two streams (the context's and
+ *     a second one of default priority, joined at the end of each sweep), so
+ *     the heatbath passes, bound by vector instructions, overlap the
+ *     overrelaxation passes, bound by memory.  2 x 4V link updates per
+ *     sweep, as grouped.
  * Applies to the restricted, free and multicanonical sweeps of llr_run /
  * llr_rm_step / llr_sweeps / llr_observables / the multicanonical run (whose
- * accepted classes then get heatbath-only dynamics, for the same reason);
- * sweeps with the per-link restriction and approach-mode sweeps stay grouped.
- * LLR_EINVAL for a null context or another value. */
-enum { LLR_SWEEP_GROUPED = 0, LLR_SWEEP_INTERLEAVED = 1 };
+ * accepted classes then get heatbath-only dynamics in the interleaved order,
+ * for the same reason); sweeps with the per-link restriction and
+ * approach-mode sweeps stay grouped.  LLR_EINVAL for a null context or
+ * another value; LLR_EDEVICE if the second stream cannot be created. */
+enum { LLR_SWEEP_GROUPED = 0, LLR_SWEEP_INTERLEAVED = 1, LLR_SWEEP_STAGGERED = 2 };
 llr_status llr_set_sweep_order(llr_ctx *ctx, int order);
 /* Final a_k, first RM iteration n with |a^(n+1)-a^(n)| < eps (-1 if never)
  * and sweeps up to it (approach + (n+1)(N_TH+N_A)); host arrays, n_intervals. */
@@ -349,7 +360,9 @@ llr_status llr_health(llr_ctx *ctx, uint32_t *flags, double *drift, int clear);
  * summed duration (ms) and count of heatbath-pass, overrelaxation-pass and
  * energy launches since enabling.  The 8 heatbath (and the 8
  * overrelaxation) launches of a sweep share one event pair, so the average
- * per launch includes the short gaps between consecutive launches. */
+ * per launch includes the short gaps between consecutive launches.  In the
+ * staggered order one event pair spans a sweep's class passes on both
+ * streams and counts as 16 heatbath launches (the two kinds overlap there). */
 llr_status llr_set_timing(llr_ctx *ctx, int on);
 llr_status llr_get_timing(llr_ctx *ctx, double *hb_ms, long long *hb_n, double *or_ms,
                           long long *or_n, double *en_ms, long long *en_n);

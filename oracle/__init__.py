@@ -30,8 +30,10 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 KIND_SWEEP, KIND_INIT, KIND_APPROACH, KIND_REPLICA, KIND_MLP, KIND_BOOT, KIND_MUCA = 0, 1, 2, 3, 4, 5, 6
 MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
 # order of the class passes in a sweep: heatbath of every colour then
-# overrelaxation of every colour, or heatbath and overrelaxation per colour
-SWEEP_GROUPED, SWEEP_INTERLEAVED = 0, 1
+# overrelaxation of every colour, or heatbath and overrelaxation per colour,
+# or the grouped order on the first ceil(n/2) chains of a lattice and
+# overrelaxation of every colour then heatbath of every colour on the others
+SWEEP_GROUPED, SWEEP_INTERLEAVED, SWEEP_STAGGERED = 0, 1, 2
 N_PARAMS = 4417
 
 
@@ -110,7 +112,7 @@ def _declare(L):
                                 _p(d), _p(d)]
     L.or_class_pass.restype = i
     L.or_sweeps.argtypes = [i, i, i, _p(d), _p(d), _p(d), _p(d), _p(i), _p(d), i, u32, i, i, i,
-                            u64, i, i, _p(i)]
+                            u64, i, i, _p(i), _p(i)]
     L.or_replica_step.argtypes = [i, _p(i), _p(i), _p(d), _p(d), _p(d), _p(d), u64, i, u32, _p(C.c_longlong)]
     L.or_replica_run.argtypes = [i, i, i, _p(d), _p(d), _p(d), _p(d), _p(d), _p(i), _p(i), i, u32, u64, i, i,
                                  _p(d), _p(C.c_longlong)]
@@ -243,20 +245,29 @@ def class_pass(d, L, theta, hb, colour, mode, a, lo, hi, E, seed, kind=KIND_SWEE
 
 
 def sweeps(d, L, theta, a, lo, hi, interval, E, n_sweeps, sweep0, mode=MODE_RESTRICTED,
-           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False, order=SWEEP_GROUPED, use=None):
+           kind=KIND_SWEEP, do_or=True, seed=0, lattice_id=0, f32=False, order=SWEEP_GROUPED, use=None,
+           chain=None, n_lattice_chains=None):
     """n_sweeps sweeps of every chain of theta (n_chains, d, V), in place.  Returns bits.
-    order (with do_or): SWEEP_GROUPED or SWEEP_INTERLEAVED.  use: a library
-    from build_variant instead of the oracle's own."""
+    order (with do_or): SWEEP_GROUPED, SWEEP_INTERLEAVED or SWEEP_STAGGERED;
+    for the staggered order, chain (default 0, 1, ...) is each chain's index
+    in its lattice and n_lattice_chains (default n_chains) the lattice's
+    chain count: chains from ceil(n/2) on take their overrelaxation first.
+    use: a library from build_variant instead of the oracle's own."""
     assert theta.dtype == np.float64 and theta.flags.c_contiguous
     nch = theta.shape[0]
     a, lo, hi = _f64(a), _f64(lo), _f64(hi)
     itv = np.ascontiguousarray(interval, dtype=np.int32)
     Earr = np.ascontiguousarray(E, dtype=np.float64).copy()
     bits = np.zeros((n_sweeps, nch), dtype=np.int32)
+    per_chain = None
+    if do_or and order == SWEEP_STAGGERED:
+        ids = np.arange(nch) if chain is None else np.asarray(chain)
+        n_lat = nch if n_lattice_chains is None else int(n_lattice_chains)
+        per_chain = np.ascontiguousarray(np.where(ids < (n_lat + 1) // 2, 1, 3), dtype=np.int32)
     (use or lib()).or_sweeps(d, L, nch, _ptr(theta, C.c_double), _ptr(a, C.c_double), _ptr(lo, C.c_double),
                     _ptr(hi, C.c_double), _ptr(itv, C.c_int), _ptr(Earr, C.c_double), n_sweeps,
                     sweep0, mode, kind, (2 if order == SWEEP_INTERLEAVED else 1) if do_or else 0, seed,
-                    lattice_id, int(f32), _ptr(bits, C.c_int))
+                    lattice_id, int(f32), _ptr(bits, C.c_int), _ptr(per_chain, C.c_int))
     return Earr, bits
 
 
@@ -266,7 +277,8 @@ def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=
     """Algorithm 1 on every interval of one lattice.  Returns a dict of results.
     per_link: the restricted sweeps impose the restriction per link (Sec. 2.4)
     instead of rejecting whole colour classes.  order: of the class passes in
-    a sweep (SWEEP_GROUPED or SWEEP_INTERLEAVED; per-link sweeps stay grouped)."""
+    a sweep (SWEEP_GROUPED, SWEEP_INTERLEAVED or SWEEP_STAGGERED; per-link
+    sweeps stay grouped)."""
     E_low = _f64(E_low)
     n = E_low.size
     V = L ** d
@@ -274,7 +286,7 @@ def llr_run(d, L, E_low, dE, a0, n_th, n_a, n_rm, seed, w=None, recompute_every=
         w = 2.0 * dE if replica_exchange else dE
     p = RunParams(d, L, n, n_th, n_a, n_rm, recompute_every, approach_cap, int(replica_exchange),
                   int(f32), lattice_id, int(theta is None), seed, dE, w, eps, int(per_link),
-                  int(order == SWEEP_INTERLEAVED))
+                  {SWEEP_INTERLEAVED: 1, SWEEP_STAGGERED: 2}.get(order, 0))
     a = _f64(a0).copy() if np.ndim(a0) else np.full(n, float(a0))
     th = np.empty((n, d, V)) if theta is None else _f64(theta).copy()
     a_hist = np.zeros((n_rm + 1, n))

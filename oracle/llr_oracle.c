@@ -714,7 +714,11 @@ void or_link_pass(int d, int L, double *theta, int colour, double a, double lo, 
 
 /* One restricted sweep of one chain.  do_or 0: heatbath over all 2d colours;
  * 1: then overrelaxation over all 2d colours (grouped order); 2: heatbath and
- * overrelaxation of colour 0, then of colour 1, ... (interleaved order).
+ * overrelaxation of colour 0, then of colour 1, ... (interleaved order);
+ * 3: overrelaxation over all 2d colours, then heatbath over all 2d colours
+ * (the staggered order's second chain set: the grouped order's passes
+ * continued half a sweep later, so that the sweep ends right after the
+ * heatbath half, as the grouped sweep's overrelaxation leaves E unchanged).
  * Algorithm 1 asks only for one sweep of the whole system.  In the
  * interleaved order the overrelaxation of colour c reflects, on unchanged
  * staples, the heatbath draw just made: -2 phi - (X - phi) = -X - phi, again
@@ -727,7 +731,10 @@ static int sweep_chain(const geo_t *g, double *th, double *scr, int mode, double
 {
     int bits = 0;
     int nc = 2 * g->d;
-    if (do_or == 2 && (mode == 1 || mode == 4)) do_or = 1;   /* approach and per-link sweeps stay grouped */
+    if ((do_or == 2 || do_or == 3) && (mode == 1 || mode == 4)) do_or = 1;   /* approach and per-link sweeps stay grouped */
+    if (do_or == 3)
+        for (int c = 0; c < nc; ++c)
+            if (class_pass(g, th, scr, 0, c, mode, a, lo, hi, E, pc, NULL, NULL)) bits |= 1 << (nc + c);
     for (int c = 0; c < nc; ++c) {
         if (class_pass(g, th, scr, 1, c, mode, a, lo, hi, E, pc, NULL, NULL)) bits |= 1 << c;
         if (do_or == 2 && class_pass(g, th, scr, 0, c, mode, a, lo, hi, E, pc, NULL, NULL))
@@ -742,10 +749,12 @@ static int sweep_chain(const geo_t *g, double *th, double *scr, int mode, double
 /* Exported: n_sweeps sweeps on n_chains independent chains (chain ch uses
  * coupling a[ch], interval [lo[ch], hi[ch]], counter word 3 = interval[ch]).
  * mode as in class_pass.  Sweep indices run sweep0, sweep0+1, ...  E is
- * in/out per chain.  bits (optional) is n_sweeps x n_chains. */
+ * in/out per chain.  bits (optional) is n_sweeps x n_chains.  do_or_ch
+ * (optional): per chain, the do_or of sweep_chain, in place of do_or. */
 void or_sweeps(int d, int L, int n_chains, double *theta, const double *a, const double *lo,
                const double *hi, const int *interval, double *E, int n_sweeps, uint32_t sweep0,
-               int mode, int kind, int do_or, uint64_t seed, int lattice_id, int f32, int *bits)
+               int mode, int kind, int do_or, uint64_t seed, int lattice_id, int f32, int *bits,
+               const int *do_or_ch)
 {
     geo_t g;
     if (geo_init(&g, d, L)) return;
@@ -756,7 +765,8 @@ void or_sweeps(int d, int L, int n_chains, double *theta, const double *a, const
         for (int t = 0; t < n_sweeps; ++t) {
             pass_ctx_t pc = {{(uint32_t)seed, (uint32_t)(seed >> 32)}, kind, lattice_id,
                              sweep0 + (uint32_t)t, (uint32_t)interval[ch], f32};
-            int b = sweep_chain(&g, theta + ch * nl, scr, mode, a[ch], lo[ch], hi[ch], &E[ch], &pc, do_or);
+            int b = sweep_chain(&g, theta + ch * nl, scr, mode, a[ch], lo[ch], hi[ch], &E[ch], &pc,
+                                do_or_ch ? do_or_ch[ch] : do_or);
             if (bits) bits[(long)t * n_chains + ch] = b;
         }
         free(scr);
@@ -782,7 +792,8 @@ typedef struct {
     double w;             /* restriction width */
     double eps;           /* convergence threshold on |a^(n+1) - a^(n)| */
     int link;             /* 1: restriction imposed per link (Sec. 2.4), 0: class-wise rejection */
-    int interleave;       /* 1: sweeps in the interleaved order (sweep_chain) */
+    int interleave;       /* sweep order: 0 grouped, 1 interleaved, 2 staggered (chains from
+                             ceil(n/2) on take their overrelaxation passes first) */
 } or_run_params;
 
 typedef struct {
@@ -997,8 +1008,11 @@ int or_llr_run(const or_run_params *p, const double *E_low, or_run_out *o)
                 double *scr = (double *)malloc(sizeof(double) * (g.V / 2 + 1));
                 int k = itv[c];
                 pass_ctx_t pc = {{key[0], key[1]}, KIND_SWEEP, p->lattice_id, t_glob, (uint32_t)k, p->f32};
+                int dor = 1;
+                if (!p->link && p->interleave == 1) dor = 2;
+                if (!p->link && p->interleave == 2 && c >= (n + 1) / 2) dor = 3;
                 int bits = sweep_chain(&g, o->theta + c * nl, scr, p->link ? 4 : 0, o->a[k], lo[k], hi[k],
-                                       &o->E[c], &pc, (p->interleave && !p->link) ? 2 : 1);
+                                       &o->E[c], &pc, dor);
                 if (o->bits) o->bits[(bitrow + (long long)it * nsw + j) * n + c] = (uint16_t)bits;
                 if (recompute) o->E[c] = energy(&g, o->theta + c * nl);
                 free(scr);

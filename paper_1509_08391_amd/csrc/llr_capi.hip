@@ -86,6 +86,7 @@ struct llr_ctx {
     bool muca_ready = false;   // multicanonical weights built (llr_muca_begin)
     bool per_link = false;     // Algorithm 1's restricted sweeps impose the restriction per link
     bool interleave = false;   // sweep = (heatbath, overrelaxation) per colour, fused in one launch
+    bool stagger = false;      // staggered order: the second half of each lattice's chains overrelaxes first
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = LLR_FP64;
@@ -107,6 +108,8 @@ struct llr_ctx {
     bool use_graphs = true;
     hipGraphExec_t sweep_graph[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t cap_stream = nullptr;  // default priority
+    hipStream_t side = nullptr;        // staggered order: the second chain set's stream (default priority)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bool rm_open = false;
     // timing
     bool timing = false;
@@ -214,6 +217,28 @@ static void set_tiles(LatTable& lt, int hb_lpt, int or_lpt) {
     lt.or_blocks = or0;
 }
 
+// The staggered order's two chain sets: per lattice, the first ceil(n/2)
+// chains (A) and the others (B), as tables of their own (a lattice may hold
+// no chain in B; its block ranges are then empty).
+static void half_tables(const LatTable& lt, LatTable& a, LatTable& b) {
+    a = lt;
+    b = lt;
+    a.n_chains = b.n_chains = 0;
+    for (int i = 0; i < lt.n; ++i) {
+        const LatDev& d = lt.l[i];
+        const int na = (d.n_chains + 1) / 2;
+        a.l[i].n_chains = na;
+        b.l[i].n_chains = d.n_chains - na;
+        b.l[i].chain0 = d.chain0 + na;
+        b.l[i].base = d.base + (long long)na * 16ll * (long long)d.V2;
+        b.l[i].lbase = d.lbase + (long long)na * (long long)d.V2;
+        a.n_chains += na;
+        b.n_chains += d.n_chains - na;
+    }
+    set_tiles(a, lt.hb_lpt, lt.or_lpt);
+    set_tiles(b, lt.hb_lpt, lt.or_lpt);
+}
+
 static llr_status layout(llr_ctx* c) {
     if (c->laid_out) return LLR_OK;
     if (c->lats.empty()) return fail(LLR_ESTATE, "no lattice added");
@@ -235,6 +260,8 @@ static llr_status layout(llr_ctx* c) {
         d.mhL = magic((uint32_t)(h.L / 2));
         d.n_chains = h.n;
         d.chain0 = chain0;
+        d.n_itv = h.n;
+        d.itv0 = chain0;
         // site kernels: the even and the odd sites of a chain in blocks of their own
         d.ebpc = 2 * (int)((V / 2 + kBlock - 1) / kBlock);
         d.eblock0 = eblock0;
@@ -389,13 +416,35 @@ static void note_sweep(llr_ctx* c, bool fused) {
 // one restricted sweep of all chains, then recompute / replica exchange / measurement
 template <typename T>
 static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bool measure) {
-    const bool fused = c->interleave && (mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_MUCA);
+    const bool plain = mode == LLR_MODE_RESTRICTED || mode == LLR_MODE_FREE || mode == LLR_MODE_MUCA;
+    const bool fused = c->interleave && plain;
     note_sweep(c, fused);
     if (fused) {
         TimeScope ts(c, 0, 8);
         for (int col = 0; col < 8; ++col)
             launch_hb_or_pass<T>(c->lt, (T*)c->state, c->ds, col, mode, (uint32_t)c->prm.seed,
                                  (uint32_t)(c->prm.seed >> 32), c->stream);
+    } else if (c->stagger && plain && c->side) {
+        // chains of A on the context's stream: heatbath of colours 0..7, then
+        // overrelaxation of 0..7; chains of B on the side stream:
+        // overrelaxation first.  The two sets share no link, so the streams
+        // join only at the end of the sweep.
+        LatTable ha, hb;
+        half_tables(c->lt, ha, hb);
+        const uint32_t k0 = (uint32_t)c->prm.seed, k1 = (uint32_t)(c->prm.seed >> 32);
+        TimeScope ts(c, 0, 16);
+        hipEventRecord(c->fork_ev, c->stream);
+        hipStreamWaitEvent(c->side, c->fork_ev, 0);
+        for (int j = 0; j < 16; ++j) {
+            const int col = j & 7;
+            if (j < 8) launch_hb_pass<T>(ha, (T*)c->state, c->ds, col, mode, kSweep, k0, k1, c->stream);
+            else launch_or_pass<T>(ha, (T*)c->state, c->ds, col, 0, c->stream);
+            if (hb.n_chains == 0) continue;
+            if (j < 8) launch_or_pass<T>(hb, (T*)c->state, c->ds, col, 0, c->side);
+            else launch_hb_pass<T>(hb, (T*)c->state, c->ds, col, mode, kSweep, k0, k1, c->side);
+        }
+        hipEventRecord(c->join_ev, c->side);
+        hipStreamWaitEvent(c->stream, c->join_ev, 0);
     } else {
         {
             TimeScope ts(c, 0, 8);
@@ -791,6 +840,12 @@ void llr_destroy(llr_ctx* c) {
     hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->side) {
+        hipStreamSynchronize(c->side);
+        hipStreamDestroy(c->side);
+    }
+    if (c->fork_ev) hipEventDestroy(c->fork_ev);
+    if (c->join_ev) hipEventDestroy(c->join_ev);
     for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
     for (void* p : c->allocs) hipFree(p);
@@ -999,12 +1054,31 @@ llr_status llr_set_order(llr_ctx* c, int serpentine) {
     return LLR_OK;
 }
 
+}  // extern "C"
+
+// The staggered order's second stream and its fork / join events.
+static llr_status ensure_side_stream(llr_ctx* c) {
+    if (c->side) return LLR_OK;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    return LLR_OK;
+}
+
+extern "C" {
+
 llr_status llr_set_sweep_order(llr_ctx* c, int order) {
     if (!c) return fail(LLR_EINVAL, "null context");
-    if (order != LLR_SWEEP_GROUPED && order != LLR_SWEEP_INTERLEAVED)
-        return fail(LLR_EINVAL, "order must be LLR_SWEEP_GROUPED or LLR_SWEEP_INTERLEAVED");
-    if (c->interleave != (order == LLR_SWEEP_INTERLEAVED)) {
+    if (order != LLR_SWEEP_GROUPED && order != LLR_SWEEP_INTERLEAVED && order != LLR_SWEEP_STAGGERED)
+        return fail(LLR_EINVAL, "order must be LLR_SWEEP_GROUPED, LLR_SWEEP_INTERLEAVED or LLR_SWEEP_STAGGERED");
+    if (order == LLR_SWEEP_STAGGERED) {
+        const llr_status st = ensure_side_stream(c);
+        if (st != LLR_OK) return st;
+    }
+    if (c->interleave != (order == LLR_SWEEP_INTERLEAVED) || c->stagger != (order == LLR_SWEEP_STAGGERED)) {
         c->interleave = order == LLR_SWEEP_INTERLEAVED;
+        c->stagger = order == LLR_SWEEP_STAGGERED;
         drop_graphs(c);   // the captured sweeps hold the pass sequence
     }
     return LLR_OK;
@@ -2067,7 +2141,7 @@ llr_status llr_checkpoint(llr_ctx* c, const char* path) {
     // host state of the driver
     CkWriter hw;
     hw.val(c->rm_done); hw.val((int)c->rm_open); hw.val((int)c->ap_open); hw.val((int)c->have_energy);
-    hw.val((int)c->interleave); hw.val((int)c->per_link); hw.val((int)c->muca_ready); hw.val((int)c->tuned);
+    hw.val(c->interleave ? (int)LLR_SWEEP_INTERLEAVED : c->stagger ? (int)LLR_SWEEP_STAGGERED : (int)LLR_SWEEP_GROUPED); hw.val((int)c->per_link); hw.val((int)c->muca_ready); hw.val((int)c->tuned);
     hw.val(c->lt.hb_lpt); hw.val(c->lt.or_lpt); hw.val(c->lt.serpentine);
     for (size_t i = 0; i < c->lats.size(); ++i) {
         hw.val(i < c->approach_sweeps.size() ? c->approach_sweeps[i] : 0ll);
@@ -2123,7 +2197,8 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     hr.val(&rm_done); hr.val(&rm_open); hr.val(&ap_open); hr.val(&have_e); hr.val(&inter); hr.val(&per_link);
     hr.val(&muca); hr.val(&tuned); hr.val(&hbl); hr.val(&orl); hr.val(&serp);
     auto ok_lpt = [](int v) { return v == 1 || v == 2 || v == 4; };
-    if (!ok_lpt(hbl) || !ok_lpt(orl) || rm_done < 0 || rm_done > p.n_rm)
+    if (!ok_lpt(hbl) || !ok_lpt(orl) || rm_done < 0 || rm_done > p.n_rm || inter < LLR_SWEEP_GROUPED ||
+        inter > LLR_SWEEP_STAGGERED)
         return fail(LLR_EINVAL, "bad driver state in checkpoint");
     // parameters (and with them the restriction widths), then the device state
     if ((st = llr_set_params(c, &p)) != LLR_OK) return st;
@@ -2169,7 +2244,9 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     c->rm_open = rm_open != 0;
     c->ap_open = ap_open != 0;
     c->have_energy = have_e != 0;
-    c->interleave = inter != 0;
+    c->interleave = inter == LLR_SWEEP_INTERLEAVED;
+    c->stagger = inter == LLR_SWEEP_STAGGERED;
+    if (c->stagger && (st = ensure_side_stream(c)) != LLR_OK) return st;
     c->per_link = per_link != 0;
     c->muca_ready = muca != 0;
     set_tiles(c->lt, hbl, orl);

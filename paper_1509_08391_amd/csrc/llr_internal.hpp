@@ -15,8 +15,9 @@ struct LatDev {
     int L, hL;             // L, L/2
     uint32_t V2;           // V/2
     uint32_t mL, mhL;      // ceil(2^32 / L), ceil(2^32 / (L/2))
-    int n_chains;          // = number of intervals
-    int chain0;            // first global chain index (= first global interval index)
+    int n_chains;          // chains of the table (all of the lattice's, or one half in the staggered order)
+    int chain0;            // first global chain index of the table
+    int n_itv, itv0;       // the lattice's intervals: count and first global index (= its first chain)
     int hb_bpc, hb_block0; // heatbath pass: blocks per chain (npt x ceil(L / LPT)), first block
     int or_bpc, or_block0; // overrelaxation pass: the same
     uint32_t P;            // positions in the (x0h, x1, x2) slab: hL L^2 = V/(2L); h = pos + P x3

@@ -396,11 +396,11 @@ __device__ __forceinline__ T or_angle(T t, T C, T S) {
 // interval the first and last pieces continue, i.e. W = e^{a_0 E + c_1} and
 // e^{a_{n-1} E + c_2} with the constants fixed by continuity.
 __device__ __forceinline__ double muca_lnw(const LatDev& L, const DevState& s, double E) {
-    const double* c = s.cen + L.chain0;
+    const double* c = s.cen + L.itv0;
     const double lo = c[0] - 0.5 * L.ds;
     int k = (int)floor((E - lo) / L.ds);
-    k = k < 0 ? 0 : (k > L.n_chains - 1 ? L.n_chains - 1 : k);
-    return -s.mu_lnrho[L.chain0 + k] + s.a[L.chain0 + k] * (E - c[k]);
+    k = k < 0 ? 0 : (k > L.n_itv - 1 ? L.n_itv - 1 : k);
+    return -s.mu_lnrho[L.itv0 + k] + s.a[L.itv0 + k] * (E - c[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,7 +448,7 @@ __device__ __forceinline__ void hb_block(const LatTable& lt, T* __restrict__ th,
     const double acoup = mode == kModeApproach ? s.b[8 * g + colour] : (mode == kModeMuca ? s.mu_b[li] : s.a[gi]);
     const uint32_t sweep = kind == kApproach ? *s.approach_ctr : *s.sweep_ctr;
     const uint32_t c1base = ctr1_word(0, (uint32_t)colour, (uint32_t)kind, (uint32_t)L.lat_id);
-    const uint32_t c3 = (uint32_t)(gi - L.chain0);
+    const uint32_t c3 = (uint32_t)(gi - L.itv0);
     const int own = (int)((curw >> (8 * colour)) & 1ull);
     T* pcur = chain + (size_t)(own * 8 + colour) * L.V2;
     const T* pown = pcur;
@@ -832,7 +832,7 @@ __global__ __launch_bounds__(kBlock) void k_link_walk(LatTable lt, T* __restrict
         const double fxw = L.fx * (double)(1 << kWalkBits), fxwinv = L.fxinv / (double)(1 << kWalkBits);
         const long long lo_fx = fx_bound(ceil((lo - E0) * fxw)), hi_fx = fx_bound(floor((hi - E0) * fxw));
         const uint32_t sweep = *s.sweep_ctr;
-        const uint32_t c3 = (uint32_t)(gi - L.chain0);
+        const uint32_t c3 = (uint32_t)(gi - L.itv0);
         long long Ssum = 0;
         unsigned fixes = 0, arcs = 0;
         for (int k = 0; k < ntiles; ++k) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libllr.so")
 OK, WARN_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
 MODE_RESTRICTED, MODE_APPROACH, MODE_FREE, MODE_MUCA, MODE_LINK = 0, 1, 2, 3, 4
-SWEEP_GROUPED, SWEEP_INTERLEAVED = 0, 1
+SWEEP_GROUPED, SWEEP_INTERLEAVED, SWEEP_STAGGERED = 0, 1, 2
 N_PARAMS = 4417
 
 _lib = None
@@ -322,8 +322,10 @@ class Context:
 
     def set_sweep_order(self, order):
         """SWEEP_GROUPED (heatbath of every colour, then overrelaxation of
-        every colour) or SWEEP_INTERLEAVED (heatbath then overrelaxation per
-        colour, fused in one launch)."""
+        every colour), SWEEP_INTERLEAVED (heatbath then overrelaxation per
+        colour, fused in one launch) or SWEEP_STAGGERED (grouped on the first
+        half of each lattice's chains, overrelaxation first on the others,
+        the two halves on two streams)."""
         _check(lib().llr_set_sweep_order(self.h, int(order)))
 
     def set_tiles(self, hb_lpt, or_lpt):

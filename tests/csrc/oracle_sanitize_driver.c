@@ -1,6 +1,6 @@
 /* Test driver for the oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
  * (tests/test_oracle_sanitizers.py): exercises the sweeps in every mode and
- * order, the per-link pass, replica exchange, the reconstruction and the
+ * order (the staggered one through per-chain orders), the per-link pass, replica exchange, the reconstruction and the
  * network, on small lattices; any out-of-bounds access, leak or undefined
  * operation aborts with a non-zero status. */
 #include <stdint.h>
@@ -11,7 +11,7 @@ void or_hot_start(int d, int L, int n_chains, uint64_t seed, int lattice_id, int
 double or_energy(int d, int L, const double *theta);
 void or_sweeps(int d, int L, int n_chains, double *theta, const double *a, const double *lo, const double *hi,
                const int *interval, double *E, int n_sweeps, uint32_t sweep0, int mode, int kind, int do_or,
-               uint64_t seed, int lattice_id, int f32, int *bits);
+               uint64_t seed, int lattice_id, int f32, int *bits, const int *do_or_ch);
 int or_class_pass(int d, int L, double *theta, int hb, int colour, int mode, double a, double lo, double hi,
                   double *E, uint64_t seed, int kind, int lattice_id, uint32_t sweep, uint32_t interval, int f32,
                   double *margin, double *dE_out);
@@ -52,13 +52,16 @@ int main(void)
         }
         /* free, approach-like and restricted sweeps in both orders, and heatbath-only */
         for (int order = 1; order <= 2; ++order)
-            or_sweeps(d, L, n, th, a, lo, hi, itv, E, 3, 5, 2, 0, order, seed, 0, 0, bits);
-        or_sweeps(d, L, n, th, a, lo, hi, itv, E, 2, 9, 2, 0, 0, seed, 0, 1, bits);
+            or_sweeps(d, L, n, th, a, lo, hi, itv, E, 3, 5, 2, 0, order, seed, 0, 0, bits, NULL);
+        or_sweeps(d, L, n, th, a, lo, hi, itv, E, 2, 9, 2, 0, 0, seed, 0, 1, bits, NULL);
+        /* the staggered order: per-chain pass orders */
+        const int stag[4] = {1, 1, 3, 3};
+        or_sweeps(d, L, n, th, a, lo, hi, itv, E, 2, 7, 2, 0, 1, seed, 0, 0, bits, stag);
         for (int c = 0; c < n; ++c) {
             lo[c] = E[c] - 2.0;
             hi[c] = E[c] + 2.0;
         }
-        or_sweeps(d, L, n, th, a, lo, hi, itv, E, 3, 11, 0, 0, 1, seed, 0, 0, bits);
+        or_sweeps(d, L, n, th, a, lo, hi, itv, E, 3, 11, 0, 0, 1, seed, 0, 0, bits, stag);
         double *mg = malloc(sizeof(double) * (size_t)(V / 2 + 1));
         int *how = malloc(sizeof(int) * (size_t)(V / 2 + 1));
         double dE = 0.0;

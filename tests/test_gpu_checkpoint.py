@@ -52,7 +52,7 @@ def _snapshot(ctx):
     return out
 
 
-@pytest.mark.parametrize("prec,order", [("FP64", 0), ("FP32", 0), ("FP32", 1)])
+@pytest.mark.parametrize("prec,order", [("FP64", 0), ("FP32", 0), ("FP32", 1), ("FP64", 2), ("FP32", 2)])
 def test_restore_continues_bit_for_bit(llr, prec, order, tmp_path):
     p = getattr(llr, prec)
     path = str(tmp_path / "run.ckpt")

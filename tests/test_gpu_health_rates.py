@@ -46,7 +46,7 @@ def _ctx(llr, prec, order, L=4, n=6, replica=False, K=5):
     return ctx
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2])
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
 def test_link_updates_follow_the_acceptance_counters(llr, prec, order):
     L, n = 4, 6

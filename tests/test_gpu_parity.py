@@ -31,6 +31,14 @@ def llr():
     return m
 
 
+def _orders(llr, order):
+    """(library, oracle) constants of a sweep order named grouped,
+    interleaved or staggered."""
+    i = {"grouped": 0, "interleaved": 1, "staggered": 2}[order]
+    return ((llr.SWEEP_GROUPED, llr.SWEEP_INTERLEAVED, llr.SWEEP_STAGGERED)[i],
+            (oracle.SWEEP_GROUPED, oracle.SWEEP_INTERLEAVED, oracle.SWEEP_STAGGERED)[i])
+
+
 def _ctx(llr, prec, lattices, a=1.0, **params):
     """a: one value for every interval, or a list with one entry (scalar or
     per-interval array) per lattice."""
@@ -160,13 +168,19 @@ def test_one_sweep_fp64_batched_chains_and_lattices(llr):
         col += n
 
 
-def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWEEP_GROUPED, interval=0):
+def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWEEP_GROUPED, interval=0,
+                                 or_first=False):
     """One FP32-state sweep of one chain by the oracle, pass by pass (in the
-    given order of the class passes), returning the set of links whose
-    sampler test had a margin below 1e-5."""
+    given order of the class passes; or_first: the staggered order's second
+    chain set, overrelaxation of every colour before the heatbath passes),
+    returning the set of links whose sampler test had a margin below 1e-5."""
     V = L ** d
     flagged = np.zeros((d, V), dtype=bool)
     par = np.array([sum((s // L ** m) % L for m in range(d)) % 2 for s in range(V)])
+    if or_first:
+        for col in range(2 * d):
+            oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep,
+                              interval=interval, f32=True)
     for col in range(2 * d):
         acc, E, dE, mg = oracle.class_pass(d, L, th, 1, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED,
                                            sweep=sweep, interval=interval, f32=True, want_margin=True)
@@ -176,7 +190,7 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWE
         if order == oracle.SWEEP_INTERLEAVED:
             oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep,
                               interval=interval, f32=True)
-    if order == oracle.SWEEP_GROUPED:
+    if order != oracle.SWEEP_INTERLEAVED and not or_first:
         for col in range(2 * d):
             oracle.class_pass(d, L, th, 0, col, oracle.MODE_RESTRICTED, a, lo, hi, E, SEED, sweep=sweep,
                               interval=interval, f32=True)
@@ -184,7 +198,7 @@ def _oracle_sweep_f32_with_flags(d, L, th, a, lo, hi, E, sweep, order=oracle.SWE
 
 
 def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GROUPED, a=1.0, interval=0,
-                   lattice_id=0):
+                   lattice_id=0, chain=0, n_lattice_chains=1):
     """Per-link linear response of one oracle sweep (FP64): the factor by which
     a 1e-9 random perturbation of the input state is amplified at each output
     link, RMS over n_dir independent perturbations (one random direction alone
@@ -194,12 +208,12 @@ def _amplification(d, L, th_k, lo, hi, E0, sweep, n_dir=4, order=oracle.SWEEP_GR
     rng = np.random.default_rng(0)
     base = np.ascontiguousarray(th_k[None].copy())
     oracle.sweeps(d, L, base, [a], [lo], [hi], [interval], [E0], 1, sweep, seed=SEED, order=order,
-                  lattice_id=lattice_id)
+                  lattice_id=lattice_id, chain=[chain], n_lattice_chains=n_lattice_chains)
     acc = np.zeros(th_k.shape)
     for _ in range(n_dir):
         t = np.ascontiguousarray(th_k[None] + rng.normal(0.0, 1e-9, th_k.shape)[None])
         oracle.sweeps(d, L, t, [a], [lo], [hi], [interval], [E0], 1, sweep, seed=SEED, order=order,
-                      lattice_id=lattice_id)
+                      lattice_id=lattice_id, chain=[chain], n_lattice_chains=n_lattice_chains)
         acc += (circ_dist(base[0], t[0]) / 1e-9) ** 2
     return np.sqrt(acc / n_dir)
 
@@ -274,12 +288,15 @@ def _states_in_intervals(L, E_low, dE, seed):
     return np.ascontiguousarray(np.array(out))
 
 
+@pytest.mark.parametrize("order", ["grouped", "staggered"])
 @pytest.mark.parametrize("replica", [False, True])
-def test_driver_short_run_fp64(llr, replica):
+def test_driver_short_run_fp64(llr, replica, order):
     """Every driver step inside the divergence horizon: N_TH = 1, N_A = 1,
     N_RM = 3 (6 sweeps) from states inside their intervals, recompute every 2
     sweeps, replica exchange after every sweep: accept bits and chain <->
-    interval labels identical to the oracle, every a_k^(n) within 1e-7."""
+    interval labels identical to the oracle, every a_k^(n) within 1e-7.  In
+    the grouped order and the staggered one (chains 4-7 overrelax first, on
+    the second stream; replica exchange pairs chains of both halves)."""
     import torch
     L, d = 4, 4
     V6 = 6 * L ** 4
@@ -287,8 +304,10 @@ def test_driver_short_run_fp64(llr, replica):
     E_low = 0.55 * V6 + dE * np.arange(8)
     th = _states_in_intervals(L, E_low, dE, seed=5)
     a0 = np.linspace(0.95, 1.1, 8)
+    lo_order, o_order = _orders(llr, order)
     ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a0], n_th=1, n_a=1, n_rm=3, recompute_every=2,
                replica_exchange=replica)
+    ctx.set_sweep_order(lo_order)
     ctx.enable_bits_log(100)
     ctx.import_state(0, torch.from_numpy(th))
     ctx.run()
@@ -298,7 +317,7 @@ def test_driver_short_run_fp64(llr, replica):
     bits = ctx.get_bits_log()
     _, _, re_prop, re_acc = ctx.stats()
     r = oracle.llr_run(d, L, E_low, dE, a0, n_th=1, n_a=1, n_rm=3, seed=SEED, recompute_every=2,
-                       replica_exchange=replica, theta=th, record_bits=True, approach_cap=0)
+                       replica_exchange=replica, theta=th, record_bits=True, approach_cap=0, order=o_order)
     assert r["approach_sweeps"] == 0
     assert np.array_equal(bits.astype(np.int64), r["bits"].astype(np.int64))
     assert np.array_equal(conf, r["conf"])
@@ -332,7 +351,7 @@ def test_approach_parity_fp64(llr):
     assert np.all((E >= E_low) & (E <= E_low + dE))
 
 
-@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+@pytest.mark.parametrize("order", ["grouped", "interleaved", "staggered"])
 def test_driver_mixed_lattices_fp64(llr, order):
     """L=4 and L=6 chains batched in one launch, in either sweep order (the
     interleaved one runs the fused launches); each lattice against its own
@@ -349,7 +368,7 @@ def test_driver_mixed_lattices_fp64(llr, order):
     1e-8, every link 1e-5."""
     import torch
     d = 4
-    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
+    lo_order, o_order = _orders(llr, order)
     lats = []
     for L, n in [(4, 4), (6, 3)]:
         V6 = 6 * L ** 4
@@ -357,7 +376,7 @@ def test_driver_mixed_lattices_fp64(llr, order):
         E_low = 0.58 * V6 + dE * np.arange(n)
         lats.append((L, E_low, dE, _states_in_intervals(L, E_low, dE, seed=L)))
     ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=0, n_a=2, n_rm=2, recompute_every=3)
-    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
+    ctx.set_sweep_order(lo_order)
     for i, x in enumerate(lats):
         ctx.import_state(i, torch.from_numpy(x[3]))
     ctx.run()
@@ -655,11 +674,13 @@ def test_tile_choices_give_identical_results(llr, prec):
         assert np.array_equal(o[2], outs[0][2])
 
 
+@pytest.mark.parametrize("order", ["grouped", "staggered"])
 @pytest.mark.parametrize("replica", [False, True])
-def test_graph_replays_match_eager_launches(llr, replica):
+def test_graph_replays_match_eager_launches(llr, replica, order):
     """The captured sweep graphs replayed over several RM iterations (with the
     host's own synchronising reads between iterations) give results
-    bit-identical to direct launches."""
+    bit-identical to direct launches; in the staggered order the graph holds
+    both streams' launches and their fork and join."""
     import torch
     L = 4
     V6 = 6 * L ** 4
@@ -670,6 +691,7 @@ def test_graph_replays_match_eager_launches(llr, replica):
     for graphs in (False, True):
         ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], n_th=3, n_a=7, n_rm=4, recompute_every=4,
                    replica_exchange=replica)
+        ctx.set_sweep_order(_orders(llr, order)[0])
         ctx.set_graphs(graphs)
         ctx.enable_bits_log(200)
         ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
@@ -707,7 +729,7 @@ def _full_size_states(dtype):
 _SAMPLE = np.array([0, 1, 63, 64, 126, 127])
 
 
-@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+@pytest.mark.parametrize("order", ["grouped", "interleaved", "staggered"])
 def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     """The benchmark's shape and launch configuration (128 chains of L = 20 in
     one lattice, 640 000 links each; heatbath tiles of 4 and overrelaxation
@@ -720,15 +742,17 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     differences of the two sides' sin, cos and atan2 by ~1/R in
     phi = arg(C + iS); with P(R < r) ~ r^2 the largest amplification over N
     links grows like sqrt(N), about 1e3 here, and measured maxima are ~2e-12.)
-    In both orders of the class passes; the interleaved one runs the fused
-    launches."""
+    In every order of the class passes; the interleaved one runs the fused
+    launches, the staggered one two streams (chains 64, 126 and 127 of the
+    sample overrelax first)."""
     import torch
     d, L = 4, 20
+    lo_order, o_order = _orders(llr, order)
     th, E, E_low, dE, a = _full_size_states(np.float64)
     ctx = _ctx(llr, llr.FP64, [(L, E_low, dE)], a=[a])
     ctx.set_tiles(4, 2)
     ctx.set_order(True)
-    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
+    ctx.set_sweep_order(lo_order)
     ctx.import_state(0, torch.from_numpy(th))
     bits = ctx.sweeps(1, sweep0=7)
     got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy()
@@ -736,7 +760,7 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
     ctx.close()
     tr = np.ascontiguousarray(th[_SAMPLE])
     Er, br = oracle.sweeps(d, L, tr, a[_SAMPLE], E_low[_SAMPLE], E_low[_SAMPLE] + dE, _SAMPLE, E[_SAMPLE], 1, 7,
-                           seed=SEED, order=oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED)
+                           seed=SEED, order=o_order, chain=_SAMPLE, n_lattice_chains=128)
     n_acc = int(sum(bin(int(b) & 0xff).count("1") for b in br[0]))
     assert 0 < n_acc < 8 * _SAMPLE.size          # both outcomes of the interval test occur
     dist = circ_dist(got, tr)
@@ -749,7 +773,7 @@ def test_full_size_one_sweep_sampled_chains_fp64(llr, order):
         assert abs(Eg[k] - Er[j]) < 1e-9 * abs(Er[j])
 
 
-@pytest.mark.parametrize("order", ["grouped", "interleaved"])
+@pytest.mark.parametrize("order", ["grouped", "interleaved", "staggered"])
 def test_full_size_one_sweep_sampled_chains_fp32(llr, order):
     """One whole FP32 sweep (in either order) at the benchmark's shape and launch
     configuration, link by link on the six sampled chains, against the
@@ -770,12 +794,12 @@ def test_full_size_one_sweep_sampled_chains_fp32(llr, order):
     0.024 in the interleaved order)."""
     import torch
     d, L = 4, 20
-    o_order = oracle.SWEEP_INTERLEAVED if order == "interleaved" else oracle.SWEEP_GROUPED
+    lo_order, o_order = _orders(llr, order)
     th, E, E_low, dE, a = _full_size_states(np.float32)
     ctx = _ctx(llr, llr.FP32, [(L, E_low, dE)], a=[a])
     ctx.set_tiles(4, 2)
     ctx.set_order(True)
-    ctx.set_sweep_order(llr.SWEEP_INTERLEAVED if order == "interleaved" else llr.SWEEP_GROUPED)
+    ctx.set_sweep_order(lo_order)
     ctx.import_state(0, torch.from_numpy(th.astype(np.float32)))
     bits = ctx.sweeps(1, sweep0=7)
     got = ctx.export_state(0)[torch.from_numpy(_SAMPLE).cuda()].cpu().numpy().astype(np.float64)
@@ -785,17 +809,20 @@ def test_full_size_one_sweep_sampled_chains_fp32(llr, order):
     for j, k in enumerate(_SAMPLE):
         tr = th[k].copy()
         lo, hi = E_low[k], E_low[k] + dE
-        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, a[k], lo, hi, E[k], 7, order=o_order, interval=k)
+        or_first = order == "staggered" and k >= 64
+        Er, flagged = _oracle_sweep_f32_with_flags(d, L, tr, a[k], lo, hi, E[k], 7, order=o_order, interval=k,
+                                                   or_first=or_first)
         # the oracle's decisions, replayed from its energies, against the GPU's bits
         tb = th[k].copy()
         Eb, br = oracle.sweeps(d, L, np.ascontiguousarray(tb[None]), [a[k]], [lo], [hi], [k], [E[k]], 1, 7,
-                               seed=SEED, f32=True, order=o_order)
+                               seed=SEED, f32=True, order=o_order, chain=[k], n_lattice_chains=128)
         if int(bits[0, k]) & 0xff != int(br[0, 0]) & 0xff:
             print(f"\nchain {k}: interval decisions differ ({int(bits[0, k]) & 0xff:08b} vs "
                   f"{int(br[0, 0]) & 0xff:08b}), set aside")
             continue
         compared += 1
-        amp = _amplification(d, L, th[k], lo, hi, E[k], 7, a=a[k], interval=k, order=o_order)
+        amp = _amplification(d, L, th[k], lo, hi, E[k], 7, a=a[k], interval=k, order=o_order, chain=k,
+                             n_lattice_chains=128)
         dist = circ_dist(got[j], tr)
         bar = 1e-6 * np.maximum(amp, 10.0)
         frac = np.mean(dist <= bar)

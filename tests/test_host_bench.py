@@ -34,3 +34,10 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_staggered_order_counts_as_grouped():
+    import bench
+    V, n, sw = 20 ** 4, 128, 10
+    assert bench.link_updates("staggered", V, n, sw, 0.3) == bench.link_updates("grouped", V, n, sw, 0.9)
+    assert bench.link_updates("staggered", V, n, sw, 0.3) == 2 * 4 * V * n * sw

@@ -1,10 +1,12 @@
-"""The oracle's two orders of a sweep's class passes (Algorithm 1 asks for
-one sweep of the whole system) are the compositions of single class passes
-they are defined as: grouped = heatbath of colours 0..2d-1, then
-overrelaxation of colours 0..2d-1; interleaved = heatbath then
-overrelaxation of colour 0, then of colour 1, ...  Angles and energies are
-compared bit for bit, for the restricted and the free mode, in 4D and 2D;
-the two orders give different states, so a swapped dispatch fails too."""
+"""The oracle's orders of a sweep's class passes (Algorithm 1 asks for one
+sweep of the whole system) are the compositions of single class passes they
+are defined as: grouped = heatbath of colours 0..2d-1, then overrelaxation
+of colours 0..2d-1; interleaved = heatbath then overrelaxation of colour 0,
+then of colour 1, ...; staggered = grouped on the first ceil(n/2) chains of
+a lattice and overrelaxation of colours 0..2d-1, then heatbath of colours
+0..2d-1, on the others.  Angles and energies are compared bit for bit, for
+the restricted and the free mode, in 4D and 2D; the orders give different
+states, so a swapped dispatch fails too."""
 import numpy as np
 import pytest
 
@@ -15,6 +17,12 @@ SEED = 99
 
 
 def _compose(d, L, th, a, lo, hi, E, sweep, mode, order):
+    if order == "or_first":
+        for col in range(2 * d):
+            _, E, _, _ = oracle.class_pass(d, L, th, 0, col, mode, a, lo, hi, E, SEED, sweep=sweep, interval=0)
+        for col in range(2 * d):
+            _, E, _, _ = oracle.class_pass(d, L, th, 1, col, mode, a, lo, hi, E, SEED, sweep=sweep, interval=0)
+        return E
     for col in range(2 * d):
         _, E, _, _ = oracle.class_pass(d, L, th, 1, col, mode, a, lo, hi, E, SEED, sweep=sweep, interval=0)
         if order == oracle.SWEEP_INTERLEAVED:
@@ -41,6 +49,34 @@ def test_sweep_orders_are_their_pass_compositions(d, L, mode):
         assert E_sw[0] == E_cp, order
         out[order] = t_sw[0]
     assert not np.array_equal(out[oracle.SWEEP_GROUPED], out[oracle.SWEEP_INTERLEAVED])
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_RESTRICTED, oracle.MODE_FREE])
+def test_staggered_order_splits_each_lattice_in_two(mode):
+    """Five chains of one 4D L=4 lattice: chains 0-2 (the first ceil(5/2))
+    sweep in the grouped order, chains 3-4 overrelaxation first; the same
+    with a subset of the chains given by their indices in the lattice."""
+    d, L = 4, 4
+    th0 = random_state(d, L, 5, seed=17, u_target=0.6)
+    E0 = np.array([oracle.energy(d, L, th0[k]) for k in range(5)])
+    lo, hi = E0 - 6.0, E0 + 6.0
+    t_sw = th0.copy()
+    E_sw, bits = oracle.sweeps(d, L, t_sw, [1.1] * 5, lo, hi, [0] * 5, E0, 1, 3, mode=mode, seed=SEED,
+                               order=oracle.SWEEP_STAGGERED)
+    for k in range(5):
+        t_cp = th0[k].copy()
+        E_cp = _compose(d, L, t_cp, 1.1, lo[k], hi[k], E0[k], 3, mode, oracle.SWEEP_GROUPED if k < 3 else "or_first")
+        assert np.array_equal(t_sw[k], t_cp), k
+        assert E_sw[k] == E_cp, k
+        t_g = th0[k].copy()
+        _compose(d, L, t_g, 1.1, lo[k], hi[k], E0[k], 3, mode, oracle.SWEEP_GROUPED)
+        assert np.array_equal(t_sw[k], t_g) == (k < 3), k
+    # chains 1 and 4 alone, as chains of the five-chain lattice
+    t_sub = np.ascontiguousarray(th0[[1, 4]])
+    E_sub, _ = oracle.sweeps(d, L, t_sub, [1.1] * 2, lo[[1, 4]], hi[[1, 4]], [0, 0], E0[[1, 4]], 1, 3, mode=mode,
+                             seed=SEED, order=oracle.SWEEP_STAGGERED, chain=[1, 4], n_lattice_chains=5)
+    assert np.array_equal(t_sub, t_sw[[1, 4]])
+    assert np.array_equal(E_sub, E_sw[[1, 4]])
 
 
 def test_overrelaxation_right_after_the_heatbath_of_its_class_is_a_relabelled_draw():

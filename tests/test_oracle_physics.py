@@ -42,10 +42,11 @@ def _astar(lo, hi, NP):
 @pytest.mark.parametrize("per_link,order,replica", [(False, oracle.SWEEP_GROUPED, False),
                                                     (True, oracle.SWEEP_GROUPED, False),
                                                     (False, oracle.SWEEP_INTERLEAVED, False),
-                                                    (False, oracle.SWEEP_GROUPED, True)])
+                                                    (False, oracle.SWEEP_GROUPED, True),
+                                                    (False, oracle.SWEEP_STAGGERED, True)])
 def test_llr_2d_matches_exact_restricted_root(per_link, order, replica):
     """Both restrictions of Sec. 2.4 (class-wise rejection and the per-link
-    constraint), both orders of the class passes in a sweep, and replica
+    constraint), the orders of the class passes in a sweep, and replica
     exchange between overlapping intervals (Sec. 2.5) drive Algorithm 1 to
     the same exact root."""
     d, L, w = 2, 8, 8.0
@@ -71,7 +72,7 @@ def test_llr_2d_matches_exact_restricted_root(per_link, order, replica):
     assert np.all(np.abs(A.mean(0) - exact) < 4e-3)
 
 
-@pytest.mark.parametrize("order", [oracle.SWEEP_GROUPED, oracle.SWEEP_INTERLEAVED])
+@pytest.mark.parametrize("order", [oracle.SWEEP_GROUPED, oracle.SWEEP_INTERLEAVED, oracle.SWEEP_STAGGERED])
 def test_canonical_2d_plaquette_exact(order):
     d, L = 2, 8
     V = L * L
