@@ -270,9 +270,11 @@ def test_mid_run_switch_recaptures_graphs(llr, switch):
 
 def test_sweep_order_arguments(llr):
     ctx = llr.Context(precision=llr.FP64)
-    with pytest.raises(llr.LLRError):
-        ctx.set_sweep_order(2)
+    for bad in (3, -1):
+        with pytest.raises(llr.LLRError):
+            ctx.set_sweep_order(bad)
     ctx.set_sweep_order(llr.SWEEP_INTERLEAVED)
+    ctx.set_sweep_order(llr.SWEEP_STAGGERED)
     ctx.set_sweep_order(llr.SWEEP_GROUPED)
     ctx.close()
 
