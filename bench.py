@@ -65,7 +65,7 @@ PEAK_HBM_GBS = 8000.0
 # order, profiles/k_hb_or_fused_L20x128_fp32_counters.md for the fused pass of
 # the interleaved order); None once the kernel changes until the counters are
 # taken again.
-HB_TRAFFIC = {("fp32", 4, "grouped"): 374.7e6, ("fp32", 4, "interleaved"): 410.1e6}
+HB_TRAFFIC = {("fp32", 4, "grouped"): 374.8e6, ("fp32", 4, "interleaved"): 410.3e6}
 
 
 WARMSTART = os.path.join(ROOT, "paper_1509_08391_amd", "warmstart")
