@@ -58,8 +58,8 @@
            linkcmp, 8000 sweeps each: mean E per interval against a second
            grouped run with other random numbers.
 
-  --order  grouped (default) or interleaved: the sweep order of the
-           Algorithm 1 runs of every configuration.
+  --order  grouped (default), interleaved or staggered: the sweep order
+           of the Algorithm 1 runs of every configuration.
   --jsonl  a file to which every Robbins-Monro iteration of those runs
            appends one JSON line: a_k and max |a^(n+1) - a^(n)| per lattice,
            acceptance rates, link updates and updates/s so far, the largest
@@ -95,6 +95,8 @@ import numpy as np
 from . import llr
 
 SEED = 1509083910
+_ORDER_NAMES = {llr.SWEEP_GROUPED: "grouped", llr.SWEEP_INTERLEAVED: "interleaved",
+                llr.SWEEP_STAGGERED: "staggered"}
 # order of the class passes in the sweeps of _run (command-line --order)
 SWEEP_ORDER = llr.SWEEP_GROUPED
 # JSON-lines record of every Robbins-Monro iteration of _run (command-line
@@ -122,7 +124,8 @@ def _iteration_record(ctx, lattices, it, a_prev, t):
 
 def _updates_per_class_link(ctx, before):
     """Link updates per class link and class pass since the stats() snapshot
-    `before`: 2 in the grouped order (one heatbath, one overrelaxation); in
+    `before`: 2 in the grouped and staggered orders (one heatbath, one
+    overrelaxation); in
     the interleaved order the overrelaxation right after an accepted heatbath
     of its class is a relabelled draw, so 1 for an accepted class and 2 (the
     rejected proposal and one overrelaxation) for a rejected one."""
@@ -185,7 +188,7 @@ def _run(lattices, prec, n_th, n_a, n_rm, replica, seed=SEED, a0=None, log=None,
     nsw = n_th + n_a
     upd = sum(per_link * 4 * L ** 4 * len(E_low) for (L, E_low, dE) in lattices) * nsw * n_rm
     meta = dict(precision="fp32" if prec == llr.FP32 else "fp64", n_th=n_th, n_a=n_a, n_rm=n_rm, replica=replica,
-                sweep_order="interleaved" if SWEEP_ORDER == llr.SWEEP_INTERLEAVED else "grouped",
+                sweep_order=_ORDER_NAMES[SWEEP_ORDER],
                 seed=seed, seconds_approach=t_ap, seconds_rm=t_rm, updates_per_s=upd / t_rm, tiles=list(tiles),
                 hb_acceptance=float(ha.sum() / max(hp.sum(), 1)),
                 re_acceptance=float(ra / max(rp, 1)) if replica else None)
@@ -679,7 +682,7 @@ def batch_profile(log, n=200):
     log(f"{dt * 1e3:.3f} ms per sweep of 192 chains (L = 12, 16, 20), {upd / dt:.4g} link updates/s, "
         f"tiles {tiles}, approach sweeps {[int(x) for x in ap]}")
     return dict(ms_per_sweep=dt * 1e3, updates_per_s=upd / dt, tiles=list(tiles), approach_sweeps=list(map(int, ap)),
-                sweep_order="interleaved" if SWEEP_ORDER == llr.SWEEP_INTERLEAVED else "grouped")
+                sweep_order=_ORDER_NAMES[SWEEP_ORDER])
 
 
 FSS_PARTS = {0: (8, 10, 12, 14), 1: (16, 18)}
@@ -761,7 +764,7 @@ def main():
     ap.add_argument("--n-rm", type=int, default=None)
     ap.add_argument("--part", type=int, default=0)
     ap.add_argument("--combine", action="store_true")
-    ap.add_argument("--order", choices=["grouped", "interleaved"], default="grouped",
+    ap.add_argument("--order", choices=["grouped", "interleaved", "staggered"], default="grouped",
                     help="order of the class passes in the sweeps of the Algorithm 1 runs")
     ap.add_argument("--jsonl", default=None,
                     help="append one JSON line per Robbins-Monro iteration of the Algorithm 1 runs to this file "
@@ -769,7 +772,7 @@ def main():
     args = ap.parse_args()
     global SWEEP_ORDER, JSONL
     JSONL = args.jsonl
-    SWEEP_ORDER = llr.SWEEP_INTERLEAVED if args.order == "interleaved" else llr.SWEEP_GROUPED
+    SWEEP_ORDER = {v: k for k, v in _ORDER_NAMES.items()}[args.order]
     os.makedirs(args.out, exist_ok=True)
 
     def log(msg):
