@@ -1057,12 +1057,23 @@ llr_status llr_set_order(llr_ctx* c, int serpentine) {
 }  // extern "C"
 
 // The staggered order's second stream and its fork / join events.
+// All three are created or none is kept, so c->side set means all exist.
 static llr_status ensure_side_stream(llr_ctx* c) {
     if (c->side) return LLR_OK;
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    hipStream_t st = nullptr;
+    hipEvent_t fe = nullptr, je = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&fe, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&je, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (fe) hipEventDestroy(fe);
+        if (je) hipEventDestroy(je);
+        return fail(LLR_EDEVICE, std::string("second stream: ") + hipGetErrorString(e));
+    }
+    c->fork_ev = fe;
+    c->join_ev = je;
+    c->side = st;
     return LLR_OK;
 }
 
