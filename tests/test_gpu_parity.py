@@ -394,6 +394,55 @@ def test_driver_mixed_lattices_fp64(llr, order):
         assert q[0] < 1e-11 and q[1] < 1e-8 and q[4] < 1e-5, q
 
 
+def test_staggered_order_with_a_single_chain_lattice(llr):
+    """The staggered order when a lattice's second half is empty: a 1-chain
+    L=4 lattice (its chain in the first half, so it sweeps as in the grouped
+    order) beside a 3-chain L=6 lattice (chains 0-1 grouped, chain 2
+    overrelaxation first), two RM iterations with replica exchange; each
+    lattice against its own oracle run in the same order: accept bits and
+    labels identical, a_k within 1e-7.  Then one lattice of a single chain
+    alone, where the second stream has no work: bit-identical to the grouped
+    order."""
+    import torch
+    d = 4
+    lats = []
+    for L, n in [(4, 1), (6, 3)]:
+        V6 = 6 * L ** 4
+        dE = 0.02 * V6
+        E_low = 0.58 * V6 + dE * np.arange(n)
+        lats.append((L, E_low, dE, _states_in_intervals(L, E_low, dE, seed=30 + L)))
+    ctx = _ctx(llr, llr.FP64, [x[:3] for x in lats], n_th=1, n_a=1, n_rm=2, recompute_every=2,
+               replica_exchange=True)
+    ctx.set_sweep_order(llr.SWEEP_STAGGERED)
+    ctx.enable_bits_log(100)
+    for i, x in enumerate(lats):
+        ctx.import_state(i, torch.from_numpy(x[3]))
+    ctx.run()
+    bits = ctx.get_bits_log()
+    col = 0
+    for i, (L, E_low, dE, th) in enumerate(lats):
+        n = E_low.size
+        r = oracle.llr_run(d, L, E_low, dE, 1.0, n_th=1, n_a=1, n_rm=2, seed=SEED, recompute_every=2,
+                           replica_exchange=True, lattice_id=i, theta=th, approach_cap=0, record_bits=True,
+                           order=oracle.SWEEP_STAGGERED)
+        _, conf = ctx.get_energy(i)
+        assert np.array_equal(bits[:, col:col + n].astype(np.int64), r["bits"].astype(np.int64)), L
+        assert np.array_equal(conf, r["conf"])
+        assert np.max(np.abs(ctx.get_history(i) - r["a_hist"])) < 1e-7
+        col += n
+    ctx.close()
+    out = []
+    L, E_low, dE, th = lats[0]
+    for order in (llr.SWEEP_GROUPED, llr.SWEEP_STAGGERED):
+        c = _ctx(llr, llr.FP64, [(L, E_low, dE)], n_th=1, n_a=1, n_rm=2, recompute_every=2)
+        c.set_sweep_order(order)
+        c.import_state(0, torch.from_numpy(th))
+        c.run()
+        out.append((c.export_state(0).cpu().numpy(), c.get_history(0)))
+        c.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 @pytest.mark.slow
 def test_full_run_l4_statistical_fp64_and_fp32(llr):
     """The L=4 case of Algorithm 1 in full (8 intervals over u in [0.5, 0.7],
