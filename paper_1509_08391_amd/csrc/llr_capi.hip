@@ -424,7 +424,7 @@ static void enqueue_sweep(llr_ctx* c, int mode, bool recompute, bool replica, bo
         for (int col = 0; col < 8; ++col)
             launch_hb_or_pass<T>(c->lt, (T*)c->state, c->ds, col, mode, (uint32_t)c->prm.seed,
                                  (uint32_t)(c->prm.seed >> 32), c->stream);
-    } else if (c->stagger && plain && c->side) {
+    } else if (c->stagger && plain) {   // c->stagger implies the side stream exists
         // chains of A on the context's stream: heatbath of colours 0..7, then
         // overrelaxation of 0..7; chains of B on the side stream:
         // overrelaxation first.  The two sets share no link, so the streams
@@ -2255,9 +2255,9 @@ llr_status llr_restore(llr_ctx* c, const char* path) {
     c->rm_open = rm_open != 0;
     c->ap_open = ap_open != 0;
     c->have_energy = have_e != 0;
+    if (inter == LLR_SWEEP_STAGGERED && (st = ensure_side_stream(c)) != LLR_OK) return st;
     c->interleave = inter == LLR_SWEEP_INTERLEAVED;
     c->stagger = inter == LLR_SWEEP_STAGGERED;
-    if (c->stagger && (st = ensure_side_stream(c)) != LLR_OK) return st;
     c->per_link = per_link != 0;
     c->muca_ready = muca != 0;
     set_tiles(c->lt, hbl, orl);
