@@ -693,11 +693,13 @@ def test_invalid_arguments_are_rejected(llr):
         ctx.close()
 
 
+@pytest.mark.parametrize("order", ["grouped", "staggered"])
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
-def test_tile_choices_give_identical_results(llr, prec):
+def test_tile_choices_give_identical_results(llr, prec, order):
     """The class-pass tiles (links per thread) change only the schedule: two
     sweeps from the same state are bit-identical for every choice, including
-    the autotuner's."""
+    the autotuner's; in the staggered order too, whose half tables are laid
+    out for each choice."""
     import torch
     L, d, n = 6, 4, 3
     dt = np.float32 if prec == "FP32" else np.float64
@@ -709,6 +711,7 @@ def test_tile_choices_give_identical_results(llr, prec):
     outs = []
     for tiles in [(1, 1), (2, 2), (4, 4), (4, 1), None]:
         ctx = _ctx(llr, getattr(llr, prec), [(L, E_low, dE)], a=1.02)
+        ctx.set_sweep_order(_orders(llr, order)[0])
         ctx.import_state(0, torch.from_numpy(th))
         if tiles is None:
             ctx.autotune()
