@@ -29,6 +29,7 @@
            u in [0.55, 0.71] cut into 16, 32, 64 and 128 intervals, eight
            replicas each, FP32; the C_V peak against delta E and the fit
            C_V(dE) = C_V(0) + 6V b_dis dE^2.
+  dE12     the same at L = 12 with 8, 16, 32, 64 and 128 intervals.
 
   obs8     a non-action observable through restricted double brackets
            (Sec. 2.3): after an L=8 run with l8's dE over u in
@@ -397,14 +398,17 @@ def muca12(log, c2, n_sweeps=100000, chunk=2000, n_therm=2000):
                 E_series_chain0=H[::10, 0].tolist())
 
 
-def dE_study_8(log, counts=(16, 32, 64, 128), replicas=8):
-    L = 8
+def dE_study(log, L=8, counts=(16, 32, 64, 128), replicas=8):
+    """Sec. 3.5: the C_V peak against the interval width over u in
+    [0.55, 0.71], cut into `counts` intervals, `replicas` runs each; the fit
+    C_V(dE) = C_V(0) + 6V b_dis dE^2."""
     V6 = 6 * L ** 4
     rows = []
     for nk in counts:
         dE = 0.16 / nk * V6
         E_low = 0.55 * V6 + dE * np.arange(nk)
-        res, meta = _run([(L, E_low, dE)] * replicas, llr.FP32, 200, 500, 50, False, seed=SEED + nk, log=log)
+        seed = SEED + nk if L == 8 else SEED + 1000 * L + nk
+        res, meta = _run([(L, E_low, dE)] * replicas, llr.FP32, 200, 500, 50, False, seed=seed, log=log)
         cen = E_low + 0.5 * dE
         ctx = llr.Context(precision=llr.FP64, device=0)
         pk = np.array([ctx.beta_c(cen, np.array(r["a"]), dE, V6, 0.98, 1.04, h=1e-5, tol=1e-9) for r in res])
@@ -415,14 +419,23 @@ def dE_study_8(log, counts=(16, 32, 64, 128), replicas=8):
                          seconds=meta["seconds_rm"]))
         log(f"{nk} intervals (dE = {dE:.2f}): C_V/(6V) peak {rows[-1]['cv_mean'] / V6:.4e} "
             f"+- {rows[-1]['cv_err'] / V6:.1e}, beta_c {rows[-1]['bc_mean']:.6f} +- {rows[-1]['bc_err']:.6f}")
-    x = np.array([r["dE"] for r in rows])
-    y = np.array([r["cv_mean"] for r in rows])
-    sg = np.array([r["cv_err"] for r in rows])
-    p, e, chi2 = llr.fss_fit(x, y, sg, [0.0, 2.0])
-    b_dis, b_err = p[1] / V6, e[1] / V6 * np.sqrt(max(chi2, 1.0))
-    log(f"fit C_V = C_V(0) + 6V b_dis dE^2: C_V(0)/(6V) = {p[0] / V6:.4e}, b_dis = {b_dis:.2e} +- {b_err:.1e}, "
-        f"chi2_red {chi2:.2f}")
-    return dict(rows=rows, cv0=p[0], cv0_over_6v=p[0] / V6, b_dis=b_dis, b_dis_err=b_err, chi2_red=chi2)
+    def fit(rs, what):
+        x = np.array([r["dE"] for r in rs])
+        y = np.array([r["cv_mean"] for r in rs])
+        sg = np.array([r["cv_err"] for r in rs])
+        p, e, chi2 = llr.fss_fit(x, y, sg, [0.0, 2.0])
+        inflate = np.sqrt(max(chi2, 1.0))
+        b_dis, b_err = p[1] / V6, e[1] / V6 * inflate
+        log(f"fit C_V = C_V(0) + 6V b_dis dE^2 ({what}): C_V(0)/(6V) = {p[0] / V6:.4e} +- "
+            f"{e[0] / V6 * inflate:.1e}, b_dis = {b_dis:.2e} +- {b_err:.1e}, chi2_red {chi2:.2f}")
+        return dict(cv0=p[0], cv0_over_6v=p[0] / V6, cv0_over_6v_err=e[0] / V6 * inflate, b_dis=b_dis,
+                    b_dis_err=b_err, chi2_red=chi2)
+
+    # the quadratic law holds for fine spacings (Sec. 3.5); the coarsest one
+    # is also fitted without, to show where it stops holding
+    out = dict(rows=rows, **fit(rows, "all spacings"))
+    out["without_coarsest"] = fit(rows[1:], f"without dE = {rows[0]['dE']:.1f}")
+    return out
 
 
 def obs8(log, n_meas=400, gap=2):
@@ -756,7 +769,7 @@ def fss_combine(log, parts, c4b_parts, n_boot=2000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["l8", "batched", "warmstart", "l20", "l20reps", "muca12",
-                                            "dE8", "obs8",
+                                            "dE8", "dE12", "obs8",
                                             "l20parts", "linkcmp", "linkprof", "fss", "batchprof", "ordercmp"])
     ap.add_argument("--out", default="experiment_out")
     ap.add_argument("--inputs", default=None, help="directory holding the records a run starts from "
@@ -794,7 +807,9 @@ def main():
     elif args.which == "muca12":
         rec = muca12(log, load("batched"))
     elif args.which == "dE8":
-        rec = dE_study_8(log)
+        rec = dE_study(log, 8)
+    elif args.which == "dE12":
+        rec = dE_study(log, 12, counts=(8, 16, 32, 64, 128))
     elif args.which == "obs8":
         rec = obs8(log)
     elif args.which == "batchprof":
