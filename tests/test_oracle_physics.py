@@ -72,6 +72,27 @@ def test_llr_2d_matches_exact_restricted_root(per_link, order, replica):
     assert np.all(np.abs(A.mean(0) - exact) < 4e-3)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("per_link", [False, True])
+def test_llr_2d_narrow_intervals_match_exact_root(per_link):
+    """Intervals a quarter as wide (w = 2, a few single-link energy changes):
+    both restrictions of Sec. 2.4 still drive Algorithm 1 to the exact root,
+    the per-link constraint now limiting most link updates.  Four seeds of
+    200 iterations: their mean within 3 standard errors of the mean (seed
+    spread) plus 2e-3, and every run within 5e-2 (measured: class-wise runs
+    up to 0.032 from the root, the rejected class passes leaving fewer
+    independent measurements; per-link runs up to 0.024)."""
+    d, L, w = 2, 8, 2.0
+    NP = L * L
+    El = np.array([17.0, 23.0, 29.0])
+    exact = np.array([_astar(e, e + w, NP) for e in El])
+    A = np.array([oracle.llr_run(d, L, El, w, 1.0, n_th=20, n_a=200, n_rm=200, seed=100 + s, per_link=per_link)["a"]
+                  for s in range(4)])
+    err = A.std(0, ddof=1) / np.sqrt(len(A))
+    assert np.all(np.abs(A.mean(0) - exact) < 3 * err + 2e-3), (A.mean(0) - exact, err)
+    assert np.all(np.abs(A - exact) < 5e-2)
+
+
 @pytest.mark.parametrize("order", [oracle.SWEEP_GROUPED, oracle.SWEEP_INTERLEAVED, oracle.SWEEP_STAGGERED])
 def test_canonical_2d_plaquette_exact(order):
     d, L = 2, 8
