@@ -54,8 +54,8 @@
            under --inputs, else a_k = 1.011 ~ beta_c(20) throughout).
   linkprof 60 sweeps per mode of the L = 20 set only, for a kernel trace.
 
-  ordercmp the two orders of a sweep's class passes (grouped, and
-           interleaved with fused launches) on the lattices and a_k of
+  ordercmp the grouped and the interleaved order of a sweep's class
+           passes (the latter with fused launches) on the lattices and a_k of
            linkcmp, 8000 sweeps each: mean E per interval against a second
            grouped run with other random numbers.
 
@@ -630,8 +630,8 @@ def link_compare(log, a20, n_meas8=8000, n_meas20=4000):
 
 
 def order_compare(log, a20, n_meas8=8000, n_meas20=8000):
-    """The two orders of a sweep's class passes (grouped; interleaved, fused
-    launches) at fixed a_k: mean E per interval against a second grouped run
+    """The grouped and the interleaved order of a sweep's class passes (the
+    latter with fused launches) at fixed a_k: mean E per interval against a second grouped run
     with other random numbers, which gives the spread of one ensemble."""
     runs = (("grouped", llr.MODE_RESTRICTED, 1 << 22, llr.SWEEP_GROUPED),
             ("grouped2", llr.MODE_RESTRICTED, 1 << 23, llr.SWEEP_GROUPED),
