@@ -22,3 +22,15 @@ def test_tau_int_of_ar1(rho):
     # the automatic window truncates the tail (bias ~ e^{-W/tau}) and the
     # estimate has relative spread ~ sqrt(2 (2 W + 1) / n)
     assert np.all(np.abs(tau - exact) < 0.06 * exact + 0.02), (tau, exact)
+
+
+def test_experiments_command_line_offers_every_sweep_order_and_study():
+    """The experiments' command line (no device used): every sweep order of
+    the library and both delta E studies are selectable."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-m", "paper_1509_08391_amd.experiments", "--help"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    for word in ("grouped", "interleaved", "staggered", "dE8", "dE12"):
+        assert word in r.stdout, word
